@@ -1,0 +1,299 @@
+"""Plain CPU oracle for the varying-parameter base-pool RNG (double precision).
+
+TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package; the product
+library never does, and it shares no code with it.
+
+The arithmetic lives in ``brng_oracle.c`` (scalar C, FP64, one file); this
+module builds it with gcc when needed and marshals numpy arrays through
+ctypes.  Every function documents the passage of Mahani & Sharabiani (arXiv
+1412.4825) it follows; see the C file's header for the stream contract.
+
+Parity status: every function here is pinned by ``tests/test_oracle_*.py``
+against values fixed by the paper or by mathematics (closed forms, library
+distributions, an independent Philox implementation, brute force).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "brng_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+KIND_U, KIND_N, KIND_E, KIND_U64 = 0, 1, 2, 3
+UNIT_WIDTH = 64  # chains per unit: the stream contract's grouping
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no GPU toolchain involved)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = C.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+_u8p = C.POINTER(C.c_uint8)
+_u32p = C.POINTER(C.c_uint32)
+_u64p = C.POINTER(C.c_uint64)
+_i32p = C.POINTER(C.c_int32)
+_dp = C.POINTER(C.c_double)
+
+
+def _declare(L):
+    L.or_philox4x32.argtypes = [_u32p, _u32p, C.c_int, _u32p]
+    L.or_block_words.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, _u32p]
+    L.or_u32.argtypes = [C.c_uint32]
+    L.or_u32.restype = C.c_double
+    L.or_u64.argtypes = [C.c_uint32, C.c_uint32]
+    L.or_u64.restype = C.c_double
+    L.or_entry.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64]
+    L.or_entry.restype = C.c_double
+    L.or_entries.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64, _dp]
+    L.or_words.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64, _u32p]
+    L.or_tol.argtypes = [C.c_double]
+    L.or_tol.restype = C.c_double
+    L.or_u32_many.argtypes = [_u32p, C.c_uint64, _dp]
+    L.or_step_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, _u64p, _dp, _dp, _dp, _dp]
+    L.or_step_normal.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _dp, _dp, _dp]
+    L.or_step_exp.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _dp, _dp]
+    L.or_step_gamma.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _dp, _dp, _dp, _i32p, _i32p]
+    L.or_step_dirichlet.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _u64p, _i32p, _dp, _dp, _dp, _dp]
+    L.or_multinomial.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _u64p, _i32p, _i32p, _dp, _i32p]
+    L.or_triangle.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _dp, _dp, _u64p, _dp, _dp, _dp, _dp]
+    L.or_normexp.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, _dp, _u64p, _dp, _dp, _dp, _dp]
+    L.or_expchain.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, _dp, _u64p, _dp, _dp]
+    L.or_gamma_chain.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _i32p, _i32p, _dp, _u64p, _dp, _dp, _dp]
+    L.or_lda.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _i32p, _i32p, C.c_uint32, _i32p, _u64p, _dp, _dp, _i32p, _dp, _dp]
+
+
+def _p(a, t):
+    if a is None:
+        return None
+    return a.ctypes.data_as(t)
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _n_units(n, width=UNIT_WIDTH):
+    return (n + width - 1) // width
+
+
+def new_cursors(n_units: int) -> np.ndarray:
+    """Four pool counters per unit, all at zero (constructor, Sec. 2.2)."""
+    return np.zeros((n_units, 4), dtype=np.uint64)
+
+
+# --------------------------------------------------------------------------
+# Core engine and conversions
+# --------------------------------------------------------------------------
+
+def philox4x32(ctr, key, rounds: int = 10) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().or_philox4x32(_p(c, _u32p), _p(k, _u32p), int(rounds), _p(out, _u32p))
+    return out
+
+
+def words(seed: int, unit: int, kind: int, block0: int, nblocks: int) -> np.ndarray:
+    """Raw Philox words of pool blocks [block0, block0 + nblocks)."""
+    out = np.zeros(4 * nblocks, dtype=np.uint32)
+    lib().or_words(seed, unit, kind, block0, nblocks, _p(out, _u32p))
+    return out
+
+
+def u32(w: int) -> float:
+    return lib().or_u32(int(w))
+
+
+def u64(wa: int, wb: int) -> float:
+    return lib().or_u64(int(wa), int(wb))
+
+
+def entries(seed: int, unit: int, kind: int, j0: int, n: int) -> np.ndarray:
+    """Pool entries [j0, j0 + n) of (seed, unit, kind), in double precision."""
+    out = np.zeros(n, dtype=np.float64)
+    lib().or_entries(seed, unit, kind, j0, n, _p(out, _dp))
+    return out
+
+
+def tol(m) -> np.ndarray:
+    """max(4 ulp32(M), 1e-6 M) elementwise."""
+    f = lib().or_tol
+    return np.array([f(float(x)) for x in np.ravel(m)]).reshape(np.shape(m))
+
+
+# --------------------------------------------------------------------------
+# One call per chain (the one-at-a-time scenario, Sec. 1)
+# --------------------------------------------------------------------------
+
+def step_uniform(seed, cursors, a, b, kind=KIND_U, width=UNIT_WIDTH, unit0=0):
+    a, b = _d(a), _d(b)
+    n = a.size
+    out, t = np.zeros(n), np.zeros(n)
+    lib().or_step_uniform(seed, unit0, n, width, kind, _p(cursors, _u64p), _p(a, _dp), _p(b, _dp),
+                          _p(out, _dp), _p(t, _dp))
+    return out, t
+
+
+def step_normal(seed, cursors, mu, sigma, width=UNIT_WIDTH, unit0=0):
+    mu, sigma = _d(mu), _d(sigma)
+    n = mu.size
+    out, t = np.zeros(n), np.zeros(n)
+    lib().or_step_normal(seed, unit0, n, width, _p(cursors, _u64p), _p(mu, _dp), _p(sigma, _dp),
+                         _p(out, _dp), _p(t, _dp))
+    return out, t
+
+
+def step_exp(seed, cursors, lam, width=UNIT_WIDTH, unit0=0):
+    lam = _d(lam)
+    n = lam.size
+    out, t = np.zeros(n), np.zeros(n)
+    lib().or_step_exp(seed, unit0, n, width, _p(cursors, _u64p), _p(lam, _dp), _p(out, _dp), _p(t, _dp))
+    return out, t
+
+
+def step_gamma(seed, cursors, alpha, width=UNIT_WIDTH, unit0=0):
+    """One Gamma(alpha_c, 1) per chain; returns (g, tol, margin, nN, nE)."""
+    alpha = _d(alpha)
+    n = alpha.size
+    out, t, m = np.zeros(n), np.zeros(n), np.zeros(n)
+    nN, nE = np.zeros(n, np.int32), np.zeros(n, np.int32)
+    lib().or_step_gamma(seed, unit0, n, width, _p(cursors, _u64p), _p(alpha, _dp), _p(out, _dp),
+                        _p(t, _dp), _p(m, _dp), _p(nN, _i32p), _p(nE, _i32p))
+    return out, t, m, nN, nE
+
+
+def step_dirichlet(seed, cursors, offsets, alpha, unit0=0):
+    """One Dirichlet(alpha_i) per item; item i owns alpha[offsets[i]:offsets[i+1]]."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.int32)
+    alpha = _d(alpha)
+    n_items = offsets.size - 1
+    out, t = np.zeros(alpha.size), np.zeros(alpha.size)
+    m = np.zeros(n_items)
+    lib().or_step_dirichlet(seed, unit0, n_items, _p(cursors, _u64p), _p(offsets, _i32p), _p(alpha, _dp),
+                            _p(out, _dp), _p(t, _dp), _p(m, _dp))
+    return out, t, m
+
+
+def multinomial(seed, cursors, offsets, ntok, theta, unit0=0):
+    offsets = np.ascontiguousarray(offsets, dtype=np.int32)
+    ntok = np.ascontiguousarray(ntok, dtype=np.int32)
+    theta = _d(theta)
+    counts = np.zeros(theta.size, dtype=np.int32)
+    lib().or_multinomial(seed, unit0, offsets.size - 1, _p(cursors, _u64p), _p(offsets, _i32p),
+                         _p(ntok, _i32p), _p(theta, _dp), _p(counts, _i32p))
+    return counts
+
+
+# --------------------------------------------------------------------------
+# Chain models
+# --------------------------------------------------------------------------
+
+def triangle(seed, n_chains, iters, x0=None, y0=None, cursors=None, trace=True,
+             width=UNIT_WIDTH, unit0=0):
+    """Eq. 1 / Fig. 1 triangle Gibbs sampler in FP64; returns dict."""
+    nu = _n_units(n_chains, width)
+    cur = new_cursors(nu) if cursors is None else cursors
+    xf, yf = np.zeros(n_chains), np.zeros(n_chains)
+    xtr = np.zeros((iters, n_chains)) if trace else None
+    ytr = np.zeros((iters, n_chains)) if trace else None
+    x0 = None if x0 is None else _d(x0)
+    y0 = None if y0 is None else _d(y0)
+    lib().or_triangle(seed, unit0, n_chains, width, iters, _p(x0, _dp), _p(y0, _dp), _p(cur, _u64p),
+                      _p(xtr, _dp), _p(ytr, _dp), _p(xf, _dp), _p(yf, _dp))
+    return dict(x=xf, y=yf, xtrace=xtr, ytrace=ytr, cursors=cur)
+
+
+def normexp(seed, n_chains, steps, s0=None, cursors=None, width=UNIT_WIDTH, unit0=0):
+    """s' ~ N(0.9 s, 0.5 + |s|), e ~ Exp(1 + s'^2); fresh when s0 is None."""
+    nu = _n_units(n_chains, width)
+    cur = new_cursors(nu) if cursors is None else cursors
+    s = np.zeros(n_chains) if s0 is None else _d(s0).copy()
+    str_, etr = np.zeros((steps, n_chains)), np.zeros((steps, n_chains))
+    stol, etol = np.zeros((steps, n_chains)), np.zeros((steps, n_chains))
+    lib().or_normexp(seed, unit0, n_chains, width, steps, 1 if s0 is None else 0, _p(s, _dp),
+                     _p(cur, _u64p), _p(str_, _dp), _p(etr, _dp), _p(stol, _dp), _p(etol, _dp))
+    return dict(s=s, strace=str_, etrace=etr, stol=stol, etol=etol, cursors=cur)
+
+
+def expchain(seed, n_chains, steps, e0=None, cursors=None, width=UNIT_WIDTH, unit0=0):
+    """e' ~ Exp(1 + e^2) (rate); fresh (e_0 = first exponential) when e0 is None."""
+    nu = _n_units(n_chains, width)
+    cur = new_cursors(nu) if cursors is None else cursors
+    e = np.zeros(n_chains) if e0 is None else _d(e0).copy()
+    etr, etol = np.zeros((steps, n_chains)), np.zeros((steps, n_chains))
+    lib().or_expchain(seed, unit0, n_chains, width, steps, 1 if e0 is None else 0, _p(e, _dp),
+                      _p(cur, _u64p), _p(etr, _dp), _p(etol, _dp))
+    return dict(e=e, etrace=etr, etol=etol, cursors=cur)
+
+
+def u32_many(w) -> np.ndarray:
+    w = np.ascontiguousarray(w, dtype=np.uint32)
+    out = np.zeros(w.size, dtype=np.float64)
+    lib().or_u32_many(_p(w, _u32p), w.size, _p(out, _dp))
+    return out
+
+
+def sort_by_length(steps) -> np.ndarray:
+    """Slot order: chains stably sorted by descending step count."""
+    steps = np.asarray(steps)
+    return np.argsort(-steps.astype(np.int64), kind="stable").astype(np.int32)
+
+
+def gamma_chain(seed, alpha0, steps, perm=None, cursors=None, width=UNIT_WIDTH, unit0=0):
+    """alpha_{t+1} = 0.1 + g_t, g_t ~ Gamma(alpha_t, 1); traces are [t][slot]."""
+    alpha = _d(alpha0).copy()
+    steps = np.ascontiguousarray(steps, dtype=np.int32)
+    n = alpha.size
+    if perm is None:
+        perm = sort_by_length(steps)
+    perm = np.ascontiguousarray(perm, dtype=np.int32)
+    nu = _n_units(n, width)
+    cur = new_cursors(nu) if cursors is None else cursors
+    smax = int(steps.max()) if n else 0
+    gtr, gtol, gmar = (np.full((smax, n), np.nan) for _ in range(3))
+    lib().or_gamma_chain(seed, unit0, n, width, _p(perm, _i32p), _p(steps, _i32p), _p(alpha, _dp),
+                         _p(cur, _u64p), _p(gtr, _dp), _p(gtol, _dp), _p(gmar, _dp))
+    return dict(alpha=alpha, gtrace=gtr, gtol=gtol, gmargin=gmar, perm=perm, cursors=cur)
+
+
+def lda(seed, offsets, ntok, sweeps, counts0=None, cursors=None, unit0=0):
+    """Dirichlet(0.1 + counts) then Multinomial(n_d, theta), per document."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.int32)
+    ntok = np.ascontiguousarray(ntok, dtype=np.int32)
+    nd = offsets.size - 1
+    total = int(offsets[-1])
+    counts = (np.zeros(total, np.int32) if counts0 is None
+              else np.ascontiguousarray(counts0, dtype=np.int32).copy())
+    cur = new_cursors(nd) if cursors is None else cursors
+    thtr, thtol = np.zeros((sweeps, total)), np.zeros((sweeps, total))
+    cntr = np.zeros((sweeps, total), np.int32)
+    gmar, mmar = np.zeros((sweeps, nd)), np.zeros((sweeps, nd))
+    lib().or_lda(seed, unit0, nd, _p(offsets, _i32p), _p(ntok, _i32p), sweeps, _p(counts, _i32p),
+                 _p(cur, _u64p), _p(thtr, _dp), _p(thtol, _dp), _p(cntr, _i32p),
+                 _p(gmar, _dp), _p(mmar, _dp))
+    return dict(counts=counts, theta=thtr, theta_tol=thtol, ctrace=cntr, gmargin=gmar,
+                mmargin=mmar, cursors=cur)

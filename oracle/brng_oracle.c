@@ -1,0 +1,821 @@
+/*
+ * brng oracle: a plain, scalar, double-precision CPU reference for the
+ * varying-parameter base-pool random number generator of Mahani & Sharabiani,
+ * "Efficient SIMD RNG for Varying-Parameter Streams: C++ Class BatchRNG"
+ * (arXiv 1412.4825).
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this library; the product path never
+ * does.  It shares no source, header, table or helper with the HIP library.
+ *
+ * Everything here is written for a reader holding the paper:
+ *   - base pools of standard uniform, Gaussian and exponential deviates that
+ *     are refilled in bulk and consumed one entry at a time, with a counter
+ *     per pool (Sec. 2.1 "Key Concepts", Sec. 2.2 "Implementation");
+ *   - reducible transforms a + (b - a) x (Sec. 2.1, second concept);
+ *   - irreducible samplers built on the pools (Sec. 2.2, RNG functions);
+ *   - the triangle Gibbs sampler (Eq. 1 and Fig. 1);
+ *   - Dirichlet from normalised gammas (Sec. 1, footnote on Dirichlet).
+ * The paper leaves the core generator, the Gaussian and exponential methods
+ * and the gamma algorithm open; this file fixes them as follows:
+ *   - core engine: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11);
+ *   - Gaussian: Box-Muller (Box & Muller, 1958);
+ *   - exponential: -ln u;
+ *   - gamma: Marsaglia & Tsang (ACM TOMS 2000) with the u^(1/alpha) boost
+ *     for alpha < 1, the uniform's logarithm taken from the exponential pool
+ *     (ln u = -E, the paper's "logarithm of uniform deviates" buffer).
+ *
+ * Stream contract (what makes exact comparison possible):
+ *   key     = (unit id, seed low 32 bits)
+ *   counter = (block low 32, block high 32, kind, seed high 32)
+ *   kinds   : 0 = U (fp32 uniform), 1 = N (Gaussian), 2 = E (exponential),
+ *             3 = U64 (fp64 uniform)
+ *   entry j of kind U/N/E lives in block j/4, word j%4; N pairs words
+ *   (0,1) and (2,3) of a block with the cosine branch on the even entry;
+ *   entry j of U64 uses words 2(j%2), 2(j%2)+1 of block j/2.
+ *   A "call" gives one entry to every active slot of a unit, in ascending
+ *   slot order; the pool counter (cursor) counts entries consumed.
+ *
+ * Build: gcc -O2 -fPIC -shared -ffp-contract=off -o liboracle.so brng_oracle.c -lm
+ * (-ffp-contract=off: every product and sum is rounded on its own, as
+ * written, so the triangle trajectories are reproducible bit for bit).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { OR_U = 0, OR_N = 1, OR_E = 2, OR_U64 = 3 };
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32 (Salmon et al. SC'11): round function and key schedule.       */
+/* ------------------------------------------------------------------------ */
+
+static void mulhilo32(uint32_t a, uint32_t b, uint32_t *hi, uint32_t *lo)
+{
+    uint64_t p = (uint64_t)a * (uint64_t)b; /* the full 64-bit product */
+    *hi = (uint32_t)(p >> 32);
+    *lo = (uint32_t)p;
+}
+
+/* Apply `rounds` Philox4x32 rounds to ctr under key; rounds = 10 is the
+ * generator.  The key is bumped by the Weyl constants between rounds, so the
+ * first round uses the key as given. */
+void or_philox4x32(const uint32_t ctr[4], const uint32_t key[2], int rounds,
+                   uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < rounds; r++) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint32_t hi0, lo0, hi1, lo1;
+        mulhilo32(0xD2511F53u, c0, &hi0, &lo0);
+        mulhilo32(0xCD9E8D57u, c2, &hi1, &lo1);
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* The four words of pool block `block` for (seed, unit, kind). */
+void or_block_words(uint64_t seed, uint32_t unit, uint32_t kind, uint64_t block,
+                    uint32_t w[4])
+{
+    uint32_t ctr[4] = {(uint32_t)block, (uint32_t)(block >> 32), kind,
+                       (uint32_t)(seed >> 32)};
+    uint32_t key[2] = {unit, (uint32_t)seed};
+    or_philox4x32(ctr, key, 10, w);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Conversions to base deviates.                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Uniform on the open midpoint grid (2k+1) 2^-24, k = the top 23 bits of w.
+ * Every value is in (0,1), so the logarithm is finite and a + (b-a)u stays
+ * strictly inside (a,b) (the paper writes U[0,1)). */
+double or_u32(uint32_t w)
+{
+    uint64_t k = (uint64_t)(w >> 9);
+    return (double)(2 * k + 1) * 0x1p-24;
+}
+
+/* Uniform on the grid (2k+1) 2^-53 with a 52-bit k built from two words. */
+double or_u64(uint32_t wa, uint32_t wb)
+{
+    uint64_t k = ((uint64_t)wa << 20) | (uint64_t)(wb >> 12);
+    return (double)(2 * k + 1) * 0x1p-53;
+}
+
+/* Entry j of the pool of `kind` for (seed, unit). */
+double or_entry(uint64_t seed, uint32_t unit, uint32_t kind, uint64_t j)
+{
+    uint32_t w[4];
+    if (kind == OR_U64) {
+        or_block_words(seed, unit, kind, j / 2, w);
+        int p = (int)(j % 2);
+        return or_u64(w[2 * p], w[2 * p + 1]);
+    }
+    or_block_words(seed, unit, kind, j / 4, w);
+    int q = (int)(j % 4);
+    if (kind == OR_U)
+        return or_u32(w[q]);
+    if (kind == OR_E)
+        return -log(or_u32(w[q]));
+    /* Box-Muller on the pair (w[2p], w[2p+1]). */
+    int p = q / 2;
+    double ua = or_u32(w[2 * p]);
+    double ub = or_u32(w[2 * p + 1]);
+    double r = sqrt(-2.0 * log(ua));
+    double ang = 2.0 * M_PI * ub;
+    return (q % 2 == 0) ? r * cos(ang) : r * sin(ang);
+}
+
+void or_entries(uint64_t seed, uint32_t unit, uint32_t kind, uint64_t j0,
+                uint64_t n, double *out)
+{
+    for (uint64_t i = 0; i < n; i++)
+        out[i] = or_entry(seed, unit, kind, j0 + i);
+}
+
+/* Conversions of many words at once (for exhaustive checks). */
+void or_u32_many(const uint32_t *w, uint64_t n, double *out)
+{
+    for (uint64_t i = 0; i < n; i++)
+        out[i] = or_u32(w[i]);
+}
+
+void or_words(uint64_t seed, uint32_t unit, uint32_t kind, uint64_t b0,
+              uint64_t nb, uint32_t *out)
+{
+    for (uint64_t b = 0; b < nb; b++)
+        or_block_words(seed, unit, kind, b0 + b, out + 4 * b);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pool counters (Sec. 2.2: buffer_counter per reducible distribution).     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint64_t seed;
+    uint32_t unit;
+    uint64_t *cur; /* four counters, one per kind */
+} stream_t;
+
+static double take(stream_t *s, int kind)
+{
+    double v = or_entry(s->seed, s->unit, (uint32_t)kind, s->cur[kind]);
+    s->cur[kind] += 1;
+    return v;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tolerances.  A single floating-point result r may differ from this       */
+/* double-precision value by max(4 ulp32(M), 1e-6 M), where M is its        */
+/* condition-aware magnitude.  For sums M is the largest of |r| and the     */
+/* operands' magnitudes; for results that depend on a base deviate through  */
+/* an amplifying map, M is |r| (1 + kappa) with kappa the relative          */
+/* condition number with respect to that deviate.                           */
+/* ------------------------------------------------------------------------ */
+
+static double ulp32(double m)
+{
+    m = fabs(m);
+    if (m < 0x1p-126)
+        return 0x1p-149;
+    int e;
+    frexp(m, &e); /* m = f 2^e with f in [0.5,1) */
+    return ldexp(1.0, e - 24);
+}
+
+double or_tol(double m)
+{
+    double a = 4.0 * ulp32(m), b = 1e-6 * fabs(m);
+    return a > b ? a : b;
+}
+
+static double dmax(double a, double b) { return a > b ? a : b; }
+
+/* ------------------------------------------------------------------------ */
+/* Reducible distributions (Sec. 2.1): one call over a set of chains.       */
+/* Chains are grouped into units of `width` consecutive chains; cursors     */
+/* holds four counters per unit.                                            */
+/* ------------------------------------------------------------------------ */
+
+static void unit_range(uint32_t n, uint32_t width, uint32_t u, uint32_t *lo,
+                       uint32_t *hi)
+{
+    *lo = u * width;
+    *hi = (*lo + width < n) ? *lo + width : n;
+}
+
+/* U(a,b) = a + (b - a) u */
+void or_step_uniform(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, int kind,
+                     uint64_t *cursors, const double *a, const double *b,
+                     double *out, double *tol)
+{
+    uint32_t nu = (n + width - 1) / width;
+    for (uint32_t u = 0; u < nu; u++) {
+        stream_t s = {seed, unit0 + u, cursors + 4 * (size_t)u};
+        uint32_t lo, hi;
+        unit_range(n, width, u, &lo, &hi);
+        for (uint32_t c = lo; c < hi; c++) {
+            double x = take(&s, kind);
+            double span = b[c] - a[c];
+            out[c] = a[c] + span * x;
+            if (tol)
+                tol[c] = or_tol(dmax(fabs(out[c]), dmax(fabs(a[c]), fabs(span * x))));
+        }
+    }
+}
+
+/* N(mu, sigma) = mu + sigma z */
+void or_step_normal(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, uint64_t *cursors,
+                    const double *mu, const double *sigma, double *out,
+                    double *tol)
+{
+    uint32_t nu = (n + width - 1) / width;
+    for (uint32_t u = 0; u < nu; u++) {
+        stream_t s = {seed, unit0 + u, cursors + 4 * (size_t)u};
+        uint32_t lo, hi;
+        unit_range(n, width, u, &lo, &hi);
+        for (uint32_t c = lo; c < hi; c++) {
+            double z = take(&s, OR_N);
+            out[c] = mu[c] + sigma[c] * z;
+            if (tol)
+                tol[c] = or_tol(dmax(fabs(out[c]), dmax(fabs(mu[c]), fabs(sigma[c] * z))));
+        }
+    }
+}
+
+/* Exp(lambda) with rate lambda: E / lambda */
+void or_step_exp(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, uint64_t *cursors,
+                 const double *lambda, double *out, double *tol)
+{
+    uint32_t nu = (n + width - 1) / width;
+    for (uint32_t u = 0; u < nu; u++) {
+        stream_t s = {seed, unit0 + u, cursors + 4 * (size_t)u};
+        uint32_t lo, hi;
+        unit_range(n, width, u, &lo, &hi);
+        for (uint32_t c = lo; c < hi; c++) {
+            double e = take(&s, OR_E);
+            out[c] = e / lambda[c];
+            if (tol)
+                tol[c] = or_tol(out[c]);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gamma(alpha, 1): Marsaglia & Tsang (2000).                               */
+/*                                                                          */
+/* For a >= 1: d = a - 1/3, c = 1/sqrt(9d).  Draw x ~ N(0,1) and set        */
+/* v = (1 + c x)^3; if 1 + c x <= 0 draw again.  Otherwise draw u and       */
+/* accept d v when ln u < x^2/2 + d - d v + d ln v.  Here ln u = -E with E  */
+/* from the exponential pool.  For alpha < 1 the draw is made with shape    */
+/* alpha + 1 and multiplied by u'^(1/alpha) = exp(-E'/alpha).               */
+/*                                                                          */
+/* Consumption order within one call over the slots of a unit: rounds of    */
+/* (a Gaussian for every pending slot, ascending; an exponential for every  */
+/* pending slot whose 1 + c x > 0, ascending; accepted slots retire), until */
+/* no slot is pending; then one exponential for every slot with alpha < 1,  */
+/* ascending.                                                               */
+/*                                                                          */
+/* Besides the value the oracle reports, per slot:                          */
+/*   tol    : bound on |gpu - oracle| (local rounding + the effect of an    */
+/*            error bound `abound` carried by alpha itself),                */
+/*   dg     : d g / d alpha (same base deviates),                           */
+/*   margin : the smallest |decision value| / its tolerance over the        */
+/*            slot's decisions; a value <= 1 means an fp32 implementation   */
+/*            may legitimately decide the other way,                        */
+/*   nN, nE : entries consumed.                                             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double g, tol, dg, margin;
+    int nN, nE;
+} gdraw_t;
+
+/* q(y) = 3 ln(1+y) - 3y + 3y^2/2 - y^3; d q(y) is the accept statistic
+ * x^2/2 + d(1 - v + ln v) rewritten with y = c x (used here only for the
+ * tolerance scales, never for a decision). */
+static double qfun(double y) { return 3.0 * log1p(y) - 3.0 * y + 1.5 * y * y - y * y * y; }
+
+#define OR_MAXSLOT 256
+
+static void or_gamma_call(stream_t *s, int nslots, const uint8_t *active,
+                   const double *alpha, const double *abound, gdraw_t *res)
+{
+    double d[OR_MAXSLOT], c[OR_MAXSLOT], x[OR_MAXSLOT], v0[OR_MAXSLOT];
+    double kx[OR_MAXSLOT]; /* |d ln(g)/d ln(x)| of the accepted draw */
+    uint8_t pending[OR_MAXSLOT];
+    int any = 0;
+    for (int k = 0; k < nslots; k++) {
+        pending[k] = active[k];
+        res[k].g = 0.0; res[k].tol = 0.0; res[k].dg = 0.0;
+        res[k].margin = INFINITY; res[k].nN = 0; res[k].nE = 0;
+        kx[k] = 0.0;
+        if (!active[k])
+            continue;
+        if (!(alpha[k] > 0.0 && alpha[k] < 0x1p64)) { /* no valid gamma: NaN */
+            pending[k] = 0;
+            res[k].g = NAN;
+            continue;
+        }
+        double a = alpha[k] < 1.0 ? alpha[k] + 1.0 : alpha[k];
+        d[k] = a - 1.0 / 3.0;
+        c[k] = 1.0 / sqrt(9.0 * d[k]);
+        any = 1;
+    }
+    while (any) {
+        /* a Gaussian for every pending slot, ascending */
+        for (int k = 0; k < nslots; k++) {
+            if (!pending[k])
+                continue;
+            x[k] = take(s, OR_N);
+            res[k].nN++;
+            v0[k] = 1.0 + c[k] * x[k];
+            /* sign decision on 1 + c x */
+            double y = c[k] * x[k];
+            double ab = abound ? abound[k] : 0.0;
+            double t = or_tol(dmax(1.0, fabs(y))) + fabs(y / (2.0 * d[k])) * ab;
+            double m = fabs(v0[k]) / t;
+            if (m < res[k].margin)
+                res[k].margin = m;
+        }
+        /* an exponential for every pending slot with 1 + c x > 0, ascending */
+        any = 0;
+        for (int k = 0; k < nslots; k++) {
+            if (!pending[k])
+                continue;
+            if (v0[k] <= 0.0) {
+                any = 1;
+                continue;
+            }
+            double e = take(s, OR_E);
+            res[k].nE++;
+            double v = v0[k] * v0[k] * v0[k];
+            double stat = e + (0.5 * x[k] * x[k] + d[k] - d[k] * v + d[k] * log(v));
+            /* decision tolerance: representation of the base deviates
+             * (E, and x through y), plus alpha's own error bound */
+            double y = c[k] * x[k];
+            double dq = d[k] * qfun(y);
+            double cond = d[k] * 3.0 * pow(y, 4) / (1.0 + y);
+            double ab = abound ? abound[k] : 0.0;
+            double dstat = qfun(y) + 1.5 * pow(y, 4) / (1.0 + y);
+            double t = or_tol(e + fabs(dq) + fabs(cond)) + fabs(dstat) * ab;
+            double m = fabs(stat) / t;
+            if (m < res[k].margin)
+                res[k].margin = m;
+            if (stat > 0.0) { /* ln u = -E < x^2/2 + d(1 - v + ln v) */
+                pending[k] = 0;
+                res[k].g = d[k] * v;
+                kx[k] = fabs(3.0 * y / (1.0 + y));
+                res[k].dg = (1.0 + y) * (1.0 + y) * (1.0 - 0.5 * y);
+                res[k].tol = or_tol(res[k].g * (1.0 + kx[k])) + fabs(res[k].dg) * ab;
+            } else {
+                any = 1;
+            }
+        }
+    }
+    /* boost for alpha < 1: multiply by exp(-E'/alpha), ascending */
+    for (int k = 0; k < nslots; k++) {
+        if (!active[k] || !(alpha[k] > 0.0 && alpha[k] < 1.0))
+            continue;
+        double e = take(s, OR_E);
+        res[k].nE++;
+        double f = exp(-e / alpha[k]);
+        double g1 = res[k].g;
+        double dg1 = res[k].dg;
+        res[k].g = g1 * f;
+        res[k].dg = f * dg1 + res[k].g * e / (alpha[k] * alpha[k]);
+        double ab = abound ? abound[k] : 0.0;
+        double kappa = kx[k] + e / alpha[k];
+        res[k].tol = or_tol(res[k].g * (1.0 + kappa)) + fabs(res[k].dg) * ab;
+    }
+}
+
+/* One gamma draw per chain, chains grouped into units of `width`. */
+void or_step_gamma(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, uint64_t *cursors,
+                   const double *alpha, double *out, double *tol, double *margin,
+                   int32_t *nN, int32_t *nE)
+{
+    if (width == 0 || width > OR_MAXSLOT)
+        return;
+    uint32_t nu = (n + width - 1) / width;
+    uint8_t act[OR_MAXSLOT];
+    gdraw_t res[OR_MAXSLOT];
+    for (uint32_t u = 0; u < nu; u++) {
+        stream_t s = {seed, unit0 + u, cursors + 4 * (size_t)u};
+        uint32_t lo, hi;
+        unit_range(n, width, u, &lo, &hi);
+        int ns = (int)(hi - lo);
+        for (int k = 0; k < ns; k++)
+            act[k] = 1;
+        or_gamma_call(&s, ns, act, alpha + lo, NULL, res);
+        for (int k = 0; k < ns; k++) {
+            out[lo + k] = res[k].g;
+            if (tol) tol[lo + k] = res[k].tol;
+            if (margin) margin[lo + k] = res[k].margin;
+            if (nN) nN[lo + k] = res[k].nN;
+            if (nE) nE[lo + k] = res[k].nE;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dirichlet (Sec. 1, footnote): y_k ~ Gamma(alpha_k, 1), x_k = y_k / sum.  */
+/* One item (a unit) holds K components; they are drawn in batches of 64    */
+/* slots, one gamma call per batch, in ascending batch order.               */
+/* ------------------------------------------------------------------------ */
+
+#define OR_BATCH 64
+
+/* Draw theta for one item; y/ytol are scratch of length K. Returns the
+ * smallest decision margin. tol: bound on |gpu theta - oracle theta|. */
+static double dirichlet_item(stream_t *s, int K, const double *alpha,
+                             double *theta, double *tol, double *y, double *ytol)
+{
+    uint8_t act[OR_BATCH];
+    gdraw_t res[OR_BATCH];
+    double mmin = INFINITY;
+    for (int b0 = 0; b0 < K; b0 += OR_BATCH) {
+        int nb = (K - b0 < OR_BATCH) ? K - b0 : OR_BATCH;
+        for (int k = 0; k < nb; k++)
+            act[k] = 1;
+        or_gamma_call(s, nb, act, alpha + b0, NULL, res);
+        for (int k = 0; k < nb; k++) {
+            y[b0 + k] = res[k].g;
+            ytol[b0 + k] = res[k].tol;
+            if (res[k].margin < mmin)
+                mmin = res[k].margin;
+        }
+    }
+    double S = 0.0, St = 0.0;
+    for (int k = 0; k < K; k++) {
+        S += y[k];
+        St += ytol[k];
+    }
+    for (int k = 0; k < K; k++) {
+        theta[k] = (S > 0.0) ? y[k] / S : 0.0;
+        if (tol) {
+            /* relative error of y_k plus that of the sum (including an fp32
+             * summation of K terms) */
+            double rel = (y[k] > 0.0 ? ytol[k] / y[k] : 0.0) +
+                         (S > 0.0 ? St / S : 0.0) + (double)K * 0x1p-24;
+            tol[k] = or_tol(theta[k]) + theta[k] * rel;
+            if (y[k] < 0x1p-126) /* an underflowed gamma gives theta ~ 0 */
+                tol[k] = dmax(tol[k], 0x1p-126 / (S > 0.0 ? S : 1.0));
+        }
+    }
+    return mmin;
+}
+
+void or_step_dirichlet(uint64_t seed, uint32_t unit0, uint32_t n_items, uint64_t *cursors,
+                       const int32_t *offsets, const double *alpha, double *out,
+                       double *tol, double *margin)
+{
+    int32_t kmax = 0;
+    for (uint32_t i = 0; i < n_items; i++) {
+        int32_t K = offsets[i + 1] - offsets[i];
+        if (K > kmax)
+            kmax = K;
+    }
+    double *y = (double *)malloc(sizeof(double) * (size_t)(kmax + 1));
+    double *yt = (double *)malloc(sizeof(double) * (size_t)(kmax + 1));
+    for (uint32_t i = 0; i < n_items; i++) {
+        stream_t s = {seed, unit0 + i, cursors + 4 * (size_t)i};
+        int K = offsets[i + 1] - offsets[i];
+        double m = dirichlet_item(&s, K, alpha + offsets[i], out + offsets[i],
+                                  tol ? tol + offsets[i] : NULL, y, yt);
+        if (margin)
+            margin[i] = m;
+    }
+    free(y);
+    free(yt);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multinomial(n, theta) from pool uniforms, integer exact.                 */
+/*   q_k = rint(theta_k 2^24) (theta_k rounded to fp32 first: the integer   */
+/*   decision is taken in the deviates' precision), Q = sum q_k (all q_k =  */
+/*   1 if Q = 0), C_k = q_0 + ... + q_k.  Token i takes u_i from the U pool,*/
+/*   j_i = (u_i 2^24 - 1)/2 in [0, 2^23), t_i = floor(j_i Q / 2^23), and    */
+/*   falls in the first bin k with t_i < C_k.                               */
+/* qdrift: allowed drift of each q_k (from theta's tolerance); the returned */
+/* value is the smallest (distance of a t_i to a boundary) - (drift of that */
+/* boundary); <= 0 means an implementation may place that token on the      */
+/* other side.                                                              */
+/* ------------------------------------------------------------------------ */
+
+static double multinomial_item(stream_t *s, int K, int32_t ntok, const double *theta,
+                               const double *ttol, int want_margin, int32_t *counts,
+                               int64_t *C)
+{
+    int64_t Q = 0;
+    for (int k = 0; k < K; k++) {
+        float t32 = (float)theta[k];
+        int64_t q = (int64_t)rint((double)t32 * 16777216.0);
+        Q += q;
+        C[k] = Q;
+    }
+    if (Q == 0) {
+        for (int k = 0; k < K; k++)
+            C[k] = k + 1;
+        Q = K;
+    }
+    /* allowed drift of each boundary and of Q */
+    double drift_acc = 0.0;
+    double *drift = (double *)malloc(sizeof(double) * (size_t)K);
+    for (int k = 0; k < K; k++) {
+        drift_acc += 1.0 + (ttol ? ttol[k] : 0.0) * 16777216.0;
+        drift[k] = drift_acc;
+    }
+    double dQ = drift_acc;
+    double mmin = INFINITY;
+    for (int k = 0; k < K; k++)
+        counts[k] = 0;
+    for (int32_t i = 0; i < ntok; i++) {
+        double u = take(s, OR_U);
+        int64_t j = (int64_t)((u * 16777216.0 - 1.0) / 2.0);
+        int64_t t = (int64_t)(((uint64_t)j * (uint64_t)Q) >> 23);
+        int bin = 0;
+        while (!(t < C[bin]))
+            bin++;
+        counts[bin]++;
+        if (!want_margin)
+            continue;
+        /* distance of t to every boundary, less that boundary's drift */
+        for (int k = 0; k < K; k++) {
+            double dist = fabs((double)t - (double)C[k]);
+            double slack = dist - drift[k] - dQ - 1.0;
+            if (slack < mmin)
+                mmin = slack;
+        }
+    }
+    free(drift);
+    return mmin;
+}
+
+void or_multinomial(uint64_t seed, uint32_t unit0, uint32_t n_items, uint64_t *cursors,
+                    const int32_t *offsets, const int32_t *ntok,
+                    const double *theta, int32_t *counts)
+{
+    int32_t kmax = 1;
+    for (uint32_t i = 0; i < n_items; i++)
+        if (offsets[i + 1] - offsets[i] > kmax)
+            kmax = offsets[i + 1] - offsets[i];
+    int64_t *C = (int64_t *)malloc(sizeof(int64_t) * (size_t)kmax);
+    for (uint32_t i = 0; i < n_items; i++) {
+        stream_t s = {seed, unit0 + i, cursors + 4 * (size_t)i};
+        multinomial_item(&s, offsets[i + 1] - offsets[i], ntok[i],
+                         theta + offsets[i], NULL, 0, counts + offsets[i], C);
+    }
+    free(C);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Chain models.  Traces are [step][slot]; slot p holds chain perm[p]       */
+/* (identity when perm is NULL); units are `width` consecutive slots.       */
+/* A chain c takes part in step t while t < steps[c].                       */
+/* ------------------------------------------------------------------------ */
+
+/* Triangle Gibbs sampler of Eq. 1 / Fig. 1, in double precision:
+ * x <- U(0, 1 - y) then y <- U(0, 1 - x), starting from x = y = 0.5, both
+ * from the U64 pool.  x0/y0 in, xf/yf out (user order). */
+void or_triangle(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, uint32_t iters,
+                 const double *x0, const double *y0, uint64_t *cursors,
+                 double *xtr, double *ytr, double *xf, double *yf)
+{
+    uint32_t nu = (n + width - 1) / width;
+    for (uint32_t u = 0; u < nu; u++) {
+        stream_t s = {seed, unit0 + u, cursors + 4 * (size_t)u};
+        uint32_t lo, hi;
+        unit_range(n, width, u, &lo, &hi);
+        for (uint32_t c = lo; c < hi; c++) {
+            xf[c] = x0 ? x0[c] : 0.5;
+            yf[c] = y0 ? y0[c] : 0.5;
+        }
+        for (uint32_t t = 0; t < iters; t++) {
+            for (uint32_t c = lo; c < hi; c++) { /* x call */
+                double w = take(&s, OR_U64);
+                xf[c] = 0.0 + (1.0 - yf[c] - 0.0) * w;
+                if (xtr)
+                    xtr[(size_t)t * n + c] = xf[c];
+            }
+            for (uint32_t c = lo; c < hi; c++) { /* y call */
+                double w = take(&s, OR_U64);
+                yf[c] = 0.0 + (1.0 - xf[c] - 0.0) * w;
+                if (ytr)
+                    ytr[(size_t)t * n + c] = yf[c];
+            }
+        }
+    }
+}
+
+/* Varying-parameter normal/exponential chain:
+ *   s_{t+1} ~ N(0.9 s_t, 0.5 + |s_t|), then e_{t+1} ~ Exp(1 + s_{t+1}^2).
+ * fresh: s_0 is the chain's first Gaussian (one N call before step 0).
+ * Traces str/etr [t][chain]; stol/etol carry first-order error bounds
+ * propagated along the chain (local tolerance + |d s'/d s| times the
+ * incoming bound). */
+void or_normexp(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, uint32_t steps,
+                int fresh, double *s_state, uint64_t *cursors, double *str,
+                double *etr, double *stol, double *etol)
+{
+    if (width == 0 || width > OR_MAXSLOT)
+        return;
+    uint32_t nu = (n + width - 1) / width;
+    double *B = (double *)malloc(sizeof(double) * (size_t)(width));
+    for (uint32_t u = 0; u < nu; u++) {
+        stream_t st = {seed, unit0 + u, cursors + 4 * (size_t)u};
+        uint32_t lo, hi;
+        unit_range(n, width, u, &lo, &hi);
+        for (uint32_t c = lo; c < hi; c++) {
+            if (fresh) {
+                s_state[c] = take(&st, OR_N);
+                B[c - lo] = or_tol(s_state[c]);
+            } else {
+                B[c - lo] = 0.0;
+            }
+        }
+        for (uint32_t t = 0; t < steps; t++) {
+            double sp[OR_MAXSLOT];
+            for (uint32_t c = lo; c < hi; c++) { /* N call */
+                double z = take(&st, OR_N);
+                double s = s_state[c];
+                double mu = 0.9 * s, sigma = 0.5 + fabs(s);
+                sp[c - lo] = mu + sigma * z;
+                double loc = or_tol(dmax(fabs(sp[c - lo]), dmax(fabs(mu), fabs(sigma * z))));
+                double slope = fabs(0.9 + (s >= 0.0 ? z : -z));
+                B[c - lo] = loc + slope * B[c - lo];
+                str[(size_t)t * n + c] = sp[c - lo];
+                if (stol)
+                    stol[(size_t)t * n + c] = B[c - lo];
+            }
+            for (uint32_t c = lo; c < hi; c++) { /* E call */
+                double e = take(&st, OR_E);
+                double s = sp[c - lo];
+                double lam = 1.0 + s * s;
+                double v = e / lam;
+                etr[(size_t)t * n + c] = v;
+                if (etol)
+                    etol[(size_t)t * n + c] =
+                        or_tol(v) + fabs(2.0 * s * e / (lam * lam)) * B[c - lo];
+                s_state[c] = s;
+            }
+        }
+    }
+    free(B);
+}
+
+/* Exponential chain (the served form's exponential kind):
+ *   e_{t+1} ~ Exp(1 + e_t^2), i.e. E / (1 + e_t^2); fresh: e_0 is the
+ * chain's first exponential.  Bounds propagate as in or_normexp. */
+void or_expchain(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, uint32_t steps,
+                 int fresh, double *e_state, uint64_t *cursors, double *etr, double *etol)
+{
+    if (width == 0 || width > OR_MAXSLOT)
+        return;
+    uint32_t nu = (n + width - 1) / width;
+    double B[OR_MAXSLOT];
+    for (uint32_t u = 0; u < nu; u++) {
+        stream_t st = {seed, unit0 + u, cursors + 4 * (size_t)u};
+        uint32_t lo, hi;
+        unit_range(n, width, u, &lo, &hi);
+        for (uint32_t c = lo; c < hi; c++) {
+            if (fresh) {
+                e_state[c] = take(&st, OR_E);
+                B[c - lo] = or_tol(e_state[c]);
+            } else {
+                B[c - lo] = 0.0;
+            }
+        }
+        for (uint32_t t = 0; t < steps; t++) {
+            for (uint32_t c = lo; c < hi; c++) {
+                double E = take(&st, OR_E);
+                double v = e_state[c];
+                double lam = 1.0 + v * v;
+                double nv = E / lam;
+                B[c - lo] = or_tol(nv) + fabs(2.0 * v * E / (lam * lam)) * B[c - lo];
+                e_state[c] = nv;
+                etr[(size_t)t * n + c] = nv;
+                if (etol)
+                    etol[(size_t)t * n + c] = B[c - lo];
+            }
+        }
+    }
+}
+
+/* Varying-shape gamma chain: alpha_{t+1} = 0.1 + g_t, g_t ~ Gamma(alpha_t, 1).
+ * alpha (user order) in: alpha_0, out: the next shape.  Slots follow perm,
+ * steps[c] per chain.  gtr/gtol/gmar are [t][slot] (NaN where a slot is
+ * idle). */
+void or_gamma_chain(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, const int32_t *perm,
+                    const int32_t *steps, double *alpha, uint64_t *cursors,
+                    double *gtr, double *gtol, double *gmar)
+{
+    if (width == 0 || width > OR_MAXSLOT)
+        return;
+    int32_t smax = 0;
+    for (uint32_t c = 0; c < n; c++)
+        if (steps[c] > smax)
+            smax = steps[c];
+    uint32_t nu = (n + width - 1) / width;
+    for (uint32_t u = 0; u < nu; u++) {
+        stream_t st = {seed, unit0 + u, cursors + 4 * (size_t)u};
+        uint32_t lo, hi;
+        unit_range(n, width, u, &lo, &hi);
+        int ns = (int)(hi - lo);
+        double a[OR_MAXSLOT], ab[OR_MAXSLOT];
+        uint8_t act[OR_MAXSLOT];
+        gdraw_t res[OR_MAXSLOT];
+        for (int k = 0; k < ns; k++) {
+            uint32_t ch = perm ? (uint32_t)perm[lo + k] : lo + k;
+            a[k] = alpha[ch];
+            ab[k] = 0.0;
+        }
+        for (int32_t t = 0; t < smax; t++) {
+            int any = 0;
+            for (int k = 0; k < ns; k++) {
+                uint32_t ch = perm ? (uint32_t)perm[lo + k] : lo + k;
+                act[k] = (uint8_t)(t < steps[ch]);
+                any |= act[k];
+            }
+            if (!any)
+                break;
+            or_gamma_call(&st, ns, act, a, ab, res);
+            for (int k = 0; k < ns; k++) {
+                size_t o = (size_t)t * n + lo + k;
+                if (!act[k]) {
+                    if (gtr) gtr[o] = NAN;
+                    if (gtol) gtol[o] = NAN;
+                    if (gmar) gmar[o] = NAN;
+                    continue;
+                }
+                if (gtr) gtr[o] = res[k].g;
+                if (gtol) gtol[o] = res[k].tol;
+                if (gmar) gmar[o] = res[k].margin;
+                double an = 0.1 + res[k].g;
+                /* the next shape carries g's bound plus the fp32 rounding of
+                 * 0.1 + g and of the constant 0.1 itself */
+                ab[k] = res[k].tol + ulp32(an) + 2e-9;
+                a[k] = an;
+            }
+        }
+        for (int k = 0; k < ns; k++) {
+            uint32_t ch = perm ? (uint32_t)perm[lo + k] : lo + k;
+            alpha[ch] = a[k];
+        }
+    }
+}
+
+/* LDA-style Dirichlet resampling.  Unit = document d (key unit id d).
+ * Per sweep: alpha_k = 0.1 + counts_k; theta ~ Dirichlet(alpha) (gamma
+ * calls per 64-component batch); counts ~ Multinomial(n_d, theta) with the
+ * integer rule above.  counts (in/out) and the traces are laid out by the
+ * component offsets; thtr/thtol/cntr are [sweep][total components],
+ * gmar/mmar are [sweep][doc]. */
+void or_lda(uint64_t seed, uint32_t unit0, uint32_t n_docs, const int32_t *offsets,
+            const int32_t *ntok, uint32_t sweeps, int32_t *counts,
+            uint64_t *cursors, double *thtr, double *thtol, int32_t *cntr,
+            double *gmar, double *mmar)
+{
+    int32_t kmax = 1;
+    for (uint32_t i = 0; i < n_docs; i++)
+        if (offsets[i + 1] - offsets[i] > kmax)
+            kmax = offsets[i + 1] - offsets[i];
+    size_t total = (size_t)offsets[n_docs];
+    double *al = (double *)malloc(sizeof(double) * (size_t)kmax);
+    double *th = (double *)malloc(sizeof(double) * (size_t)kmax);
+    double *tt = (double *)malloc(sizeof(double) * (size_t)kmax);
+    double *y = (double *)malloc(sizeof(double) * (size_t)kmax);
+    double *yt = (double *)malloc(sizeof(double) * (size_t)kmax);
+    int64_t *C = (int64_t *)malloc(sizeof(int64_t) * (size_t)kmax);
+    for (uint32_t d = 0; d < n_docs; d++) {
+        stream_t st = {seed, unit0 + d, cursors + 4 * (size_t)d};
+        int K = offsets[d + 1] - offsets[d];
+        int32_t *cnt = counts + offsets[d];
+        for (uint32_t sw = 0; sw < sweeps; sw++) {
+            for (int k = 0; k < K; k++)
+                al[k] = 0.1 + (double)cnt[k];
+            double gm = dirichlet_item(&st, K, al, th, tt, y, yt);
+            double mm = multinomial_item(&st, K, ntok[d], th, tt, mmar != NULL, cnt, C);
+            for (int k = 0; k < K; k++) {
+                size_t o = (size_t)sw * total + (size_t)offsets[d] + (size_t)k;
+                if (thtr) thtr[o] = th[k];
+                if (thtol) thtol[o] = tt[k];
+                if (cntr) cntr[o] = cnt[k];
+            }
+            if (gmar) gmar[(size_t)sw * n_docs + d] = gm;
+            if (mmar) mmar[(size_t)sw * n_docs + d] = mm;
+        }
+    }
+    free(al); free(th); free(tt); free(y); free(yt); free(C);
+}

@@ -1,0 +1,74 @@
+"""Seeded synthetic workloads (inputs only; no sampler arithmetic lives here).
+
+The paper measures on synthetic streams (Sec. 2.4: 200M samples per
+distribution) and motivates the method with Gibbs sampling (Eq. 1, Fig. 1)
+and LDA (Sec. 1).  These generators draw the inputs of the chain workloads
+with numpy's PCG64 from a fixed workload seed; the same arrays feed the HIP
+library and the CPU oracle.  Sizes can be scaled down for tests.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+WORKLOAD_SEED = 20141217
+
+
+def _rng(seed: int, salt: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64([seed, salt]))
+
+
+def triangle(n_chains: int = 1024, iters: int = 10000):
+    """Eq. 1 / Fig. 1: chains start at x = y = 0.5; nothing random here."""
+    return dict(n_chains=n_chains, iters=iters)
+
+
+def normexp(n_chains: int = 65536, steps: int = 1000):
+    """s' ~ N(0.9 s, 0.5 + |s|), e ~ Exp(1 + s'^2); s_0 is the first Gaussian."""
+    return dict(n_chains=n_chains, steps=steps)
+
+
+def gamma_chain(n_chains: int = 262144, lmin: int = 50, lmax: int = 1000,
+                seed: int = WORKLOAD_SEED):
+    """Uneven lengths L ~ U{lmin..lmax}; alpha_0 = 0.1 * 1000^w, w ~ U(0,1)
+    (log-uniform on [0.1, 100]), rounded to fp32."""
+    r = _rng(seed, 3)
+    steps = r.integers(lmin, lmax + 1, size=n_chains, dtype=np.int64).astype(np.int32)
+    w = r.random(n_chains)
+    alpha0 = (0.1 * np.power(1000.0, w)).astype(np.float32)
+    return dict(n_chains=n_chains, steps=steps, alpha0=alpha0)
+
+
+def lda(n_docs: int = 16384, sweeps: int = 100, mean_len: float = 200.0,
+        ks=(8, 16, 64, 256), seed: int = WORKLOAD_SEED):
+    """Documents with n_d ~ Poisson(mean_len) tokens and K_d drawn uniformly
+    from `ks`; counts start at 0."""
+    r = _rng(seed, 4)
+    K = r.choice(np.asarray(ks, dtype=np.int64), size=n_docs).astype(np.int32)
+    ntok = r.poisson(mean_len, size=n_docs).astype(np.int32)
+    offsets = np.zeros(n_docs + 1, dtype=np.int32)
+    offsets[1:] = np.cumsum(K)
+    return dict(n_docs=n_docs, sweeps=sweeps, K=K, ntok=ntok, offsets=offsets)
+
+
+def step_params(n: int, seed: int = WORKLOAD_SEED):
+    """Per-chain parameters for one-at-a-time calls: U(a,b), N(mu,sigma),
+    Exp(lambda), Gamma(alpha) with alpha log-uniform on [0.05, 5000]."""
+    r = _rng(seed, 7)
+    a = r.normal(0.0, 3.0, n).astype(np.float32)
+    b = (a + r.exponential(2.0, n) + 1e-3).astype(np.float32)
+    mu = r.normal(0.0, 5.0, n).astype(np.float32)
+    sigma = r.exponential(1.0, n).astype(np.float32) + np.float32(1e-3)
+    lam = np.exp(r.uniform(np.log(1e-3), np.log(1e3), n)).astype(np.float32)
+    alpha = np.exp(r.uniform(np.log(0.05), np.log(5000.0), n)).astype(np.float32)
+    return dict(a=a, b=b, mu=mu, sigma=sigma, lam=lam, alpha=alpha)
+
+
+def dirichlet_items(n_items: int, kmin: int = 1, kmax: int = 300, seed: int = WORKLOAD_SEED):
+    """Ragged Dirichlet items: K_i ~ U{kmin..kmax}, alpha log-uniform on
+    [0.05, 50]."""
+    r = _rng(seed, 8)
+    K = r.integers(kmin, kmax + 1, size=n_items).astype(np.int32)
+    offsets = np.zeros(n_items + 1, dtype=np.int32)
+    offsets[1:] = np.cumsum(K)
+    alpha = np.exp(r.uniform(np.log(0.05), np.log(50.0), int(offsets[-1]))).astype(np.float32)
+    return dict(offsets=offsets, alpha=alpha, K=K)
