@@ -1,0 +1,222 @@
+/*
+ * brng.h: C interface of the MI355X (gfx950) varying-parameter random number
+ * library built on the buffering idea of Mahani & Sharabiani, "Efficient SIMD
+ * RNG for Varying-Parameter Streams: C++ Class BatchRNG" (arXiv 1412.4825).
+ *
+ * The method (Sec. 2.1, Key Concepts): keep pools of standard uniform,
+ * Gaussian and exponential deviates that a vector engine fills in bulk, and
+ * serve samplers whose parameters change at every call (the one-at-a-time
+ * scenario of Sec. 1) from those pools through a cheap transform.  Here the
+ * engine is Philox4x32-10 on the GPU, a pool "unit" is 64 consecutive chains
+ * (one gfx950 wavefront) or one item (a Dirichlet vector / document), and
+ * thousands of chains consume their unit's pools in parallel.
+ *
+ * Stream contract (fixed; results never depend on window length, launch
+ * shape, graph capture or tuning):
+ *   Philox key = (unit id, seed low 32), counter = (block low 32,
+ *   block high 32, kind, seed high 32).  Entry j of kind U/N/E is word j%4 of
+ *   block j/4 (N: Box-Muller on words (0,1) and (2,3), cosine on the even
+ *   entry); entry j of U64 uses words 2(j%2), 2(j%2)+1 of block j/2.
+ *   U = (2(w>>9)+1) 2^-24, U64 = (2k+1) 2^-53 with k = (wa<<20)|(wb>>12),
+ *   E = -ln U, N = sqrt(-2 ln Ua) cos/sin(2 pi Ub).
+ *   A call gives one entry of a kind to every active slot of a unit, in
+ *   ascending slot order; the unit's cursor for that kind counts entries
+ *   consumed (the paper's buffer_counter, Sec. 2.2).
+ *
+ * Conventions for every function:
+ *   - Return value: brng_status, 0 on success.  Argument errors are
+ *     reported synchronously and launch nothing.  BRNG_E_HIP reports a HIP
+ *     runtime failure; brng_last_hip_error() gives its hipError_t code.
+ *   - Pointers named d_* are device pointers owned by the caller; they must
+ *     stay valid until the context's stream has passed the call.  Pointers
+ *     named h_* are host pointers.  Context-owned memory (pools, cursors)
+ *     is allocated by brng_create and freed by brng_destroy only.
+ *   - All device work is asynchronous on the context's stream (default
+ *     stream when NULL).  A context is not thread safe; distinct contexts
+ *     are independent.
+ *   - Arrays are contiguous.  Precision: see brng_config.prec.
+ */
+#ifndef BRNG_H
+#define BRNG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t brng_status;
+enum {
+    BRNG_OK = 0,
+    BRNG_E_ARG = 1,           /* invalid argument (null, size, range) */
+    BRNG_E_NOMEM = 2,         /* device allocation failed */
+    BRNG_E_HIP = 3,           /* HIP runtime error */
+    BRNG_E_KIND_DISABLED = 4, /* call needs a pool whose window length is 0 */
+    BRNG_E_BUSY = 5,          /* served form: no slot or memory available */
+    BRNG_E_UNSUPPORTED = 6    /* combination not provided (e.g. fp64 gamma) */
+};
+
+/* Pool kinds (Sec. 2.1: reducible base distributions). */
+enum { BRNG_U = 0, BRNG_N = 1, BRNG_E = 2, BRNG_U64 = 3, BRNG_NKINDS = 4 };
+/* Precision of step-call parameter and output arrays. */
+enum { BRNG_F32 = 0, BRNG_F64 = 1 };
+/* What a pool unit is: 64 consecutive chains, or one item. */
+enum { BRNG_LAYOUT_CHAINS = 0, BRNG_LAYOUT_ITEMS = 1 };
+
+#define BRNG_UNIT_WIDTH 64      /* chains per unit (one wavefront) */
+#define BRNG_WINDOW_ALIGN 256   /* window lengths are multiples of this */
+#define BRNG_WINDOW_MIN 512     /* smallest non-zero window */
+
+typedef struct {
+    uint64_t seed;
+    uint32_t n_chains;   /* chains (LAYOUT_CHAINS) or items (LAYOUT_ITEMS) */
+    uint32_t layout;     /* BRNG_LAYOUT_* */
+    uint32_t window[4];  /* pool window per unit per kind, in entries: 0
+                            disables the kind (Sec. 2.4 zero-length buffers),
+                            else a multiple of 256, at least 512 */
+    int32_t prec;        /* BRNG_F32 or BRNG_F64 (F64: uniform steps only,
+                            from the U64 pool) */
+    void *hip_stream;    /* hipStream_t, or NULL for the default stream */
+} brng_config;
+
+typedef struct brng_ctx brng_ctx;
+
+/* Constructor (Sec. 2.2): allocate one window per unit per enabled kind,
+ * set every cursor to 0 and fill every window with its first entries.
+ * Units are ceil(n_chains/64) (chains) or n_chains (items).  Unit u's
+ * stream is keyed by (u, seed).  Errors: BRNG_E_ARG, BRNG_E_NOMEM,
+ * BRNG_E_HIP; *out is NULL on error. */
+brng_status brng_create(const brng_config *cfg, brng_ctx **out);
+
+/* Destructor (Sec. 2.2): wait for the stream, free everything.  NULL is a
+ * no-op. */
+brng_status brng_destroy(brng_ctx *ctx);
+
+/* Bulk refill (the paper's batch call of the core engine, Sec. 1 and 2.2):
+ * regenerate every unit's window of `kind` starting at its cursor rounded
+ * down to 256 (128 for U64) entries, with coalesced 128-bit stores.
+ * Errors: BRNG_E_ARG (kind), BRNG_E_KIND_DISABLED, BRNG_E_HIP. */
+brng_status brng_fill_base(brng_ctx *ctx, int32_t kind);
+
+/* One-at-a-time calls (Sec. 1; reducible transforms of Sec. 2.1): one draw
+ * per chain, parameters per chain.  Layout CHAINS.  Windows that run out
+ * are refilled inside the kernel.  Arrays hold n_chains elements of the
+ * context precision.
+ *   uniform: out = a + (b - a) u      (U pool; U64 pool when prec = F64)
+ *   normal : out = mu + sigma z       (N pool; sigma is a standard deviation)
+ *   exp    : out = E / lambda         (E pool; lambda is the rate)
+ *   gamma  : out ~ Gamma(alpha, 1)    (Marsaglia-Tsang on N and E pools,
+ *                                      alpha < 1 boosted by exp(-E'/alpha);
+ *                                      alpha > 0 required, F32 only)
+ * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_UNSUPPORTED, BRNG_E_HIP. */
+brng_status brng_step_uniform(brng_ctx *ctx, const void *d_a, const void *d_b, void *d_out);
+brng_status brng_step_normal(brng_ctx *ctx, const void *d_mu, const void *d_sigma, void *d_out);
+brng_status brng_step_exp(brng_ctx *ctx, const void *d_lambda, void *d_out);
+brng_status brng_step_gamma(brng_ctx *ctx, const float *d_alpha, float *d_out);
+
+/* Dirichlet by normalised gammas (Sec. 1, footnote on Dirichlet): layout
+ * ITEMS, item i has components [d_offsets[i], d_offsets[i+1]) of d_alpha and
+ * d_out (F32).  Components are drawn in batches of 64, one gamma call per
+ * batch.  n_items = n_chains of the context; d_offsets has n_items + 1
+ * entries, starting at 0, each item 1..4096 components. */
+brng_status brng_step_dirichlet(brng_ctx *ctx, const int32_t *d_offsets,
+                                const float *d_alpha, float *d_out);
+
+/* ---------------------------------------------------------------------- */
+/* Chain drivers (Fig. 1 generalised): many independent Gibbs chains, state */
+/* in registers, one kernel for all steps.                                */
+/* ---------------------------------------------------------------------- */
+enum {
+    BRNG_MODEL_TRIANGLE_F64 = 0, /* Eq. 1 / Fig. 1: x~U(0,1-y), y~U(0,1-x), fp64 */
+    BRNG_MODEL_NORMEXP = 1,      /* s'~N(0.9 s, 0.5+|s|), e~Exp(1+s'^2), fp32 */
+    BRNG_MODEL_GAMMA_CHAIN = 2,  /* g~Gamma(alpha,1), alpha' = 0.1 + g, fp32 */
+    BRNG_MODEL_LDA = 3,          /* theta~Dir(0.1+counts), counts~Mult(n,theta) */
+    BRNG_MODEL_EXP_CHAIN = 4,    /* e' ~ Exp(1 + e^2), fp32 */
+    BRNG_NMODELS = 5
+};
+enum {
+    BRNG_FLAG_RESUME = 1u /* continue from the units' cursors and d_state;
+                             otherwise start fresh: cursors 0, windows
+                             regenerated, model's initial state */
+};
+
+typedef struct {
+    int32_t model;         /* BRNG_MODEL_* */
+    uint32_t n_chains;     /* chains, or documents for LDA */
+    uint32_t unit_base;    /* first context unit used; units are request-local
+                              ids 0..n_units-1 for the Philox key */
+    uint32_t flags;        /* BRNG_FLAG_* */
+    uint64_t seed;         /* stream seed of this request */
+    int32_t max_steps;     /* steps (sweeps for LDA) when d_steps is NULL */
+    int32_t pad0;
+    const int32_t *d_steps; /* per-chain steps (user order) or NULL */
+    const int32_t *d_perm;  /* slot -> chain, or NULL for identity; see
+                               brng_sort_by_length */
+    void *d_state;          /* model state, user order, in/out:
+                               TRIANGLE: double[2][n] (x then y)
+                               NORMEXP : float[n] (s)
+                               GAMMA   : float[n] (next shape alpha; alpha_0
+                                         on a fresh start, must be > 0)
+                               EXP     : float[n] (e; fresh: first E draw)
+                               LDA     : int32 counts[total components] */
+    void *d_trace;          /* [step][slot] first output, or NULL:
+                               TRIANGLE x, NORMEXP s', GAMMA g, EXP e',
+                               LDA theta ([sweep][component], float) */
+    void *d_trace2;         /* second output, or NULL: TRIANGLE y, NORMEXP e,
+                               LDA counts ([sweep][component], int32) */
+    int64_t trace_stride;   /* elements between steps (>= n_chains; LDA: >=
+                               total components) */
+    const int32_t *d_offsets; /* LDA: n_docs + 1 component offsets */
+    const int32_t *d_ntok;    /* LDA: tokens per document */
+} brng_gibbs_desc;
+
+/* Run chains to completion on the context's stream.  n_desc = 1 is the
+ * plain form (one launch of the model's kernel).  n_desc > 1 is the batched
+ * form: all requests' units go into one persistent kernel that pulls units
+ * from a device queue, longest first, whatever their model.  Each request's
+ * units [unit_base, unit_base + n_units) must lie inside the context and
+ * must not overlap another request's.  Layout CHAINS contexts serve the
+ * chain models, ITEMS contexts serve LDA.  The needed kinds must be enabled:
+ * TRIANGLE U64; NORMEXP N,E; GAMMA N,E; EXP E; LDA U,N,E.
+ * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_HIP. */
+brng_status brng_run_gibbs(brng_ctx *ctx, const brng_gibbs_desc *h_descs, uint32_t n_desc);
+
+/* Slot order for uneven chain lengths: perm[p] = chain in slot p, chains
+ * stably sorted by descending steps (so a unit's lanes finish together).
+ * Host arrays of n entries.  Errors: BRNG_E_ARG. */
+brng_status brng_sort_by_length(uint32_t n, const int32_t *h_steps, int32_t *h_perm);
+
+/* Copy the cursors to the host as uint64[n_units][4] (waits for the
+ * stream).  Errors: BRNG_E_ARG, BRNG_E_HIP. */
+brng_status brng_get_cursors(brng_ctx *ctx, uint64_t *h_out);
+
+/* Restore cursors (checkpoint/resume): uint64[n_units][4]; invalidates the
+ * windows, which the next call regenerates from the cursors.  Units keep
+ * their stream keys.  Errors: BRNG_E_ARG, BRNG_E_HIP. */
+brng_status brng_set_cursors(brng_ctx *ctx, const uint64_t *h_in);
+
+/* Copy unit `unit`'s current window of `kind` to the host: *h_base gets the
+ * pool index of its first entry, *h_len its valid length (0 if empty), and
+ * h_out up to cap entries (float, or double for U64).  Waits for the
+ * stream.  Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_HIP. */
+brng_status brng_get_window(brng_ctx *ctx, int32_t kind, uint32_t unit, void *h_out,
+                            uint32_t cap, uint64_t *h_base, uint32_t *h_len);
+
+/* Context facts: number of units, window lengths. */
+brng_status brng_get_info(const brng_ctx *ctx, uint32_t *n_units, uint32_t *window4);
+
+/* Launch shape of the chain kernels (the autotuner's knobs; results do not
+ * depend on them): waves per workgroup (1, 2, 4 or 8) and the number of
+ * workgroups of the persistent batched kernel (0 = one per unit).
+ * Errors: BRNG_E_ARG. */
+brng_status brng_set_launch(brng_ctx *ctx, int32_t waves_per_block, int32_t persistent_blocks);
+
+/* Human-readable status. Never NULL. */
+const char *brng_status_string(brng_status s);
+/* hipError_t of the last BRNG_E_HIP in this thread (0 if none). */
+int32_t brng_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BRNG_H */

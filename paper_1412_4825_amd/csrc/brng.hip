@@ -1,0 +1,747 @@
+// brng: kernels and the C interface declared in include/brng.h.
+//
+// Kernels (gfx950, wave64, no matrix cores: nothing here is a contraction):
+//   k_fill<K>        bulk refill of every unit's window (Sec. 1 batch call /
+//                    Sec. 2.2 constructor fill): one Philox block per lane,
+//                    one 128-bit store per block, coalesced per wave
+//   k_step_*         one draw per chain per launch (the one-at-a-time call
+//                    of Sec. 1 with the reducible transforms of Sec. 2.1)
+//   k_gibbs<M>       all steps of every chain of one request (plain form)
+//   k_batch          many requests of any model in one persistent launch,
+//                    units pulled from a device queue (batched form)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/brng.h"
+#include "models.hpp"
+
+using namespace brng;
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_init_meta(Meta* meta, uint32_t n_units, uint64_t seed) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_units) return;
+    Meta m;
+    for (int k = 0; k < 4; ++k) {
+        m.cur[k] = 0;
+        m.wbase[k] = 0;
+        m.wlen[k] = 0;
+    }
+    m.key_unit = i;
+    m.pad = 0;
+    m.key_seed = seed;
+    meta[i] = m;
+}
+
+// Cursors from a device array [unit][4]; windows become empty.
+__global__ void k_set_cursors(Meta* meta, uint32_t n_units, const uint64_t* cur) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_units) return;
+    for (int k = 0; k < 4; ++k) {
+        meta[i].cur[k] = cur[4 * (size_t)i + k];
+        meta[i].wbase[k] = 0;
+        meta[i].wlen[k] = 0;
+    }
+}
+
+__global__ void k_get_cursors(const Meta* meta, uint32_t n_units, uint64_t* cur) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_units) return;
+    for (int k = 0; k < 4; ++k) cur[4 * (size_t)i + k] = meta[i].cur[k];
+}
+
+constexpr int FILL_THREADS = 256;
+constexpr int FILL_BPT = 4;  // blocks per thread
+
+// Grid (x: window slices of FILL_THREADS * FILL_BPT blocks, y: unit).  The
+// window starts at the unit's cursor rounded down to 64 blocks.
+template <uint32_t KIND>
+__global__ __launch_bounds__(FILL_THREADS) void k_fill(Meta* meta,
+                                                       typename KindTraits<KIND>::T* pool,
+                                                       uint32_t W) {
+    constexpr int EPB = KindTraits<KIND>::EPB;
+    const uint32_t unit = blockIdx.y;
+    Meta* mp = meta + unit;
+    const uint64_t cur = mp->cur[KIND];
+    const uint64_t first = cur & ~(uint64_t)(64 * EPB - 1);
+    const Key key = meta_key(*mp);
+    const uint32_t nblk = W / EPB;
+    uint4* dst = reinterpret_cast<uint4*>(pool + (size_t)unit * W);
+    const uint64_t b0 = first / EPB;
+    const uint32_t base = blockIdx.x * (FILL_THREADS * FILL_BPT) + threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < FILL_BPT; ++i) {
+        const uint32_t b = base + i * FILL_THREADS;
+        if (b < nblk) dst[b] = gen_block<KIND>(key, b0 + b);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        mp->wbase[KIND] = first;
+        mp->wlen[KIND] = W;
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_in_block() {
+    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// One-at-a-time calls: one wave per unit of 64 chains.
+template <uint32_t KIND, typename T>
+__global__ __launch_bounds__(512) void k_step_uniform(Meta* meta, T* pool, uint32_t W,
+                                                      uint32_t n, const T* a, const T* b,
+                                                      T* out) {
+    const uint32_t unit = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (unit * 64 >= n) return;
+    const uint32_t c = unit * 64 + lane_id();
+    const bool act = c < n;
+    DirectReader<KIND> r;
+    r.open(meta[unit], pool + (size_t)unit * W, W);
+    const T u = r.take(act);
+    if (act) {
+        const T lo = a[c];
+        out[c] = lo + (b[c] - lo) * u;
+    }
+    r.close(meta[unit]);
+}
+
+__global__ __launch_bounds__(512) void k_step_normal(Meta* meta, float* pool, uint32_t W,
+                                                     uint32_t n, const float* mu,
+                                                     const float* sigma, float* out) {
+    const uint32_t unit = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (unit * 64 >= n) return;
+    const uint32_t c = unit * 64 + lane_id();
+    const bool act = c < n;
+    DirectReader<KIND_N> r;
+    r.open(meta[unit], pool + (size_t)unit * W, W);
+    const float z = r.take(act);
+    if (act) out[c] = fmaf(sigma[c], z, mu[c]);
+    r.close(meta[unit]);
+}
+
+__global__ __launch_bounds__(512) void k_step_exp(Meta* meta, float* pool, uint32_t W, uint32_t n,
+                                                  const float* lam, float* out) {
+    const uint32_t unit = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (unit * 64 >= n) return;
+    const uint32_t c = unit * 64 + lane_id();
+    const bool act = c < n;
+    DirectReader<KIND_E> r;
+    r.open(meta[unit], pool + (size_t)unit * W, W);
+    const float e = r.take(act);
+    if (act) out[c] = e / lam[c];
+    r.close(meta[unit]);
+}
+
+__global__ __launch_bounds__(512) void k_step_gamma(Meta* meta, Pools P, uint32_t n,
+                                                    const float* alpha, float* out) {
+    const uint32_t unit = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (unit * 64 >= n) return;
+    const uint32_t c = unit * 64 + lane_id();
+    const bool act = c < n;
+    DirectReader<KIND_N> rn;
+    DirectReader<KIND_E> re;
+    rn.open(meta[unit], P.n + (size_t)unit * P.W[KIND_N], P.W[KIND_N]);
+    re.open(meta[unit], P.e + (size_t)unit * P.W[KIND_E], P.W[KIND_E]);
+    const float g = gamma_call(rn, re, act, act ? alpha[c] : 1.0f);
+    if (act) out[c] = g;
+    rn.close(meta[unit]);
+    re.close(meta[unit]);
+}
+
+// Dirichlet: one wave per item, any K (gammas go to `out`, then are scaled
+// by the sum, which is accumulated in the same order as in the LDA model).
+__global__ __launch_bounds__(512) void k_step_dirichlet(Meta* meta, Pools P, uint32_t n_items,
+                                                        const int32_t* offsets,
+                                                        const float* alpha, float* out) {
+    const uint32_t item = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (item >= n_items) return;
+    const uint32_t lane = lane_id();
+    const int32_t off = offsets[item];
+    const int K = offsets[item + 1] - off;
+    if (K < 1) return;
+    DirectReader<KIND_N> rn;
+    DirectReader<KIND_E> re;
+    rn.open(meta[item], P.n + (size_t)item * P.W[KIND_N], P.W[KIND_N]);
+    re.open(meta[item], P.e + (size_t)item * P.W[KIND_E], P.W[KIND_E]);
+    float part = 0.0f;
+    for (int b0 = 0; b0 < K; b0 += 64) {
+        const int k = b0 + (int)lane;
+        const bool act = k < K;
+        const float y = gamma_call(rn, re, act, act ? alpha[off + k] : 1.0f);
+        if (act) {
+            out[off + k] = y;
+            part += y;
+        }
+    }
+    const float S = wave_sum(part);
+    for (int b0 = 0; b0 < K; b0 += 64) {
+        const int k = b0 + (int)lane;
+        if (k < K) out[off + k] = S > 0.0f ? out[off + k] / S : 0.0f;
+    }
+    rn.close(meta[item]);
+    re.close(meta[item]);
+}
+
+template <int MODEL>
+__device__ __forceinline__ void run_unit(const DescDev& D, Meta* meta, const Pools& P,
+                                         uint32_t local, unsigned char* lds) {
+    Meta* mp = meta + D.unit_base + local;
+    if constexpr (MODEL == M_TRIANGLE) unit_triangle(D, mp, P, local, lds);
+    if constexpr (MODEL == M_NORMEXP) unit_normexp(D, mp, P, local, lds);
+    if constexpr (MODEL == M_GAMMA) unit_gamma(D, mp, P, local, lds);
+    if constexpr (MODEL == M_LDA) unit_lda(D, mp, P, local, lds);
+    if constexpr (MODEL == M_EXPCHAIN) unit_expchain(D, mp, P, local, lds);
+}
+
+__host__ __device__ constexpr int model_lds_bytes(int model) {
+    return model == M_LDA ? WAVE_LDS_BYTES
+                          : ((model == M_TRIANGLE || model == M_EXPCHAIN) ? RING_BYTES
+                                                                         : 2 * RING_BYTES);
+}
+
+// Documents the LDA kernel cannot serve are skipped: K outside [1, 256],
+// negative token counts, or traces too narrow for their components.
+__device__ __forceinline__ bool lda_doc_ok(const DescDev& D, uint32_t doc) {
+    const int32_t off = D.offsets[doc];
+    const int K = D.offsets[doc + 1] - off;
+    const bool fits = (!D.trace && !D.trace2) || (off >= 0 && (int64_t)off + K <= D.stride);
+    return K >= 1 && K <= LDA_KMAX && D.ntok[doc] >= 0 && fits;
+}
+
+// Plain form: one launch per request, one wave per unit.
+template <int MODEL>
+__global__ __launch_bounds__(512) void k_gibbs(DescDev D, Meta* meta, Pools P) {
+    extern __shared__ __align__(16) unsigned char lds_all[];
+    const uint32_t w = wave_in_block();
+    const uint32_t local = blockIdx.x * (blockDim.x >> 6) + w;
+    if (local >= D.n_units) return;
+    if (MODEL == M_LDA && !lda_doc_ok(D, local)) return;
+    run_unit<MODEL>(D, meta, P, local, lds_all + w * model_lds_bytes(MODEL));
+}
+
+// Batched form: a persistent grid; each wave takes the next queue index,
+// finds its request (requests are ordered longest first) and runs that unit.
+__global__ __launch_bounds__(512) void k_batch(const DescDev* descs, uint32_t n_desc,
+                                               uint32_t n_total, uint32_t* queue, Meta* meta,
+                                               Pools P) {
+    extern __shared__ __align__(16) unsigned char lds_all[];
+    const uint32_t w = wave_in_block();
+    unsigned char* lds = lds_all + w * WAVE_LDS_BYTES;
+    for (;;) {
+        uint32_t idx = 0;
+        if (lane_id() == 0) idx = atomicAdd(queue, 1u);
+        idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
+        if (idx >= n_total) break;
+        uint32_t lo = 0, hi = n_desc - 1;  // last request with queue_first <= idx
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (descs[mid].queue_first <= idx)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const DescDev D = descs[lo];
+        const uint32_t local = idx - D.queue_first;
+        switch (D.model) {
+            case M_TRIANGLE: run_unit<M_TRIANGLE>(D, meta, P, local, lds); break;
+            case M_NORMEXP: run_unit<M_NORMEXP>(D, meta, P, local, lds); break;
+            case M_GAMMA: run_unit<M_GAMMA>(D, meta, P, local, lds); break;
+            case M_LDA:
+                if (lda_doc_ok(D, local)) run_unit<M_LDA>(D, meta, P, local, lds);
+                break;
+            case M_EXPCHAIN: run_unit<M_EXPCHAIN>(D, meta, P, local, lds); break;
+            default: break;
+        }
+    }
+}
+
+// Queue reset as a kernel node (graph-safe, unlike a memset node).
+__global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+struct brng_ctx {
+    brng_config cfg;
+    hipStream_t stream;
+    uint32_t n_units;
+    void* pool[4];
+    Meta* meta;
+    uint32_t* queue;
+    DescDev* d_descs;
+    DescDev* h_descs;  // pinned staging for descriptor uploads
+    uint32_t desc_cap;
+    hipEvent_t desc_done;
+    bool desc_pending;
+    int wpb;
+    int persistent_blocks;
+    int n_cu;
+};
+
+static thread_local int32_t g_last_hip = 0;
+
+static brng_status hip_fail(hipError_t e) {
+    g_last_hip = (int32_t)e;
+    return BRNG_E_HIP;
+}
+
+#define HIPCHK(x)                                     \
+    do {                                              \
+        hipError_t e_ = (x);                          \
+        if (e_ != hipSuccess) return hip_fail(e_);    \
+    } while (0)
+
+static size_t kind_elem(int k) { return k == BRNG_U64 ? sizeof(double) : sizeof(float); }
+
+static bool window_ok(uint32_t W) {
+    return W == 0 || (W % BRNG_WINDOW_ALIGN == 0 && W >= BRNG_WINDOW_MIN);
+}
+
+static Pools make_pools(const brng_ctx* c) {
+    Pools p;
+    p.u = (float*)c->pool[BRNG_U];
+    p.n = (float*)c->pool[BRNG_N];
+    p.e = (float*)c->pool[BRNG_E];
+    p.u64 = (double*)c->pool[BRNG_U64];
+    for (int k = 0; k < 4; ++k) p.W[k] = c->cfg.window[k];
+    return p;
+}
+
+static brng_status launch_fill(brng_ctx* c, int kind) {
+    const uint32_t W = c->cfg.window[kind];
+    const uint32_t epb = kind == BRNG_U64 ? 2 : 4;
+    const uint32_t nblk = W / epb;
+    dim3 grid((nblk + FILL_THREADS * FILL_BPT - 1) / (FILL_THREADS * FILL_BPT), c->n_units);
+    switch (kind) {
+        case BRNG_U:
+            hipLaunchKernelGGL(k_fill<KIND_U>, grid, dim3(FILL_THREADS), 0, c->stream, c->meta,
+                               (float*)c->pool[kind], W);
+            break;
+        case BRNG_N:
+            hipLaunchKernelGGL(k_fill<KIND_N>, grid, dim3(FILL_THREADS), 0, c->stream, c->meta,
+                               (float*)c->pool[kind], W);
+            break;
+        case BRNG_E:
+            hipLaunchKernelGGL(k_fill<KIND_E>, grid, dim3(FILL_THREADS), 0, c->stream, c->meta,
+                               (float*)c->pool[kind], W);
+            break;
+        default:
+            hipLaunchKernelGGL(k_fill<KIND_U64>, grid, dim3(FILL_THREADS), 0, c->stream, c->meta,
+                               (double*)c->pool[kind], W);
+            break;
+    }
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
+static void free_ctx(brng_ctx* c) {
+    if (!c) return;
+    for (int k = 0; k < 4; ++k)
+        if (c->pool[k]) (void)hipFree(c->pool[k]);
+    if (c->meta) (void)hipFree(c->meta);
+    if (c->queue) (void)hipFree(c->queue);
+    if (c->d_descs) (void)hipFree(c->d_descs);
+    if (c->h_descs) (void)hipHostFree(c->h_descs);
+    if (c->desc_done) (void)hipEventDestroy(c->desc_done);
+    delete c;
+}
+
+extern "C" {
+
+const char* brng_status_string(brng_status s) {
+    switch (s) {
+        case BRNG_OK: return "ok";
+        case BRNG_E_ARG: return "invalid argument";
+        case BRNG_E_NOMEM: return "device allocation failed";
+        case BRNG_E_HIP: return "HIP runtime error";
+        case BRNG_E_KIND_DISABLED: return "pool kind disabled (window length 0)";
+        case BRNG_E_BUSY: return "no capacity available";
+        case BRNG_E_UNSUPPORTED: return "unsupported combination";
+        default: return "unknown status";
+    }
+}
+
+int32_t brng_last_hip_error(void) { return g_last_hip; }
+
+brng_status brng_create(const brng_config* cfg, brng_ctx** out) {
+    if (!out) return BRNG_E_ARG;
+    *out = nullptr;
+    if (!cfg || cfg->n_chains == 0) return BRNG_E_ARG;
+    if (cfg->layout != BRNG_LAYOUT_CHAINS && cfg->layout != BRNG_LAYOUT_ITEMS) return BRNG_E_ARG;
+    if (cfg->prec != BRNG_F32 && cfg->prec != BRNG_F64) return BRNG_E_ARG;
+    for (int k = 0; k < 4; ++k)
+        if (!window_ok(cfg->window[k])) return BRNG_E_ARG;
+    brng_ctx* c = new (std::nothrow) brng_ctx();
+    if (!c) return BRNG_E_NOMEM;
+    c->cfg = *cfg;
+    c->stream = (hipStream_t)cfg->hip_stream;
+    c->n_units = cfg->layout == BRNG_LAYOUT_CHAINS ? (cfg->n_chains + 63) / 64 : cfg->n_chains;
+    c->wpb = 4;
+    c->persistent_blocks = 0;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) {
+        free_ctx(c);
+        return hip_fail(e);
+    }
+    for (int k = 0; k < 4; ++k) {
+        if (!cfg->window[k]) continue;
+        const size_t bytes = (size_t)c->n_units * cfg->window[k] * kind_elem(k);
+        if (hipMalloc(&c->pool[k], bytes) != hipSuccess) {
+            free_ctx(c);
+            return BRNG_E_NOMEM;
+        }
+    }
+    if (hipMalloc((void**)&c->meta, sizeof(Meta) * (size_t)c->n_units) != hipSuccess ||
+        hipMalloc((void**)&c->queue, sizeof(uint32_t)) != hipSuccess) {
+        free_ctx(c);
+        return BRNG_E_NOMEM;
+    }
+    e = hipEventCreateWithFlags(&c->desc_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        free_ctx(c);
+        return hip_fail(e);
+    }
+    hipLaunchKernelGGL(k_init_meta, dim3((c->n_units + 255) / 256), dim3(256), 0, c->stream,
+                       c->meta, c->n_units, cfg->seed);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        free_ctx(c);
+        return hip_fail(e);
+    }
+    for (int k = 0; k < 4; ++k) {
+        if (!cfg->window[k]) continue;
+        brng_status s = launch_fill(c, k);
+        if (s != BRNG_OK) {
+            free_ctx(c);
+            return s;
+        }
+    }
+    *out = c;
+    return BRNG_OK;
+}
+
+brng_status brng_destroy(brng_ctx* c) {
+    if (!c) return BRNG_OK;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    free_ctx(c);
+    if (e != hipSuccess) return hip_fail(e);
+    return BRNG_OK;
+}
+
+brng_status brng_fill_base(brng_ctx* c, int32_t kind) {
+    if (!c || kind < 0 || kind >= BRNG_NKINDS) return BRNG_E_ARG;
+    if (!c->cfg.window[kind]) return BRNG_E_KIND_DISABLED;
+    return launch_fill(c, kind);
+}
+
+static dim3 unit_grid(const brng_ctx* c, uint32_t n_units) {
+    return dim3((n_units + c->wpb - 1) / c->wpb);
+}
+
+brng_status brng_step_uniform(brng_ctx* c, const void* a, const void* b, void* out) {
+    if (!c || !a || !b || !out) return BRNG_E_ARG;
+    if (c->cfg.layout != BRNG_LAYOUT_CHAINS) return BRNG_E_ARG;
+    const int kind = c->cfg.prec == BRNG_F64 ? BRNG_U64 : BRNG_U;
+    if (!c->cfg.window[kind]) return BRNG_E_KIND_DISABLED;
+    const uint32_t n = c->cfg.n_chains, W = c->cfg.window[kind];
+    if (kind == BRNG_U64)
+        hipLaunchKernelGGL((k_step_uniform<KIND_U64, double>), unit_grid(c, c->n_units),
+                           dim3(64 * c->wpb), 0, c->stream, c->meta, (double*)c->pool[kind], W, n,
+                           (const double*)a, (const double*)b, (double*)out);
+    else
+        hipLaunchKernelGGL((k_step_uniform<KIND_U, float>), unit_grid(c, c->n_units),
+                           dim3(64 * c->wpb), 0, c->stream, c->meta, (float*)c->pool[kind], W, n,
+                           (const float*)a, (const float*)b, (float*)out);
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
+brng_status brng_step_normal(brng_ctx* c, const void* mu, const void* sigma, void* out) {
+    if (!c || !mu || !sigma || !out) return BRNG_E_ARG;
+    if (c->cfg.layout != BRNG_LAYOUT_CHAINS) return BRNG_E_ARG;
+    if (c->cfg.prec != BRNG_F32) return BRNG_E_UNSUPPORTED;
+    if (!c->cfg.window[BRNG_N]) return BRNG_E_KIND_DISABLED;
+    hipLaunchKernelGGL(k_step_normal, unit_grid(c, c->n_units), dim3(64 * c->wpb), 0, c->stream,
+                       c->meta, (float*)c->pool[BRNG_N], c->cfg.window[BRNG_N], c->cfg.n_chains,
+                       (const float*)mu, (const float*)sigma, (float*)out);
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
+brng_status brng_step_exp(brng_ctx* c, const void* lam, void* out) {
+    if (!c || !lam || !out) return BRNG_E_ARG;
+    if (c->cfg.layout != BRNG_LAYOUT_CHAINS) return BRNG_E_ARG;
+    if (c->cfg.prec != BRNG_F32) return BRNG_E_UNSUPPORTED;
+    if (!c->cfg.window[BRNG_E]) return BRNG_E_KIND_DISABLED;
+    hipLaunchKernelGGL(k_step_exp, unit_grid(c, c->n_units), dim3(64 * c->wpb), 0, c->stream,
+                       c->meta, (float*)c->pool[BRNG_E], c->cfg.window[BRNG_E], c->cfg.n_chains,
+                       (const float*)lam, (float*)out);
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
+brng_status brng_step_gamma(brng_ctx* c, const float* alpha, float* out) {
+    if (!c || !alpha || !out) return BRNG_E_ARG;
+    if (c->cfg.layout != BRNG_LAYOUT_CHAINS) return BRNG_E_ARG;
+    if (c->cfg.prec != BRNG_F32) return BRNG_E_UNSUPPORTED;
+    if (!c->cfg.window[BRNG_N] || !c->cfg.window[BRNG_E]) return BRNG_E_KIND_DISABLED;
+    hipLaunchKernelGGL(k_step_gamma, unit_grid(c, c->n_units), dim3(64 * c->wpb), 0, c->stream,
+                       c->meta, make_pools(c), c->cfg.n_chains, alpha, out);
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
+brng_status brng_step_dirichlet(brng_ctx* c, const int32_t* offsets, const float* alpha,
+                                float* out) {
+    if (!c || !offsets || !alpha || !out) return BRNG_E_ARG;
+    if (c->cfg.layout != BRNG_LAYOUT_ITEMS) return BRNG_E_ARG;
+    if (c->cfg.prec != BRNG_F32) return BRNG_E_UNSUPPORTED;
+    if (!c->cfg.window[BRNG_N] || !c->cfg.window[BRNG_E]) return BRNG_E_KIND_DISABLED;
+    hipLaunchKernelGGL(k_step_dirichlet, unit_grid(c, c->n_units), dim3(64 * c->wpb), 0,
+                       c->stream, c->meta, make_pools(c), c->n_units, offsets, alpha, out);
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
+static uint32_t desc_units(const brng_gibbs_desc& d) {
+    return d.model == BRNG_MODEL_LDA ? d.n_chains : (d.n_chains + 63) / 64;
+}
+
+static brng_status check_desc(const brng_ctx* c, const brng_gibbs_desc& d) {
+    if (d.model < 0 || d.model >= BRNG_NMODELS) return BRNG_E_ARG;
+    if (d.n_chains == 0 || d.max_steps < 0 || !d.d_state) return BRNG_E_ARG;
+    const uint64_t nu = desc_units(d);
+    if ((uint64_t)d.unit_base + nu > c->n_units) return BRNG_E_ARG;
+    const int64_t width = d.model == BRNG_MODEL_LDA ? 0 : (int64_t)d.n_chains;
+    if ((d.d_trace || d.d_trace2) && d.trace_stride < width) return BRNG_E_ARG;
+    const uint32_t* W = c->cfg.window;
+    switch (d.model) {
+        case BRNG_MODEL_TRIANGLE_F64:
+            if (!W[BRNG_U64]) return BRNG_E_KIND_DISABLED;
+            break;
+        case BRNG_MODEL_NORMEXP:
+        case BRNG_MODEL_GAMMA_CHAIN:
+            if (!W[BRNG_N] || !W[BRNG_E]) return BRNG_E_KIND_DISABLED;
+            break;
+        case BRNG_MODEL_EXP_CHAIN:
+            if (!W[BRNG_E]) return BRNG_E_KIND_DISABLED;
+            break;
+        case BRNG_MODEL_LDA:
+            if (!d.d_offsets || !d.d_ntok) return BRNG_E_ARG;
+            if (!W[BRNG_U] || !W[BRNG_N] || !W[BRNG_E]) return BRNG_E_KIND_DISABLED;
+            break;
+    }
+    return BRNG_OK;
+}
+
+static DescDev to_dev(const brng_gibbs_desc& d) {
+    DescDev D;
+    D.model = d.model;
+    D.n_chains = d.n_chains;
+    D.unit_base = d.unit_base;
+    D.flags = d.flags;
+    D.seed = d.seed;
+    D.max_steps = d.max_steps;
+    D.n_units = desc_units(d);
+    D.steps = d.d_steps;
+    D.perm = d.d_perm;
+    D.state = d.d_state;
+    D.trace = d.d_trace;
+    D.trace2 = d.d_trace2;
+    D.stride = d.trace_stride;
+    D.offsets = d.d_offsets;
+    D.ntok = d.d_ntok;
+    D.queue_first = 0;
+    D.pad = 0;
+    return D;
+}
+
+static brng_status launch_plain(brng_ctx* c, const DescDev& D) {
+    const dim3 grid = unit_grid(c, D.n_units), block(64 * c->wpb);
+    const size_t lds = (size_t)c->wpb * model_lds_bytes(D.model);
+    const Pools P = make_pools(c);
+    switch (D.model) {
+        case M_TRIANGLE:
+            hipLaunchKernelGGL(k_gibbs<M_TRIANGLE>, grid, block, lds, c->stream, D, c->meta, P);
+            break;
+        case M_NORMEXP:
+            hipLaunchKernelGGL(k_gibbs<M_NORMEXP>, grid, block, lds, c->stream, D, c->meta, P);
+            break;
+        case M_GAMMA:
+            hipLaunchKernelGGL(k_gibbs<M_GAMMA>, grid, block, lds, c->stream, D, c->meta, P);
+            break;
+        case M_LDA:
+            hipLaunchKernelGGL(k_gibbs<M_LDA>, grid, block, lds, c->stream, D, c->meta, P);
+            break;
+        default:
+            hipLaunchKernelGGL(k_gibbs<M_EXPCHAIN>, grid, block, lds, c->stream, D, c->meta, P);
+            break;
+    }
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
+static int batch_blocks(brng_ctx* c) {
+    if (c->persistent_blocks > 0) return c->persistent_blocks;
+    int per_cu = 0;
+    const size_t lds = (size_t)c->wpb * WAVE_LDS_BYTES;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, 64 * c->wpb, lds) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return per_cu * c->n_cu;
+}
+
+brng_status brng_run_gibbs(brng_ctx* c, const brng_gibbs_desc* descs, uint32_t n_desc) {
+    if (!c || !descs || n_desc == 0) return BRNG_E_ARG;
+    for (uint32_t i = 0; i < n_desc; ++i) {
+        brng_status s = check_desc(c, descs[i]);
+        if (s != BRNG_OK) return s;
+    }
+    // requests must not share units
+    std::vector<std::pair<uint32_t, uint32_t>> ranges(n_desc);
+    for (uint32_t i = 0; i < n_desc; ++i)
+        ranges[i] = {descs[i].unit_base, descs[i].unit_base + desc_units(descs[i])};
+    std::sort(ranges.begin(), ranges.end());
+    for (uint32_t i = 1; i < n_desc; ++i)
+        if (ranges[i].first < ranges[i - 1].second) return BRNG_E_ARG;
+    if (n_desc == 1) return launch_plain(c, to_dev(descs[0]));
+
+    // batched: order requests by decreasing work per unit (steps, and an LDA
+    // sweep costs about as much as 8 chain steps), then enumerate their units
+    std::vector<uint32_t> order(n_desc);
+    for (uint32_t i = 0; i < n_desc; ++i) order[i] = i;
+    auto cost = [&](uint32_t i) {
+        const double w = descs[i].model == BRNG_MODEL_LDA ? 8.0 : 1.0;
+        return w * descs[i].max_steps;
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t b) { return cost(a) > cost(b); });
+    if (n_desc > c->desc_cap) {
+        if (c->desc_pending) {
+            HIPCHK(hipEventSynchronize(c->desc_done));
+            c->desc_pending = false;
+        }
+        if (c->d_descs) (void)hipFree(c->d_descs);
+        if (c->h_descs) (void)hipHostFree(c->h_descs);
+        c->d_descs = nullptr;
+        c->h_descs = nullptr;
+        c->desc_cap = 0;
+        if (hipMalloc((void**)&c->d_descs, sizeof(DescDev) * n_desc) != hipSuccess ||
+            hipHostMalloc((void**)&c->h_descs, sizeof(DescDev) * n_desc, 0) != hipSuccess)
+            return BRNG_E_NOMEM;
+        c->desc_cap = n_desc;
+    }
+    if (c->desc_pending) {  // the staging buffer may still be read by a copy
+        HIPCHK(hipEventSynchronize(c->desc_done));
+        c->desc_pending = false;
+    }
+    uint32_t total = 0;
+    for (uint32_t i = 0; i < n_desc; ++i) {
+        DescDev D = to_dev(descs[order[i]]);
+        D.queue_first = total;
+        total += D.n_units;
+        c->h_descs[i] = D;
+    }
+    HIPCHK(hipMemcpyAsync(c->d_descs, c->h_descs, sizeof(DescDev) * n_desc,
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipEventRecord(c->desc_done, c->stream));
+    c->desc_pending = true;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, c->queue);
+    const int blocks = batch_blocks(c);
+    hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(64 * c->wpb),
+                       (size_t)c->wpb * WAVE_LDS_BYTES, c->stream, c->d_descs, n_desc, total,
+                       c->queue, c->meta, make_pools(c));
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
+brng_status brng_sort_by_length(uint32_t n, const int32_t* steps, int32_t* perm) {
+    if ((n && (!steps || !perm))) return BRNG_E_ARG;
+    std::vector<int32_t> idx(n);
+    for (uint32_t i = 0; i < n; ++i) idx[i] = (int32_t)i;
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](int32_t a, int32_t b) { return steps[a] > steps[b]; });
+    std::memcpy(perm, idx.data(), sizeof(int32_t) * n);
+    return BRNG_OK;
+}
+
+brng_status brng_get_cursors(brng_ctx* c, uint64_t* out) {
+    if (!c || !out) return BRNG_E_ARG;
+    uint64_t* d = nullptr;
+    const size_t bytes = sizeof(uint64_t) * 4 * (size_t)c->n_units;
+    HIPCHK(hipMalloc(&d, bytes));
+    hipLaunchKernelGGL(k_get_cursors, dim3((c->n_units + 255) / 256), dim3(256), 0, c->stream,
+                       c->meta, c->n_units, d);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d, bytes, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e);
+    return BRNG_OK;
+}
+
+brng_status brng_set_cursors(brng_ctx* c, const uint64_t* in) {
+    if (!c || !in) return BRNG_E_ARG;
+    uint64_t* d = nullptr;
+    const size_t bytes = sizeof(uint64_t) * 4 * (size_t)c->n_units;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMalloc(&d, bytes));
+    hipError_t e = hipMemcpy(d, in, bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_set_cursors, dim3((c->n_units + 255) / 256), dim3(256), 0,
+                           c->stream, c->meta, c->n_units, d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e);
+    return BRNG_OK;
+}
+
+brng_status brng_get_window(brng_ctx* c, int32_t kind, uint32_t unit, void* out, uint32_t cap,
+                            uint64_t* base, uint32_t* len) {
+    if (!c || kind < 0 || kind >= BRNG_NKINDS || unit >= c->n_units || !base || !len)
+        return BRNG_E_ARG;
+    if (!c->cfg.window[kind]) return BRNG_E_KIND_DISABLED;
+    Meta m;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(&m, c->meta + unit, sizeof(Meta), hipMemcpyDeviceToHost));
+    *base = m.wbase[kind];
+    *len = m.wlen[kind];
+    const uint32_t n = std::min(cap, c->cfg.window[kind]);
+    if (n && out) {
+        const size_t el = kind_elem(kind);
+        const char* src = (const char*)c->pool[kind] + (size_t)unit * c->cfg.window[kind] * el;
+        HIPCHK(hipMemcpy(out, src, n * el, hipMemcpyDeviceToHost));
+    }
+    return BRNG_OK;
+}
+
+brng_status brng_get_info(const brng_ctx* c, uint32_t* n_units, uint32_t* window4) {
+    if (!c) return BRNG_E_ARG;
+    if (n_units) *n_units = c->n_units;
+    if (window4)
+        for (int k = 0; k < 4; ++k) window4[k] = c->cfg.window[k];
+    return BRNG_OK;
+}
+
+brng_status brng_set_launch(brng_ctx* c, int32_t wpb, int32_t persistent_blocks) {
+    if (!c || !(wpb == 1 || wpb == 2 || wpb == 4 || wpb == 8) || persistent_blocks < 0)
+        return BRNG_E_ARG;
+    c->wpb = wpb;
+    c->persistent_blocks = persistent_blocks;
+    return BRNG_OK;
+}
+
+}  // extern "C"

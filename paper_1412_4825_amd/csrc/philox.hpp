@@ -1,0 +1,110 @@
+// Core engine and base-deviate conversions, device side (gfx950).
+//
+// The paper keeps "buffers of random deviates for reducible distributions
+// (uniform, Gaussian, exponential)" that a vector engine refills in bulk
+// (Sec. 2.1, Key Concepts; Sec. 2.2, Implementation).  The engine here is
+// the counter-based Philox4x32-10 generator (Salmon, Moraes, Dror & Shaw,
+// SC'11): one 128-bit counter block gives four 32-bit words, so any pool
+// entry is a pure function of (seed, unit, kind, index) and a window can be
+// regenerated anywhere, by any wave, in any order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace brng {
+
+enum : uint32_t { KIND_U = 0, KIND_N = 1, KIND_E = 2, KIND_U64 = 3 };
+
+struct Key {
+    uint32_t k0;     // unit id (request-local)
+    uint32_t k1;     // seed, low 32 bits
+    uint32_t c3;     // seed, high 32 bits (fourth counter word)
+};
+
+// Ten Philox4x32 rounds.  Each round multiplies c0 and c2 by the Philox
+// constants (full 64-bit products, one v_mad_u64_u32 each), swaps the halves
+// and mixes in the key; the key advances by the Weyl increments between
+// rounds.  Key words are wave-uniform in every caller, so the key schedule
+// runs on the scalar unit.
+__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint4 block_words(const Key& key, uint32_t kind, uint64_t block) {
+    return philox10((uint32_t)block, (uint32_t)(block >> 32), kind, key.c3, key.k0, key.k1);
+}
+
+// U = (2 (w >> 9) + 1) 2^-24: the open midpoint grid, exact in fp32.
+// 2 (w >> 9) + 1 == (w >> 8) | 1.
+__device__ __forceinline__ float u01(uint32_t w) {
+    return (float)((w >> 8) | 1u) * 0x1p-24f;
+}
+
+// U64 = (2k + 1) 2^-53 with k = (wa << 20) | (wb >> 12): 52 random bits.
+__device__ __forceinline__ double u01d(uint32_t wa, uint32_t wb) {
+    const uint64_t k = ((uint64_t)wa << 20) | (uint64_t)(wb >> 12);
+    return (double)(2 * k + 1) * 0x1p-53;
+}
+
+// E = -ln U.
+__device__ __forceinline__ float expo(uint32_t w) { return -logf(u01(w)); }
+
+// Box-Muller: radius from the first word, angle 2 pi Ub from the second;
+// cosine goes to the even entry, sine to the odd one.  sincospi takes the
+// exact argument 2 Ub, so no rounding of 2 pi enters.
+__device__ __forceinline__ float2 box_muller(uint32_t wa, uint32_t wb) {
+    const float r = sqrtf(-2.0f * logf(u01(wa)));
+    float s, c;
+    sincospif(2.0f * u01(wb), &s, &c);
+    return make_float2(r * c, r * s);
+}
+
+// One block -> the raw bits of its entries (four floats, or two doubles for
+// U64), ready for one 128-bit store.
+template <uint32_t KIND>
+__device__ __forceinline__ uint4 gen_block(const Key& key, uint64_t block) {
+    const uint4 w = block_words(key, KIND, block);
+    if constexpr (KIND == KIND_U) {
+        return make_uint4(__float_as_uint(u01(w.x)), __float_as_uint(u01(w.y)),
+                          __float_as_uint(u01(w.z)), __float_as_uint(u01(w.w)));
+    } else if constexpr (KIND == KIND_E) {
+        return make_uint4(__float_as_uint(expo(w.x)), __float_as_uint(expo(w.y)),
+                          __float_as_uint(expo(w.z)), __float_as_uint(expo(w.w)));
+    } else if constexpr (KIND == KIND_N) {
+        const float2 a = box_muller(w.x, w.y);
+        const float2 b = box_muller(w.z, w.w);
+        return make_uint4(__float_as_uint(a.x), __float_as_uint(a.y), __float_as_uint(b.x),
+                          __float_as_uint(b.y));
+    } else {
+        const double a = u01d(w.x, w.y);
+        const double b = u01d(w.z, w.w);
+        const uint64_t ia = (uint64_t)__double_as_longlong(a);
+        const uint64_t ib = (uint64_t)__double_as_longlong(b);
+        return make_uint4((uint32_t)ia, (uint32_t)(ia >> 32), (uint32_t)ib, (uint32_t)(ib >> 32));
+    }
+}
+
+template <uint32_t KIND> struct KindTraits {
+    using T = float;
+    static constexpr int EPB = 4;  // entries per Philox block / per 16-byte store
+};
+template <> struct KindTraits<KIND_U64> {
+    using T = double;
+    static constexpr int EPB = 2;
+};
+
+}  // namespace brng

@@ -1,0 +1,80 @@
+"""The C interface library loads and exports every function include/brng.h
+declares; host-only entry points and argument checks work without a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1412_4825_amd import binding as b
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "brng.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(brng_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_function_is_exported():
+    names = _declared()
+    assert "brng_create" in names and "brng_run_gibbs" in names
+    lib = ctypes.CDLL(b.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(b.EXPORTS)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes layouts equal what a C compiler makes of include/brng.h."""
+    fields = {"brng_config": [f[0] for f in b.brng_config._fields_],
+              "brng_gibbs_desc": [f[0] for f in b.brng_gibbs_desc._fields_]}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "brng.h"', "int main(void){"]
+    for st, fs in fields.items():
+        lines.append('printf("%%zu\\n", sizeof(%s));' % st)
+        for f in fs:
+            lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (st, f))
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    want = []
+    for st, cls in (("brng_config", b.brng_config), ("brng_gibbs_desc", b.brng_gibbs_desc)):
+        want.append(ctypes.sizeof(cls))
+        want += [getattr(cls, f).offset for f in fields[st]]
+    assert got == want
+
+
+@pytest.mark.parametrize("window", [[100, 0, 0, 0], [256, 0, 0, 0], [513, 0, 0, 0]])
+def test_bad_window_rejected_without_device(window):
+    with pytest.raises(b.BrngError) as e:
+        b.brng_create(1, 64, window)
+    assert e.value.status == b.BRNG_E_ARG
+
+
+def test_bad_config_rejected():
+    for kw in (dict(n_chains=0), dict(layout=7), dict(prec=3)):
+        args = dict(seed=1, n_chains=64, window=[512, 0, 0, 0])
+        args.update(kw)
+        with pytest.raises(b.BrngError):
+            b.brng_create(**args)
+
+
+def test_null_context_rejected():
+    lib = b.lib()
+    assert lib.brng_fill_base(None, 0) == b.BRNG_E_ARG
+    assert lib.brng_run_gibbs(None, None, 0) == b.BRNG_E_ARG
+    assert lib.brng_destroy(None) == b.BRNG_OK
+    assert b.brng_status_string(b.BRNG_E_KIND_DISABLED).startswith("pool kind disabled")
+
+
+def test_sort_by_length_matches_contract():
+    rng = np.random.default_rng(0)
+    steps = rng.integers(1, 30, size=5000).astype(np.int32)
+    assert np.array_equal(b.brng_sort_by_length(steps), oracle.sort_by_length(steps))

@@ -1,0 +1,400 @@
+"""GPU parity: the HIP library (through its C interface) against the oracle.
+
+Every test prints the case it runs (seed, sizes, entry point) before the GPU
+call, so a failing run names its case.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1412_4825_amd import workloads
+from tests.parity_util import compare_units, tol_of, within
+
+pytestmark = pytest.mark.gpu
+
+W_SMALL = [512, 512, 512, 512]
+
+
+def _b():
+    from paper_1412_4825_amd import binding
+    return binding
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _ctx(seed, n, window, layout=0, prec=0):
+    import torch
+    b = _b()
+    return b.brng_create(seed, n, window, layout=layout, prec=prec,
+                         stream=torch.cuda.current_stream())
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+SEEDS = [0, 20141217, 0xFFFFFFFF00000005]
+
+
+@pytest.mark.parametrize("seed", SEEDS)
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+def test_fill_base_windows(dev, seed, kind):
+    b = _b()
+    _say("fill_base", seed, kind)
+    n = 130  # three units, the last one partial
+    W = [1024] * 4
+    ctx = _ctx(seed, n, W)
+    try:
+        for unit in range(3):
+            base, ln, win = b.brng_get_window(ctx, kind, unit)
+            assert base == 0 and ln == 1024
+            ref = oracle.entries(seed, unit, kind, 0, 1024)
+            if kind in (0, 3):
+                assert np.array_equal(win.astype(np.float64), ref)
+            else:
+                assert within(win, ref, tol_of(ref)).all()
+        # refill at a large cursor: block index above 2^32 exercises the
+        # counter's high word
+        cur = b.brng_get_cursors(ctx)
+        big = (1 << 34) + 777
+        cur[:, kind] = [big, big + 300, 5]
+        b.brng_set_cursors(ctx, cur)
+        b.brng_fill_base(ctx, kind)
+        align = 128 if kind == 3 else 256
+        for unit, c in enumerate([big, big + 300, 5]):
+            base, ln, win = b.brng_get_window(ctx, kind, unit)
+            assert base == c - c % align and ln == 1024
+            ref = oracle.entries(seed, unit, kind, base, 1024)
+            if kind in (0, 3):
+                assert np.array_equal(win.astype(np.float64), ref)
+            else:
+                assert within(win, ref, tol_of(ref)).all()
+    finally:
+        b.brng_destroy(ctx)
+
+
+def test_steps_reducible_and_gamma(dev):
+    """Five calls of each one-at-a-time function with per-chain parameters;
+    small windows force refills inside the kernels."""
+    b = _b()
+    n, seed = 1000, 99
+    p = workloads.step_params(n, seed=5)
+    _say("steps", n, seed)
+    ctx = _ctx(seed, n, W_SMALL)
+    cur = oracle.new_cursors((n + 63) // 64)
+    out = _t(np.zeros(n, np.float32), dev)
+    try:
+        ta, tb = _t(p["a"], dev), _t(p["b"], dev)
+        tmu, tsg, tl = _t(p["mu"], dev), _t(p["sigma"], dev), _t(p["lam"], dev)
+        tal = _t(p["alpha"], dev)
+        units = np.arange(n) // 64
+        flips = set()
+        for it in range(5):
+            b.brng_step_uniform(ctx, ta, tb, out)
+            r, tol = oracle.step_uniform(seed, cur, p["a"], p["b"])
+            assert within(_np(out), r, tol).all()
+            b.brng_step_normal(ctx, tmu, tsg, out)
+            r, tol = oracle.step_normal(seed, cur, p["mu"], p["sigma"])
+            assert within(_np(out), r, tol).all()
+            b.brng_step_exp(ctx, tl, out)
+            r, tol = oracle.step_exp(seed, cur, p["lam"])
+            assert within(_np(out), r, tol).all()
+        gcur = cur.copy()
+        b.brng_step_gamma(ctx, tal, out)
+        g, tol, margin, nN, nE = oracle.step_gamma(seed, gcur, p["alpha"])
+        bad, flips = compare_units(_np(out)[None], g[None], tol[None], margin[None], units)
+        assert bad == 0
+        got = b.brng_get_cursors(ctx)
+        keep = np.array([u not in flips for u in range(got.shape[0])])
+        assert np.array_equal(got[keep], gcur[keep])
+        assert len(flips) <= 1
+    finally:
+        b.brng_destroy(ctx)
+
+
+def test_step_uniform_fp64(dev):
+    b = _b()
+    n, seed = 300, 7
+    _say("step_uniform fp64", n, seed)
+    ctx = _ctx(seed, n, [0, 0, 0, 512], prec=1)
+    rng = np.random.default_rng(1)
+    a = rng.normal(size=n)
+    bb = a + rng.exponential(size=n)
+    out = _t(np.zeros(n), dev)
+    cur = oracle.new_cursors(5)
+    try:
+        for it in range(6):
+            b.brng_step_uniform(ctx, _t(a, dev), _t(bb, dev), out)
+            r, _ = oracle.step_uniform(seed, cur, a, bb, kind=3)
+            g = _np(out)
+            assert np.all(np.abs(g - r) <= 4e-16 * np.maximum(np.abs(a), np.abs(r)) + 1e-300)
+        assert np.array_equal(b.brng_get_cursors(ctx), cur)
+    finally:
+        b.brng_destroy(ctx)
+
+
+def test_step_dirichlet_ragged(dev):
+    b = _b()
+    it = workloads.dirichlet_items(150, kmin=1, kmax=300, seed=3)
+    seed = 1234
+    n = it["K"].size
+    _say("step_dirichlet", n, seed)
+    ctx = _ctx(seed, n, W_SMALL, layout=1)
+    out = _t(np.zeros(it["alpha"].size, np.float32), dev)
+    cur = oracle.new_cursors(n)
+    try:
+        for rep in range(2):
+            b.brng_step_dirichlet(ctx, _t(it["offsets"], dev), _t(it["alpha"], dev), out)
+            th, tol, margin = oracle.step_dirichlet(seed, cur, it["offsets"], it["alpha"])
+            g = _np(out)
+            ok = within(g, th, tol)
+            bad_items = [i for i in range(n) if not ok[it["offsets"][i]:it["offsets"][i + 1]].all()]
+            assert all(margin[i] <= 1.0 for i in bad_items)
+            assert len(bad_items) <= 1
+        got = b.brng_get_cursors(ctx)
+        assert (got == cur).all(axis=1).sum() >= n - 1
+    finally:
+        b.brng_destroy(ctx)
+
+
+def _gibbs(ctx, model, n, state, steps, seed, dev, trace=None, trace2=None, stride=0, **kw):
+    b = _b()
+    d = b.gibbs_desc(model, n, state, max_steps=steps, seed=seed, trace=trace, trace2=trace2,
+                     trace_stride=stride, **kw)
+    b.brng_run_gibbs(ctx, d)
+
+
+def test_triangle_full_size_bit_exact(dev):
+    """1,024 chains x 10,000 iterations in fp64 (the paper's example at the
+    configured size): every x and y of every iteration, bit for bit."""
+    import torch
+    b = _b()
+    n, iters, seed = 1024, 10000, 20141217
+    _say("triangle", n, iters, seed)
+    ctx = _ctx(seed, n, [0, 0, 0, 4096])
+    st = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+    tx = torch.zeros((iters, n), dtype=torch.float64, device=dev)
+    ty = torch.zeros((iters, n), dtype=torch.float64, device=dev)
+    try:
+        _gibbs(ctx, b.BRNG_MODEL_TRIANGLE_F64, n, st, iters, seed, dev, tx, ty, n)
+        r = oracle.triangle(seed, n, iters)
+        assert np.array_equal(_np(tx), r["xtrace"])
+        assert np.array_equal(_np(ty), r["ytrace"])
+        s = _np(st)
+        assert np.array_equal(s[:n], r["x"]) and np.array_equal(s[n:], r["y"])
+        assert np.array_equal(b.brng_get_cursors(ctx), r["cursors"])
+    finally:
+        b.brng_destroy(ctx)
+
+
+def test_normexp_chains(dev):
+    import torch
+    b = _b()
+    n, steps, seed = 2048 + 40, 300, 5
+    _say("normexp", n, steps, seed)
+    ctx = _ctx(seed, n, W_SMALL)
+    st = torch.zeros(n, dtype=torch.float32, device=dev)
+    ts = torch.zeros((steps, n), dtype=torch.float32, device=dev)
+    te = torch.zeros((steps, n), dtype=torch.float32, device=dev)
+    try:
+        _gibbs(ctx, b.BRNG_MODEL_NORMEXP, n, st, steps, seed, dev, ts, te, n)
+        r = oracle.normexp(seed, n, steps)
+        gs, ge = _np(ts), _np(te)
+        ok_s = within(gs, r["strace"], r["stol"])
+        ok_e = within(ge, r["etrace"], r["etol"])
+        frac = 1.0 - (ok_s.mean() + ok_e.mean()) / 2
+        print("normexp out-of-bound fraction", frac, flush=True)
+        assert ok_s.all() and ok_e.all()
+        assert np.array_equal(b.brng_get_cursors(ctx), r["cursors"])
+    finally:
+        b.brng_destroy(ctx)
+
+
+def test_expchain(dev):
+    import torch
+    b = _b()
+    n, steps, seed = 640, 200, 8
+    _say("expchain", n, steps, seed)
+    ctx = _ctx(seed, n, W_SMALL)
+    st = torch.zeros(n, dtype=torch.float32, device=dev)
+    te = torch.zeros((steps, n), dtype=torch.float32, device=dev)
+    try:
+        _gibbs(ctx, b.BRNG_MODEL_EXP_CHAIN, n, st, steps, seed, dev, te, None, n)
+        r = oracle.expchain(seed, n, steps)
+        assert within(_np(te), r["etrace"], r["etol"]).all()
+        assert np.array_equal(b.brng_get_cursors(ctx), r["cursors"])
+    finally:
+        b.brng_destroy(ctx)
+
+
+def _run_gamma_chain(dev, w, seed, window, perm=None):
+    import torch
+    b = _b()
+    n = w["n_chains"]
+    if perm is None:
+        perm = b.brng_sort_by_length(w["steps"])
+    smax = int(w["steps"].max())
+    ctx = _ctx(seed, n, window)
+    st = _t(w["alpha0"], dev)
+    tg = torch.full((smax, n), float("nan"), dtype=torch.float32, device=dev)
+    try:
+        _gibbs(ctx, b.BRNG_MODEL_GAMMA_CHAIN, n, st, smax, seed, dev, tg, None, n,
+               steps=_t(w["steps"], dev), perm=_t(perm, dev))
+        return _np(tg), _np(st), b.brng_get_cursors(ctx), perm
+    finally:
+        b.brng_destroy(ctx)
+
+
+def test_gamma_chains(dev):
+    w = workloads.gamma_chain(n_chains=4096 + 17, lmin=5, lmax=120, seed=77)
+    seed = 31
+    _say("gamma_chain", w["n_chains"], seed)
+    g, alpha, cur, perm = _run_gamma_chain(dev, w, seed, W_SMALL)
+    r = oracle.gamma_chain(seed, w["alpha0"], w["steps"], perm=perm)
+    assert np.array_equal(perm, oracle.sort_by_length(w["steps"]))
+    units = np.arange(w["n_chains"]) // 64
+    bad, flips = compare_units(g, r["gtrace"], r["gtol"], r["gmargin"], units)
+    print("gamma flips", len(flips), "bad", bad, flush=True)
+    assert bad == 0
+    assert len(flips) <= 2
+    keep = np.array([u not in flips for u in range(cur.shape[0])])
+    assert np.array_equal(cur[keep], r["cursors"][keep])
+
+
+def test_lda(dev):
+    import torch
+    b = _b()
+    w = workloads.lda(n_docs=240, sweeps=8, seed=5)
+    seed = 404
+    nd, total = w["n_docs"], int(w["offsets"][-1])
+    _say("lda", nd, w["sweeps"], seed)
+    ctx = _ctx(seed, nd, W_SMALL, layout=1)
+    counts = torch.zeros(total, dtype=torch.int32, device=dev)
+    th = torch.zeros((w["sweeps"], total), dtype=torch.float32, device=dev)
+    ct = torch.zeros((w["sweeps"], total), dtype=torch.int32, device=dev)
+    try:
+        _gibbs(ctx, b.BRNG_MODEL_LDA, nd, counts, w["sweeps"], seed, dev, th, ct, total,
+               offsets=_t(w["offsets"], dev), ntok=_t(w["ntok"], dev))
+        r = oracle.lda(seed, w["offsets"], w["ntok"], w["sweeps"])
+        gth, gct = _np(th), _np(ct)
+        off = w["offsets"]
+        diverged = 0
+        for d in range(nd):
+            a, z = off[d], off[d + 1]
+            for s in range(w["sweeps"]):
+                okt = within(gth[s, a:z], r["theta"][s, a:z], r["theta_tol"][s, a:z]).all()
+                okc = np.array_equal(gct[s, a:z], r["ctrace"][s, a:z])
+                if okt and okc:
+                    continue
+                # only a decision within tolerance may change the course
+                if not okt:
+                    assert r["gmargin"][s, d] <= 1.0, (d, s)
+                else:
+                    assert r["mmargin"][s, d] <= 0.0, (d, s)
+                diverged += 1
+                break
+        print("lda diverged docs", diverged, flush=True)
+        assert diverged <= 2
+    finally:
+        b.brng_destroy(ctx)
+
+
+def test_window_length_invariance(dev):
+    """Window length is a speed knob only (Sec. 2.4): bitwise equal results."""
+    w = workloads.gamma_chain(n_chains=1024 + 5, lmin=10, lmax=80, seed=9)
+    outs = [_run_gamma_chain(dev, w, 3, [0, win, win, 0]) for win in (512, 768, 4096, 65536)]
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0], equal_nan=True)
+        assert np.array_equal(o[1], outs[0][1])
+        assert np.array_equal(o[2], outs[0][2])
+
+
+def test_step_api_equals_chain_kernel(dev):
+    """A host loop of one-at-a-time gamma calls reproduces the chain kernel
+    bit for bit (same streams, same consumption order)."""
+    import torch
+    b = _b()
+    n, steps, seed = 640, 40, 12
+    w = workloads.gamma_chain(n_chains=n, lmin=steps, lmax=steps, seed=2)
+    _say("step loop vs chain", n, steps)
+    g, alpha, cur, perm = _run_gamma_chain(dev, w, seed, W_SMALL)
+    ctx = _ctx(seed, n, W_SMALL)
+    try:
+        a = _t(w["alpha0"][perm], dev)
+        out = torch.zeros(n, dtype=torch.float32, device=dev)
+        rows = []
+        for t in range(steps):
+            b.brng_step_gamma(ctx, a, out)
+            rows.append(out.clone())
+            a = torch.tensor(0.1, dtype=torch.float32, device=dev) + out
+        G = _np(torch.stack(rows))
+        assert np.array_equal(G, g)
+        assert np.array_equal(b.brng_get_cursors(ctx), cur)
+    finally:
+        b.brng_destroy(ctx)
+
+
+def test_batched_equals_alone_and_resume(dev):
+    """Two requests in one persistent launch give the same bits as each run
+    alone; a run split in two with RESUME equals the straight run."""
+    import torch
+    b = _b()
+    seed_a, seed_b = 41, 42
+    n_a, n_b, steps = 700, 300, 120
+    wa = workloads.gamma_chain(n_chains=n_a, lmin=20, lmax=steps, seed=4)
+    perm_a = b.brng_sort_by_length(wa["steps"])
+
+    def alone_gamma():
+        g, al, cur, _ = _run_gamma_chain(dev, wa, seed_a, W_SMALL, perm=perm_a)
+        return g, al
+
+    def alone_normexp():
+        ctx = _ctx(seed_b, n_b, W_SMALL)
+        st = torch.zeros(n_b, dtype=torch.float32, device=dev)
+        ts = torch.zeros((steps, n_b), dtype=torch.float32, device=dev)
+        try:
+            _gibbs(ctx, b.BRNG_MODEL_NORMEXP, n_b, st, steps, seed_b, dev, ts, None, n_b)
+            return _np(ts), _np(st)
+        finally:
+            b.brng_destroy(ctx)
+
+    _say("batched mix")
+    ga, ala = alone_gamma()
+    sb, stb = alone_normexp()
+    units_a = (n_a + 63) // 64
+    ctx = _ctx(777, n_a + n_b + 64 * 3, W_SMALL)
+    try:
+        st_a = _t(wa["alpha0"], dev)
+        tg = torch.full((steps, n_a), float("nan"), dtype=torch.float32, device=dev)
+        st_b = torch.zeros(n_b, dtype=torch.float32, device=dev)
+        ts = torch.zeros((steps, n_b), dtype=torch.float32, device=dev)
+        d1 = b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, n_a, st_a, max_steps=steps, seed=seed_a,
+                          trace=tg, trace_stride=n_a, steps=_t(wa["steps"], dev),
+                          perm=_t(perm_a, dev), unit_base=2)
+        d2 = b.gibbs_desc(b.BRNG_MODEL_NORMEXP, n_b, st_b, max_steps=steps, seed=seed_b,
+                          trace=ts, trace_stride=n_b, unit_base=2 + units_a + 1)
+        b.brng_run_gibbs(ctx, [d1, d2])
+        assert np.array_equal(_np(tg), ga, equal_nan=True)
+        assert np.array_equal(_np(st_a), ala)
+        assert np.array_equal(_np(ts), sb)
+        assert np.array_equal(_np(st_b), stb)
+        # resume: 50 + 70 steps of the normexp request equal 120 straight
+        st_c = torch.zeros(n_b, dtype=torch.float32, device=dev)
+        t1 = torch.zeros((50, n_b), dtype=torch.float32, device=dev)
+        t2 = torch.zeros((70, n_b), dtype=torch.float32, device=dev)
+        _gibbs(ctx, b.BRNG_MODEL_NORMEXP, n_b, st_c, 50, seed_b, dev, t1, None, n_b)
+        _gibbs(ctx, b.BRNG_MODEL_NORMEXP, n_b, st_c, 70, seed_b, dev, t2, None, n_b,
+               flags=b.BRNG_FLAG_RESUME)
+        assert np.array_equal(np.vstack([_np(t1), _np(t2)]), sb)
+        assert np.array_equal(_np(st_c), stb)
+    finally:
+        b.brng_destroy(ctx)
