@@ -2,12 +2,13 @@
 """Benchmark of the varying-parameter pool RNG on one MI355X.
 
 Default workload (normal/exponential chains): 65,536 chains x 1,000 steps,
-s' ~ N(0.9 s, 0.5 + |s|) then e ~ Exp(1 + s'^2), fp32, Philox4x32-10 pools.
-One timed step is the whole hot path over that batch: bulk refill of the
-Gaussian and exponential pool windows (one 128-bit store per Philox block)
-followed by one launch that runs every chain for all 1,000 steps from the
-pools, writing both outputs of every step.  Chains continue from step to
-step (each step draws fresh deviates).
+s' ~ N(0.9 s, 0.5 + |s|) then e ~ Exp(1 + s'^2), fp32, Philox4x32-10 pools
+with a window of 4,096 entries per unit (64 chains) per kind, refilled on
+exhaustion.  One timed step is the whole hot path over that batch: bulk
+refill of the Gaussian and exponential windows (one 128-bit store per Philox
+block) followed by one launch that runs every chain for all 1,000 steps from
+the pools (regenerating each window in place when it runs out), writing both
+outputs of every step.  Chains continue from step to step.
 
 Prints one JSON line: deviates/s, the roofline of the dominant kernel
 (algorithmic bytes over its event-timed duration against 8 TB/s), and the
@@ -60,7 +61,9 @@ class Timer:
 
 def setup_normexp(torch, b, args):
     n, steps = args.chains or 65536, args.chain_steps or 1000
-    W = args.window or _round_up(64 * steps + 256, 256)
+    # pool window per unit (64 chains) per kind: 4,096 entries, refilled on
+    # exhaustion inside the chain kernel
+    W = args.window or 4096
     dev = torch.device("cuda:0")
     ctx = b.brng_create(args.seed, n, [0, W, W, 0], stream=torch.cuda.current_stream())
     st = torch.zeros(n, dtype=torch.float32, device=dev)
@@ -90,16 +93,20 @@ def setup_normexp(torch, b, args):
 
     deviates = 2 * n * steps
     consumed = 2 * n * steps  # one N and one E entry per chain-step
+    # algorithmic bytes: every consumed pool entry is written once and read
+    # once (4 B each), every output is written once (4 B).  The bulk fill
+    # writes the first window of each unit and kind; the chain kernel writes
+    # the rest (its in-kernel refills) and does all reads and output writes.
+    per_unit_kind = 64 * steps
+    fill_written = 2 * units * min(W, per_unit_kind)
     bytes_ = {
-        # the fill writes every window entry (4 B) of both kinds
-        "fill": 2 * units * W * 4,
-        # the chain kernel reads each consumed entry once and writes 2 outputs
-        "chains": consumed * 4 + deviates * 4,
+        "fill": fill_written * 4,
+        "chains": (consumed - fill_written) * 4 + consumed * 4 + deviates * 4,
     }
     launches = {"fill": 2, "chains": 1}
     cfg = {"workload": "normal/exponential chains: s'~N(0.9s,0.5+|s|), e~Exp(1+s'^2)",
-           "chains": n, "steps": steps, "window": W, "precision": "fp32",
-           "generator": "Philox4x32-10"}
+           "chains": n, "steps": steps, "window_per_unit_per_kind": W, "unit_chains": 64,
+           "precision": "fp32", "generator": "Philox4x32-10"}
 
     def cpu(workers):
         return cpu_normexp(args.seed, n, steps, workers)
@@ -172,7 +179,7 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     W = WORKLOADS[args.workload](torch, b, args)
-    b.brng_set_launch(W["ctx"], args.wpb, 0)
+    b.brng_set_launch(W["ctx"], args.wpb)
     step = W["step"]
 
     warm = Timer(torch)

@@ -170,14 +170,14 @@ typedef struct {
     const int32_t *d_ntok;    /* LDA: tokens per document */
 } brng_gibbs_desc;
 
-/* Run chains to completion on the context's stream.  n_desc = 1 is the
- * plain form (one launch of the model's kernel).  n_desc > 1 is the batched
- * form: all requests' units go into one persistent kernel that pulls units
- * from a device queue, longest first, whatever their model.  Each request's
- * units [unit_base, unit_base + n_units) must lie inside the context and
- * must not overlap another request's.  Layout CHAINS contexts serve the
- * chain models, ITEMS contexts serve LDA.  The needed kinds must be enabled:
- * TRIANGLE U64; NORMEXP N,E; GAMMA N,E; EXP E; LDA U,N,E.
+/* Run chains to completion on the context's stream.  Each request is one
+ * launch of its model's kernel (one wave per unit, every step of every chain
+ * inside that launch); several requests run back to back on the stream.
+ * Each request's units [unit_base, unit_base + n_units) must lie inside the
+ * context and must not overlap another request's.  The needed kinds must be
+ * enabled: TRIANGLE U64; NORMEXP N,E; GAMMA N,E; EXP E; LDA U,N,E.  LDA
+ * documents need 1..256 components (others are skipped).  Traces need
+ * max_steps rows of trace_stride elements.
  * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_HIP. */
 brng_status brng_run_gibbs(brng_ctx *ctx, const brng_gibbs_desc *h_descs, uint32_t n_desc);
 
@@ -202,14 +202,23 @@ brng_status brng_set_cursors(brng_ctx *ctx, const uint64_t *h_in);
 brng_status brng_get_window(brng_ctx *ctx, int32_t kind, uint32_t unit, void *h_out,
                             uint32_t cap, uint64_t *h_base, uint32_t *h_len);
 
+/* The conversion half of the core engine on caller-supplied words: n_words
+ * 32-bit words (a multiple of 4, 16-byte aligned device arrays) become
+ * n_words entries of kind U, N or E (floats; N pairs words 2i, 2i+1) or
+ * n_words/2 entries of U64 (doubles), exactly as pool entries are made from
+ * Philox words.  For validating the conversions and for callers with their
+ * own word streams.  Asynchronous on `stream` (hipStream_t, NULL = default).
+ * Errors: BRNG_E_ARG, BRNG_E_HIP. */
+brng_status brng_convert(int32_t kind, const uint32_t *d_words, uint64_t n_words, void *d_out,
+                         void *stream);
+
 /* Context facts: number of units, window lengths. */
 brng_status brng_get_info(const brng_ctx *ctx, uint32_t *n_units, uint32_t *window4);
 
-/* Launch shape of the chain kernels (the autotuner's knobs; results do not
- * depend on them): waves per workgroup (1, 2, 4 or 8) and the number of
- * workgroups of the persistent batched kernel (0 = one per unit).
+/* Launch shape of the chain and step kernels (a tuning knob; results do not
+ * depend on it): waves per workgroup, 1, 2, 4 or 8; `reserved` must be 0.
  * Errors: BRNG_E_ARG. */
-brng_status brng_set_launch(brng_ctx *ctx, int32_t waves_per_block, int32_t persistent_blocks);
+brng_status brng_set_launch(brng_ctx *ctx, int32_t waves_per_block, int32_t reserved);
 
 /* Human-readable status. Never NULL. */
 const char *brng_status_string(brng_status s);

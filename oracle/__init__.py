@@ -73,6 +73,7 @@ def _declare(L):
     L.or_tol.argtypes = [C.c_double]
     L.or_tol.restype = C.c_double
     L.or_u32_many.argtypes = [_u32p, C.c_uint64, _dp]
+    L.or_convert.argtypes = [C.c_int, _u32p, C.c_uint64, _dp]
     L.or_step_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, _u64p, _dp, _dp, _dp, _dp]
     L.or_step_normal.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _dp, _dp, _dp]
     L.or_step_exp.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _dp, _dp]
@@ -248,6 +249,14 @@ def expchain(seed, n_chains, steps, e0=None, cursors=None, width=UNIT_WIDTH, uni
     lib().or_expchain(seed, unit0, n_chains, width, steps, 1 if e0 is None else 0, _p(e, _dp),
                       _p(cur, _u64p), _p(etr, _dp), _p(etol, _dp))
     return dict(e=e, etrace=etr, etol=etol, cursors=cur)
+
+
+def convert(kind: int, w) -> np.ndarray:
+    """Entries made from caller-supplied words (pool conversion rules)."""
+    w = np.ascontiguousarray(w, dtype=np.uint32)
+    out = np.zeros(w.size // 2 if kind == KIND_U64 else w.size, dtype=np.float64)
+    lib().or_convert(kind, _p(w, _u32p), w.size, _p(out, _dp))
+    return out
 
 
 def u32_many(w) -> np.ndarray:

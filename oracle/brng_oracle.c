@@ -144,6 +144,31 @@ void or_entries(uint64_t seed, uint32_t unit, uint32_t kind, uint64_t j0,
         out[i] = or_entry(seed, unit, kind, j0 + i);
 }
 
+/* Entries of `kind` made from caller-supplied words, as pool entries are made
+ * from Philox words: U/E/N give one entry per word (N pairs words 2i, 2i+1),
+ * U64 one entry per two words.  n_words is a multiple of 4. */
+void or_convert(int kind, const uint32_t *w, uint64_t n_words, double *out)
+{
+    for (uint64_t i = 0; i < n_words; i += 2) {
+        if (kind == OR_U64) {
+            out[i / 2] = or_u64(w[i], w[i + 1]);
+            continue;
+        }
+        for (int q = 0; q < 2; q++) {
+            uint64_t j = i + (uint64_t)q;
+            if (kind == OR_U)
+                out[j] = or_u32(w[j]);
+            else if (kind == OR_E)
+                out[j] = -log(or_u32(w[j]));
+            else {
+                double r = sqrt(-2.0 * log(or_u32(w[i])));
+                double ang = 2.0 * M_PI * or_u32(w[i + 1]);
+                out[j] = q == 0 ? r * cos(ang) : r * sin(ang);
+            }
+        }
+    }
+}
+
 /* Conversions of many words at once (for exhaustive checks). */
 void or_u32_many(const uint32_t *w, uint64_t n, double *out)
 {

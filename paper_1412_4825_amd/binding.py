@@ -31,6 +31,7 @@ EXPORTS = [
     "brng_step_exp", "brng_step_gamma", "brng_step_dirichlet", "brng_run_gibbs",
     "brng_sort_by_length", "brng_get_cursors", "brng_set_cursors", "brng_get_window",
     "brng_get_info", "brng_set_launch", "brng_status_string", "brng_last_hip_error",
+    "brng_convert",
 ]
 
 
@@ -99,6 +100,7 @@ def _load():
                                   C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)]
     L.brng_get_info.argtypes = [vp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
     L.brng_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
+    L.brng_convert.argtypes = [C.c_int32, vp, C.c_uint64, vp, vp]
     L.brng_status_string.argtypes = [C.c_int32]
     L.brng_status_string.restype = C.c_char_p
     L.brng_last_hip_error.argtypes = []
@@ -259,8 +261,13 @@ def brng_get_window(ctx: int, kind: int, unit: int):
     return base.value, ln.value, out
 
 
-def brng_set_launch(ctx: int, waves_per_block: int, persistent_blocks: int = 0) -> None:
-    _check(_lib.brng_set_launch(ctx, waves_per_block, persistent_blocks), "brng_set_launch")
+def brng_set_launch(ctx: int, waves_per_block: int) -> None:
+    _check(_lib.brng_set_launch(ctx, waves_per_block, 0), "brng_set_launch")
+
+
+def brng_convert(kind: int, words, n_words: int, out, stream=None) -> None:
+    _check(_lib.brng_convert(kind, _ptr(words), n_words, _ptr(out), _stream_handle(stream)),
+           "brng_convert")
 
 
 def brng_status_string(status: int) -> str:

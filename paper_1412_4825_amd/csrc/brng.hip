@@ -6,9 +6,7 @@
 //                    one 128-bit store per block, coalesced per wave
 //   k_step_*         one draw per chain per launch (the one-at-a-time call
 //                    of Sec. 1 with the reducible transforms of Sec. 2.1)
-//   k_gibbs<M>       all steps of every chain of one request (plain form)
-//   k_batch          many requests of any model in one persistent launch,
-//                    units pulled from a device queue (batched form)
+//   k_gibbs<M>       all steps of every chain of one request
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -87,6 +85,14 @@ __global__ __launch_bounds__(FILL_THREADS) void k_fill(Meta* meta,
         mp->wbase[KIND] = first;
         mp->wlen[KIND] = W;
     }
+}
+
+// Raw words -> base deviates (the conversion half of the engine): thread i
+// converts words [4i, 4i + 4).
+template <uint32_t KIND>
+__global__ __launch_bounds__(256) void k_convert(const uint4* words, uint64_t nblk, uint4* out) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nblk) out[i] = convert_block<KIND>(words[i]);
 }
 
 __device__ __forceinline__ uint32_t wave_in_block() {
@@ -201,9 +207,11 @@ __device__ __forceinline__ void run_unit(const DescDev& D, Meta* meta, const Poo
 }
 
 __host__ __device__ constexpr int model_lds_bytes(int model) {
-    return model == M_LDA ? WAVE_LDS_BYTES
-                          : ((model == M_TRIANGLE || model == M_EXPCHAIN) ? RING_BYTES
-                                                                         : 2 * RING_BYTES);
+    return model == M_LDA        ? WAVE_LDS_BYTES
+           : model == M_NORMEXP  ? NORMEXP_LDS_BYTES
+           : model == M_EXPCHAIN ? EXPCHAIN_LDS_BYTES
+           : model == M_GAMMA    ? 2 * RING_BYTES
+                                 : RING_BYTES;
 }
 
 // Documents the LDA kernel cannot serve are skipped: K outside [1, 256],
@@ -226,45 +234,6 @@ __global__ __launch_bounds__(512) void k_gibbs(DescDev D, Meta* meta, Pools P) {
     run_unit<MODEL>(D, meta, P, local, lds_all + w * model_lds_bytes(MODEL));
 }
 
-// Batched form: a persistent grid; each wave takes the next queue index,
-// finds its request (requests are ordered longest first) and runs that unit.
-__global__ __launch_bounds__(512) void k_batch(const DescDev* descs, uint32_t n_desc,
-                                               uint32_t n_total, uint32_t* queue, Meta* meta,
-                                               Pools P) {
-    extern __shared__ __align__(16) unsigned char lds_all[];
-    const uint32_t w = wave_in_block();
-    unsigned char* lds = lds_all + w * WAVE_LDS_BYTES;
-    for (;;) {
-        uint32_t idx = 0;
-        if (lane_id() == 0) idx = atomicAdd(queue, 1u);
-        idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
-        if (idx >= n_total) break;
-        uint32_t lo = 0, hi = n_desc - 1;  // last request with queue_first <= idx
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (descs[mid].queue_first <= idx)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const DescDev D = descs[lo];
-        const uint32_t local = idx - D.queue_first;
-        switch (D.model) {
-            case M_TRIANGLE: run_unit<M_TRIANGLE>(D, meta, P, local, lds); break;
-            case M_NORMEXP: run_unit<M_NORMEXP>(D, meta, P, local, lds); break;
-            case M_GAMMA: run_unit<M_GAMMA>(D, meta, P, local, lds); break;
-            case M_LDA:
-                if (lda_doc_ok(D, local)) run_unit<M_LDA>(D, meta, P, local, lds);
-                break;
-            case M_EXPCHAIN: run_unit<M_EXPCHAIN>(D, meta, P, local, lds); break;
-            default: break;
-        }
-    }
-}
-
-// Queue reset as a kernel node (graph-safe, unlike a memset node).
-__global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
-
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -275,14 +244,7 @@ struct brng_ctx {
     uint32_t n_units;
     void* pool[4];
     Meta* meta;
-    uint32_t* queue;
-    DescDev* d_descs;
-    DescDev* h_descs;  // pinned staging for descriptor uploads
-    uint32_t desc_cap;
-    hipEvent_t desc_done;
-    bool desc_pending;
     int wpb;
-    int persistent_blocks;
     int n_cu;
 };
 
@@ -347,10 +309,6 @@ static void free_ctx(brng_ctx* c) {
     for (int k = 0; k < 4; ++k)
         if (c->pool[k]) (void)hipFree(c->pool[k]);
     if (c->meta) (void)hipFree(c->meta);
-    if (c->queue) (void)hipFree(c->queue);
-    if (c->d_descs) (void)hipFree(c->d_descs);
-    if (c->h_descs) (void)hipHostFree(c->h_descs);
-    if (c->desc_done) (void)hipEventDestroy(c->desc_done);
     delete c;
 }
 
@@ -385,7 +343,6 @@ brng_status brng_create(const brng_config* cfg, brng_ctx** out) {
     c->stream = (hipStream_t)cfg->hip_stream;
     c->n_units = cfg->layout == BRNG_LAYOUT_CHAINS ? (cfg->n_chains + 63) / 64 : cfg->n_chains;
     c->wpb = 4;
-    c->persistent_blocks = 0;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -401,15 +358,9 @@ brng_status brng_create(const brng_config* cfg, brng_ctx** out) {
             return BRNG_E_NOMEM;
         }
     }
-    if (hipMalloc((void**)&c->meta, sizeof(Meta) * (size_t)c->n_units) != hipSuccess ||
-        hipMalloc((void**)&c->queue, sizeof(uint32_t)) != hipSuccess) {
+    if (hipMalloc((void**)&c->meta, sizeof(Meta) * (size_t)c->n_units) != hipSuccess) {
         free_ctx(c);
         return BRNG_E_NOMEM;
-    }
-    e = hipEventCreateWithFlags(&c->desc_done, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        free_ctx(c);
-        return hip_fail(e);
     }
     hipLaunchKernelGGL(k_init_meta, dim3((c->n_units + 255) / 256), dim3(256), 0, c->stream,
                        c->meta, c->n_units, cfg->seed);
@@ -561,8 +512,6 @@ static DescDev to_dev(const brng_gibbs_desc& d) {
     D.stride = d.trace_stride;
     D.offsets = d.d_offsets;
     D.ntok = d.d_ntok;
-    D.queue_first = 0;
-    D.pad = 0;
     return D;
 }
 
@@ -591,17 +540,6 @@ static brng_status launch_plain(brng_ctx* c, const DescDev& D) {
     return BRNG_OK;
 }
 
-static int batch_blocks(brng_ctx* c) {
-    if (c->persistent_blocks > 0) return c->persistent_blocks;
-    int per_cu = 0;
-    const size_t lds = (size_t)c->wpb * WAVE_LDS_BYTES;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, 64 * c->wpb, lds) !=
-            hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    return per_cu * c->n_cu;
-}
-
 brng_status brng_run_gibbs(brng_ctx* c, const brng_gibbs_desc* descs, uint32_t n_desc) {
     if (!c || !descs || n_desc == 0) return BRNG_E_ARG;
     for (uint32_t i = 0; i < n_desc; ++i) {
@@ -615,54 +553,12 @@ brng_status brng_run_gibbs(brng_ctx* c, const brng_gibbs_desc* descs, uint32_t n
     std::sort(ranges.begin(), ranges.end());
     for (uint32_t i = 1; i < n_desc; ++i)
         if (ranges[i].first < ranges[i - 1].second) return BRNG_E_ARG;
-    if (n_desc == 1) return launch_plain(c, to_dev(descs[0]));
-
-    // batched: order requests by decreasing work per unit (steps, and an LDA
-    // sweep costs about as much as 8 chain steps), then enumerate their units
-    std::vector<uint32_t> order(n_desc);
-    for (uint32_t i = 0; i < n_desc; ++i) order[i] = i;
-    auto cost = [&](uint32_t i) {
-        const double w = descs[i].model == BRNG_MODEL_LDA ? 8.0 : 1.0;
-        return w * descs[i].max_steps;
-    };
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t a, uint32_t b) { return cost(a) > cost(b); });
-    if (n_desc > c->desc_cap) {
-        if (c->desc_pending) {
-            HIPCHK(hipEventSynchronize(c->desc_done));
-            c->desc_pending = false;
-        }
-        if (c->d_descs) (void)hipFree(c->d_descs);
-        if (c->h_descs) (void)hipHostFree(c->h_descs);
-        c->d_descs = nullptr;
-        c->h_descs = nullptr;
-        c->desc_cap = 0;
-        if (hipMalloc((void**)&c->d_descs, sizeof(DescDev) * n_desc) != hipSuccess ||
-            hipHostMalloc((void**)&c->h_descs, sizeof(DescDev) * n_desc, 0) != hipSuccess)
-            return BRNG_E_NOMEM;
-        c->desc_cap = n_desc;
-    }
-    if (c->desc_pending) {  // the staging buffer may still be read by a copy
-        HIPCHK(hipEventSynchronize(c->desc_done));
-        c->desc_pending = false;
-    }
-    uint32_t total = 0;
+    // several requests: each runs its own chain kernel, back to back on the
+    // context's stream (requests are independent: their units are disjoint)
     for (uint32_t i = 0; i < n_desc; ++i) {
-        DescDev D = to_dev(descs[order[i]]);
-        D.queue_first = total;
-        total += D.n_units;
-        c->h_descs[i] = D;
+        brng_status s = launch_plain(c, to_dev(descs[i]));
+        if (s != BRNG_OK) return s;
     }
-    HIPCHK(hipMemcpyAsync(c->d_descs, c->h_descs, sizeof(DescDev) * n_desc,
-                          hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipEventRecord(c->desc_done, c->stream));
-    c->desc_pending = true;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, c->queue);
-    const int blocks = batch_blocks(c);
-    hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(64 * c->wpb),
-                       (size_t)c->wpb * WAVE_LDS_BYTES, c->stream, c->d_descs, n_desc, total,
-                       c->queue, c->meta, make_pools(c));
-    HIPCHK(hipGetLastError());
     return BRNG_OK;
 }
 
@@ -728,6 +624,27 @@ brng_status brng_get_window(brng_ctx* c, int32_t kind, uint32_t unit, void* out,
     return BRNG_OK;
 }
 
+brng_status brng_convert(int32_t kind, const uint32_t* words, uint64_t n_words, void* out,
+                         void* stream) {
+    if (kind < 0 || kind >= BRNG_NKINDS || (n_words & 3) || (n_words && (!words || !out)))
+        return BRNG_E_ARG;
+    if (((uintptr_t)words & 15) || ((uintptr_t)out & 15)) return BRNG_E_ARG;
+    const uint64_t nblk = n_words / 4;
+    if (!nblk) return BRNG_OK;
+    const dim3 grid((unsigned)((nblk + 255) / 256));
+    hipStream_t st = (hipStream_t)stream;
+    const uint4* w = (const uint4*)words;
+    uint4* o = (uint4*)out;
+    switch (kind) {
+        case BRNG_U: hipLaunchKernelGGL(k_convert<KIND_U>, grid, dim3(256), 0, st, w, nblk, o); break;
+        case BRNG_N: hipLaunchKernelGGL(k_convert<KIND_N>, grid, dim3(256), 0, st, w, nblk, o); break;
+        case BRNG_E: hipLaunchKernelGGL(k_convert<KIND_E>, grid, dim3(256), 0, st, w, nblk, o); break;
+        default: hipLaunchKernelGGL(k_convert<KIND_U64>, grid, dim3(256), 0, st, w, nblk, o); break;
+    }
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
 brng_status brng_get_info(const brng_ctx* c, uint32_t* n_units, uint32_t* window4) {
     if (!c) return BRNG_E_ARG;
     if (n_units) *n_units = c->n_units;
@@ -736,11 +653,9 @@ brng_status brng_get_info(const brng_ctx* c, uint32_t* n_units, uint32_t* window
     return BRNG_OK;
 }
 
-brng_status brng_set_launch(brng_ctx* c, int32_t wpb, int32_t persistent_blocks) {
-    if (!c || !(wpb == 1 || wpb == 2 || wpb == 4 || wpb == 8) || persistent_blocks < 0)
-        return BRNG_E_ARG;
+brng_status brng_set_launch(brng_ctx* c, int32_t wpb, int32_t reserved) {
+    if (!c || !(wpb == 1 || wpb == 2 || wpb == 4 || wpb == 8) || reserved != 0) return BRNG_E_ARG;
     c->wpb = wpb;
-    c->persistent_blocks = persistent_blocks;
     return BRNG_OK;
 }
 

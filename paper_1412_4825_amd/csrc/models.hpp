@@ -29,8 +29,6 @@ struct DescDev {
     int64_t stride;
     const int32_t* offsets;
     const int32_t* ntok;
-    uint32_t queue_first;  // first index of this request in the batched queue
-    uint32_t pad;
 };
 
 enum : int32_t { M_TRIANGLE = 0, M_NORMEXP = 1, M_GAMMA = 2, M_LDA = 3, M_EXPCHAIN = 4 };
@@ -125,67 +123,154 @@ __device__ void unit_triangle(const DescDev& D, Meta* mp, const Pools& P, uint32
 }
 
 // ---------------------------------------------------------------------------
+// Output staging for the full-occupancy paths: four steps of one output go
+// through LDS so that each lane stores 16 bytes (four consecutive chains of
+// one step) instead of 4 bytes per step.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool aligned16(const void* p, int64_t stride) {
+    return ((uintptr_t)p & 15) == 0 && (stride & 3) == 0;
+}
+
+// ob: 256 floats of LDS holding [step i][lane] for the block's four steps.
+__device__ __forceinline__ void store4(float* ob, float* trace, int64_t stride, uint32_t slot0,
+                                       uint32_t t0) {
+    const uint32_t lane = lane_id();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const float4 v = reinterpret_cast<const float4*>(ob)[lane];
+    float* dst = trace + (size_t)(t0 + (lane >> 4)) * stride + slot0 + 4 * (lane & 15);
+    *reinterpret_cast<float4*>(dst) = v;
+}
+
+// ---------------------------------------------------------------------------
 // Normal/exponential chain: s' = 0.9 s + (0.5 + |s|) z, e = E / (1 + s'^2).
 // Fresh chains draw s_0 as their first Gaussian.
 // ---------------------------------------------------------------------------
+constexpr int NORMEXP_LDS_BYTES = 2 * PIPE_RING_BYTES + 2048;
+
 __device__ void unit_normexp(const DescDev& D, Meta* mp, const Pools& P, uint32_t local,
                              unsigned char* lds) {
     const uint32_t lane = lane_id();
-    const uint32_t slot = local * 64 + lane;
+    const uint32_t slot0 = local * 64;
+    const uint32_t slot = slot0 + lane;
     const bool in0 = slot < D.n_chains;
     const uint32_t chain = in0 ? (D.perm ? (uint32_t)D.perm[slot] : slot) : 0;
     const bool in = in0 && chain < D.n_chains;  // a bad permutation entry idles the lane
     const int32_t L = in ? (D.steps ? D.steps[chain] : D.max_steps) : 0;
     const bool fresh = !(D.flags & FLAG_RESUME);
-    const Meta m = open_meta(D, mp, local);
+    Meta m = open_meta(D, mp, local);
     const uint32_t gu = D.unit_base + local;
-    StagedReader<KIND_N> rn;
-    StagedReader<KIND_E> re;
-    rn.open(m, P.n + (size_t)gu * P.W[KIND_N], P.W[KIND_N], reinterpret_cast<float*>(lds));
-    re.open(m, P.e + (size_t)gu * P.W[KIND_E], P.W[KIND_E],
-            reinterpret_cast<float*>(lds + RING_BYTES));
+    float* pool_n = P.n + (size_t)gu * P.W[KIND_N];
+    float* pool_e = P.e + (size_t)gu * P.W[KIND_E];
     float* st = reinterpret_cast<float*>(D.state);
-    float s;
-    if (fresh)
-        s = rn.take(in);
-    else
-        s = in ? st[chain] : 0.0f;
     float* ts = reinterpret_cast<float*>(D.trace);
     float* te = reinterpret_cast<float*>(D.trace2);
     const int32_t smax = D.max_steps;
-    const bool full = (wave_ballot(in && L >= smax) == ~0ull);
-    if (full && ts && te) {
-        // every lane runs every step: no ballots, four steps per ring check
-        int32_t t = 0;
-        for (; t + 4 <= smax; t += 4) {
-            rn.ensure(rn.cur + 256);
-            re.ensure(re.cur + 256);
-            float z[4], ee[4];
+    const bool full = smax > 0 && P.W[KIND_N] >= LanePipe<KIND_N>::MIN_WINDOW &&
+                      P.W[KIND_E] >= LanePipe<KIND_E>::MIN_WINDOW &&
+                      (wave_ballot(in && L >= smax) == ~0ull);
+    float s;
+    if (full) {
+        if (fresh) {  // s_0: one call on the Gaussian pool
+            DirectReader<KIND_N> r0;
+            r0.open(m, pool_n, P.W[KIND_N]);
+            s = r0.take(true);
+            m.cur[KIND_N] = r0.cur;
+            m.wbase[KIND_N] = r0.wbase;
+            m.wlen[KIND_N] = r0.wlen;
+        } else {
+            s = st[chain];
+        }
+        LanePipe<KIND_N> pn;
+        LanePipe<KIND_E> pe;
+        pn.open(m, pool_n, P.W[KIND_N], reinterpret_cast<float*>(lds), (uint32_t)smax);
+        pe.open(m, pool_e, P.W[KIND_E], reinterpret_cast<float*>(lds + PIPE_RING_BYTES),
+                (uint32_t)smax);
+        float* ob = reinterpret_cast<float*>(lds + 2 * PIPE_RING_BYTES);
+        const bool vec = ts && te && aligned16(ts, D.stride) && aligned16(te, D.stride);
+        const uint32_t blocks = ((uint32_t)smax + 3) / 4;
+        const uint32_t nfast =
+            (uint32_t)min((uint64_t)((uint32_t)smax / 4), min(pn.fast_blocks(), pe.fast_blocks()));
+        // one block: 4 steps (fewer in the last block)
+        auto block = [&](auto jc, uint32_t b, auto fastc, auto vecc) {
+            constexpr int j = decltype(jc)::value;
+            constexpr bool FAST = decltype(fastc)::value;
+            constexpr bool VEC = decltype(vecc)::value;
+            if constexpr (FAST) {
+                pn.template advance_fast<j>(b);
+                pe.template advance_fast<j>(b);
+            } else {
+                pn.template advance<j>(b);
+                pe.template advance<j>(b);
+            }
+            const uint32_t t0 = 4 * b;
+            const uint32_t nc = FAST ? 4u : min(4u, (uint32_t)smax - t0);
+            float sp[4], ev[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                z[i] = rn.ring[(rn.cur + 64 * i + lane) & (rn.R - 1)];
-                ee[i] = re.ring[(re.cur + 64 * i + lane) & (re.R - 1)];
+                if (FAST || (uint32_t)i < nc) {
+                    const float z = pn.get(i);
+                    const float e = pe.get(i);
+                    sp[i] = fmaf(0.5f + fabsf(s), z, 0.9f * s);
+                    ev[i] = e / fmaf(sp[i], sp[i], 1.0f);
+                    s = sp[i];
+                }
             }
-            rn.cur += 256;
-            re.cur += 256;
+            if constexpr (FAST && VEC) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float sp = fmaf(0.5f + fabsf(s), z[i], 0.9f * s);
-                const float lam = fmaf(sp, sp, 1.0f);
-                ts[(size_t)(t + i) * D.stride + slot] = sp;
-                te[(size_t)(t + i) * D.stride + slot] = ee[i] / lam;
-                s = sp;
+                for (int i = 0; i < 4; ++i) {
+                    ob[64 * i + lane] = sp[i];
+                    ob[256 + 64 * i + lane] = ev[i];
+                }
+                store4(ob, ts, D.stride, slot0, t0);
+                store4(ob + 256, te, D.stride, slot0, t0);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (FAST || (uint32_t)i < nc) {
+                        if (ts) ts[(size_t)(t0 + i) * D.stride + slot] = sp[i];
+                        if (te) te[(size_t)(t0 + i) * D.stride + slot] = ev[i];
+                    }
+                }
             }
-        }
-        for (; t < smax; ++t) {
-            const float z = rn.take_all();
-            const float sp = fmaf(0.5f + fabsf(s), z, 0.9f * s);
-            const float e = re.take_all();
-            ts[(size_t)t * D.stride + slot] = sp;
-            te[(size_t)t * D.stride + slot] = e / fmaf(sp, sp, 1.0f);
-            s = sp;
-        }
+            pn.consume(nc);
+            pe.consume(nc);
+        };
+        auto run = [&](auto vecc) {
+            uint32_t sb = 0;
+            for (; sb + PIPE_DEPTH <= nfast; sb += PIPE_DEPTH) {  // branch-free body
+                pn.prepare(sb);
+                pe.prepare(sb);
+                static_for<0, PIPE_DEPTH>([&](auto jc) {
+                    block(jc, sb + decltype(jc)::value, std::true_type{}, vecc);
+                });
+            }
+            for (; sb < blocks; sb += PIPE_DEPTH) {  // the last few blocks
+                pn.prepare(sb);
+                pe.prepare(sb);
+                static_for<0, PIPE_DEPTH>([&](auto jc) {
+                    const uint32_t b = sb + decltype(jc)::value;
+                    if (b < blocks) block(jc, b, std::false_type{}, vecc);
+                });
+            }
+        };
+        if (vec)
+            run(std::true_type{});
+        else
+            run(std::false_type{});
+        st[chain] = s;
+        pn.close(*mp);
+        pe.close(*mp);
     } else {
+        StagedReader<KIND_N> rn;
+        StagedReader<KIND_E> re;
+        rn.open(m, pool_n, P.W[KIND_N], reinterpret_cast<float*>(lds));
+        re.open(m, pool_e, P.W[KIND_E], reinterpret_cast<float*>(lds + RING_BYTES));
+        if (fresh)
+            s = rn.take(in);
+        else
+            s = in ? st[chain] : 0.0f;
         for (int32_t t = 0; t < smax; ++t) {
             const bool act = in && t < L;
             if (wave_ballot(act) == 0) break;
@@ -198,10 +283,10 @@ __device__ void unit_normexp(const DescDev& D, Meta* mp, const Pools& P, uint32_
                 s = sp;
             }
         }
+        if (in) st[chain] = s;
+        rn.close(*mp);
+        re.close(*mp);
     }
-    if (in) st[chain] = s;
-    rn.close(*mp);
-    re.close(*mp);
     store_key(mp, m);
 }
 
@@ -209,37 +294,116 @@ __device__ void unit_normexp(const DescDev& D, Meta* mp, const Pools& P, uint32_
 // Exponential chain (served form's exponential kind): e' = E / (1 + e^2).
 // Fresh chains draw e_0 as their first exponential.
 // ---------------------------------------------------------------------------
+constexpr int EXPCHAIN_LDS_BYTES = PIPE_RING_BYTES + 1024;
+
 __device__ void unit_expchain(const DescDev& D, Meta* mp, const Pools& P, uint32_t local,
                               unsigned char* lds) {
     const uint32_t lane = lane_id();
-    const uint32_t slot = local * 64 + lane;
+    const uint32_t slot0 = local * 64;
+    const uint32_t slot = slot0 + lane;
     const bool in0 = slot < D.n_chains;
     const uint32_t chain = in0 ? (D.perm ? (uint32_t)D.perm[slot] : slot) : 0;
-    const bool in = in0 && chain < D.n_chains;  // a bad permutation entry idles the lane
+    const bool in = in0 && chain < D.n_chains;
     const int32_t L = in ? (D.steps ? D.steps[chain] : D.max_steps) : 0;
     const bool fresh = !(D.flags & FLAG_RESUME);
-    const Meta m = open_meta(D, mp, local);
+    Meta m = open_meta(D, mp, local);
     const uint32_t gu = D.unit_base + local;
-    StagedReader<KIND_E> re;
-    re.open(m, P.e + (size_t)gu * P.W[KIND_E], P.W[KIND_E], reinterpret_cast<float*>(lds));
+    float* pool_e = P.e + (size_t)gu * P.W[KIND_E];
     float* st = reinterpret_cast<float*>(D.state);
-    float v;
-    if (fresh)
-        v = re.take(in);
-    else
-        v = in ? st[chain] : 0.0f;
     float* tr = reinterpret_cast<float*>(D.trace);
-    for (int32_t t = 0; t < D.max_steps; ++t) {
-        const bool act = in && t < L;
-        if (wave_ballot(act) == 0) break;
-        const float e = re.take(act);
-        if (act) {
-            v = e / fmaf(v, v, 1.0f);
-            if (tr) tr[(size_t)t * D.stride + slot] = v;
+    const int32_t smax = D.max_steps;
+    const bool full = smax > 0 && P.W[KIND_E] >= LanePipe<KIND_E>::MIN_WINDOW &&
+                      (wave_ballot(in && L >= smax) == ~0ull);
+    float v;
+    if (full) {
+        if (fresh) {
+            DirectReader<KIND_E> r0;
+            r0.open(m, pool_e, P.W[KIND_E]);
+            v = r0.take(true);
+            m.cur[KIND_E] = r0.cur;
+            m.wbase[KIND_E] = r0.wbase;
+            m.wlen[KIND_E] = r0.wlen;
+        } else {
+            v = st[chain];
         }
+        LanePipe<KIND_E> pe;
+        pe.open(m, pool_e, P.W[KIND_E], reinterpret_cast<float*>(lds), (uint32_t)smax);
+        float* ob = reinterpret_cast<float*>(lds + PIPE_RING_BYTES);
+        const bool vec = tr && aligned16(tr, D.stride);
+        const uint32_t blocks = ((uint32_t)smax + 3) / 4;
+        const uint32_t nfast = (uint32_t)min((uint64_t)((uint32_t)smax / 4), pe.fast_blocks());
+        auto block = [&](auto jc, uint32_t b, auto fastc, auto vecc) {
+            constexpr int j = decltype(jc)::value;
+            constexpr bool FAST = decltype(fastc)::value;
+            constexpr bool VEC = decltype(vecc)::value;
+            if constexpr (FAST)
+                pe.template advance_fast<j>(b);
+            else
+                pe.template advance<j>(b);
+            const uint32_t t0 = 4 * b;
+            const uint32_t nc = FAST ? 4u : min(4u, (uint32_t)smax - t0);
+            float ev[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (FAST || (uint32_t)i < nc) {
+                    v = pe.get(i) / fmaf(v, v, 1.0f);
+                    ev[i] = v;
+                }
+            }
+            if constexpr (FAST && VEC) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) ob[64 * i + lane] = ev[i];
+                store4(ob, tr, D.stride, slot0, t0);
+            } else {
+                if (tr) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (FAST || (uint32_t)i < nc) tr[(size_t)(t0 + i) * D.stride + slot] = ev[i];
+                }
+            }
+            pe.consume(nc);
+        };
+        auto run = [&](auto vecc) {
+            uint32_t sb = 0;
+            for (; sb + PIPE_DEPTH <= nfast; sb += PIPE_DEPTH) {
+                pe.prepare(sb);
+                static_for<0, PIPE_DEPTH>([&](auto jc) {
+                    block(jc, sb + decltype(jc)::value, std::true_type{}, vecc);
+                });
+            }
+            for (; sb < blocks; sb += PIPE_DEPTH) {
+                pe.prepare(sb);
+                static_for<0, PIPE_DEPTH>([&](auto jc) {
+                    const uint32_t b = sb + decltype(jc)::value;
+                    if (b < blocks) block(jc, b, std::false_type{}, vecc);
+                });
+            }
+        };
+        if (vec)
+            run(std::true_type{});
+        else
+            run(std::false_type{});
+        st[chain] = v;
+        pe.close(*mp);
+    } else {
+        StagedReader<KIND_E> re;
+        re.open(m, pool_e, P.W[KIND_E], reinterpret_cast<float*>(lds));
+        if (fresh)
+            v = re.take(in);
+        else
+            v = in ? st[chain] : 0.0f;
+        for (int32_t t = 0; t < smax; ++t) {
+            const bool act = in && t < L;
+            if (wave_ballot(act) == 0) break;
+            const float e = re.take(act);
+            if (act) {
+                v = e / fmaf(v, v, 1.0f);
+                if (tr) tr[(size_t)t * D.stride + slot] = v;
+            }
+        }
+        if (in) st[chain] = v;
+        re.close(*mp);
     }
-    if (in) st[chain] = v;
-    re.close(*mp);
     store_key(mp, m);
 }
 

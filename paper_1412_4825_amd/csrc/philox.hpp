@@ -32,8 +32,9 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
         const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        // three-input xor in one gfx950 instruction (truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -60,24 +61,53 @@ __device__ __forceinline__ double u01d(uint32_t wa, uint32_t wb) {
     return (double)(2 * k + 1) * 0x1p-53;
 }
 
-// E = -ln U.
-__device__ __forceinline__ float expo(uint32_t w) { return -logf(u01(w)); }
+// E = -ln U = -ln 2 * log2 U.  U is a normal fp32 number in [2^-24, 1), so
+// the hardware base-2 logarithm needs no range handling; one product with ln 2
+// follows (a few ulp in all).
+__device__ __forceinline__ float neg_ln(float u) {
+    return __builtin_amdgcn_logf(u) * -0.693147180559945309f;
+}
+__device__ __forceinline__ float expo(uint32_t w) { return neg_ln(u01(w)); }
 
-// Box-Muller: radius from the first word, angle 2 pi Ub from the second;
-// cosine goes to the even entry, sine to the odd one.  sincospi takes the
-// exact argument 2 Ub, so no rounding of 2 pi enters.
-__device__ __forceinline__ float2 box_muller(uint32_t wa, uint32_t wb) {
-    const float r = sqrtf(-2.0f * logf(u01(wa)));
-    float s, c;
-    sincospif(2.0f * u01(wb), &s, &c);
-    return make_float2(r * c, r * s);
+// sin and cos of 2 pi u for u on the uniform grid (u in (0,1)).  The
+// reduction is exact: t = 4u and k = rint(t) are exact, f = t - k is exact
+// and lies in [-1/2, 1/2], so 2 pi u = (pi/2)(k + f) and only a = (pi/2) f,
+// |a| <= pi/4, goes through the Taylor polynomials (the first omitted terms
+// are below 3e-9 relative).  The quadrant k mod 4 rotates the pair.
+__device__ __forceinline__ float2 sincos_2pi(float u) {
+    const float t = 4.0f * u;
+    const float kf = rintf(t);
+    const float f = t - kf;
+    const float a = f * 1.57079632679489662f;
+    const float a2 = a * a;
+    float s = fmaf(a2, 2.75573192e-6f, -1.98412698e-4f);  // 1/9!, -1/7!
+    s = fmaf(a2, s, 8.33333333e-3f);                       // 1/5!
+    s = fmaf(a2, s, -1.66666667e-1f);                      // -1/3!
+    s = fmaf(a2 * a, s, a);
+    float c = fmaf(a2, 2.48015873e-5f, -1.38888889e-3f);  // 1/8!, -1/6!
+    c = fmaf(a2, c, 4.16666667e-2f);                       // 1/4!
+    c = fmaf(a2, c, -0.5f);
+    c = fmaf(a2, c, 1.0f);
+    const int k = (int)kf;
+    const float ss = (k & 1) ? c : s;  // sin(theta + k pi/2)
+    const float cc = (k & 1) ? s : c;
+    const float sn = (k & 2) ? -ss : ss;
+    const float cs = ((k + 1) & 2) ? -cc : cc;
+    return make_float2(sn, cs);
 }
 
-// One block -> the raw bits of its entries (four floats, or two doubles for
-// U64), ready for one 128-bit store.
+// Box-Muller: radius from the first word, angle 2 pi Ub from the second;
+// cosine goes to the even entry, sine to the odd one.
+__device__ __forceinline__ float2 box_muller(uint32_t wa, uint32_t wb) {
+    const float r = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(u01(wa)) * -1.38629436111989061f);
+    const float2 sc = sincos_2pi(u01(wb));
+    return make_float2(r * sc.y, r * sc.x);
+}
+
+// Four words -> the raw bits of their entries (four floats, or two doubles
+// for U64), ready for one 128-bit store.
 template <uint32_t KIND>
-__device__ __forceinline__ uint4 gen_block(const Key& key, uint64_t block) {
-    const uint4 w = block_words(key, KIND, block);
+__device__ __forceinline__ uint4 convert_block(const uint4 w) {
     if constexpr (KIND == KIND_U) {
         return make_uint4(__float_as_uint(u01(w.x)), __float_as_uint(u01(w.y)),
                           __float_as_uint(u01(w.z)), __float_as_uint(u01(w.w)));
@@ -96,6 +126,12 @@ __device__ __forceinline__ uint4 gen_block(const Key& key, uint64_t block) {
         const uint64_t ib = (uint64_t)__double_as_longlong(b);
         return make_uint4((uint32_t)ia, (uint32_t)(ia >> 32), (uint32_t)ib, (uint32_t)(ib >> 32));
     }
+}
+
+// Pool block `block` of (key, KIND), converted.
+template <uint32_t KIND>
+__device__ __forceinline__ uint4 gen_block(const Key& key, uint64_t block) {
+    return convert_block<KIND>(block_words(key, KIND, block));
 }
 
 template <uint32_t KIND> struct KindTraits {

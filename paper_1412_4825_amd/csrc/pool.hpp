@@ -15,6 +15,8 @@
 //     blocking refill, Sec. 2.2), with the same Philox blocks a bulk fill
 //     would write, so results never depend on the window length.
 #pragma once
+#include <type_traits>
+
 #include "philox.hpp"
 
 namespace brng {
@@ -123,10 +125,11 @@ struct DirectReader {
 
 // ---------------------------------------------------------------------------
 // Staged reader: the window streams through an LDS ring of two chunks
-// (a chunk = one 16-byte load per lane = 256 floats or 128 doubles), with
-// DEPTH further chunks in flight in registers.
+// (a chunk = one 16-byte load per lane = 256 floats or 128 doubles), the
+// next chunk already in flight in a register while the current one is read.
+// Runs on this path (uneven lengths, rejection loops) keep several waves per
+// SIMD busy, which hides the rest of the memory latency.
 // ---------------------------------------------------------------------------
-constexpr int STAGE_DEPTH = 3;
 constexpr int RING_BYTES = 2048;  // two chunks
 
 template <uint32_t KIND>
@@ -140,7 +143,7 @@ struct StagedReader {
     Key key;
     uint64_t wbase, cur, staged, front;
     uint32_t wlen, W;
-    uint4 pf[STAGE_DEPTH];
+    uint4 pf;  // chunk `staged`, in flight
 
     __device__ __forceinline__ uint4 load_chunk(uint64_t f) {
         if (f < wbase || f + CH > wbase + wlen) {
@@ -160,21 +163,14 @@ struct StagedReader {
         cur = m.cur[KIND];
         W = Wk;
         staged = cur & ~(uint64_t)(CH - 1);
-        front = staged;
-#pragma unroll
-        for (int i = 0; i < STAGE_DEPTH; ++i) {
-            pf[i] = load_chunk(front);
-            front += CH;
-        }
+        pf = load_chunk(staged);
+        front = staged + CH;
     }
     // Make entries [.., need) readable from the ring.
     __device__ __forceinline__ void ensure(uint64_t need) {
         while (staged < need) {
-            uint4* dst = reinterpret_cast<uint4*>(ring + (staged & (R - 1)));
-            dst[lane_id()] = pf[0];
-#pragma unroll
-            for (int i = 0; i + 1 < STAGE_DEPTH; ++i) pf[i] = pf[i + 1];
-            pf[STAGE_DEPTH - 1] = load_chunk(front);
+            reinterpret_cast<uint4*>(ring + (staged & (R - 1)))[lane_id()] = pf;
+            pf = load_chunk(front);
             front += CH;
             staged += CH;
         }
@@ -192,16 +188,127 @@ struct StagedReader {
         cur += n;
         return active ? v : T(0);
     }
-    // A call with every lane active (no ballot needed).
-    __device__ __forceinline__ T take_all() {
-        ensure(cur + 64);
-        const T v = ring[(cur + lane_id()) & (R - 1)];
-        cur += 64;
-        return v;
-    }
     __device__ void close(Meta& m) const {
         if (lane_id() == 0) {
             m.cur[KIND] = cur;
+            m.wbase[KIND] = wbase;
+            m.wlen[KIND] = wlen;
+        }
+    }
+};
+
+// Compile-time loop: f(integral_constant<int, J>) for J = I .. N-1.
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lane pipe: the reader for runs where all 64 lanes take one entry per call
+// for a known number of calls.  A "block" consumes one chunk's worth of
+// entries (CH / 64 calls).  Chunks are loaded PIPE_DEPTH blocks ahead into
+// registers that the caller indexes statically (the block loop is unrolled by
+// PIPE_DEPTH with static_for), so every load has PIPE_DEPTH blocks of work
+// to hide behind and no register is ever indexed at run time.  The window is
+// checked once per PIPE_DEPTH blocks (cover), so the unrolled body holds no
+// branch with stores in it and the compiler can count outstanding loads.
+// The LDS ring holds four chunks; a block reads from two of them.
+// ---------------------------------------------------------------------------
+constexpr int PIPE_DEPTH = 8;
+constexpr int PIPE_RING_BYTES = 4096;
+
+template <uint32_t KIND>
+struct LanePipe {
+    using T = typename KindTraits<KIND>::T;
+    static constexpr int EPL = KindTraits<KIND>::EPB;
+    static constexpr uint32_t CH = 64 * EPL;
+    static constexpr uint32_t R = 4 * CH;
+    // smallest window the pipe can work with: PIPE_DEPTH + 1 chunks
+    static constexpr uint32_t MIN_WINDOW = (PIPE_DEPTH + 1) * CH;
+    T* win;
+    T* ring;
+    Key key;
+    uint64_t wbase, pos, next, last;
+    uint32_t wlen, W;
+    uint4 pf[PIPE_DEPTH];
+
+    // Make the window hold chunks [c, c_end] (c_end - c < W / CH).
+    __device__ __forceinline__ void cover(uint64_t c, uint64_t c_end) {
+        const uint64_t f = c * CH, g = (c_end + 1) * CH;
+        if (f < wbase || g > wbase + wlen) {
+            refill_window<KIND>(win, key, f, W);
+            wbase = f;
+            wlen = W;
+        }
+    }
+    __device__ __forceinline__ uint4 raw_load(uint64_t c) const {
+        return reinterpret_cast<const uint4*>(win + (c * CH - wbase))[lane_id()];
+    }
+    __device__ __forceinline__ void put(uint64_t c, const uint4& v) {
+        reinterpret_cast<uint4*>(ring + ((c * CH) & (R - 1)))[lane_id()] = v;
+    }
+    // Prepare for `calls` calls of 64 entries each (calls >= 1).
+    __device__ void open(const Meta& m, T* pool_unit, uint32_t Wk, T* lds_ring, uint32_t calls) {
+        win = pool_unit;
+        ring = lds_ring;
+        key = meta_key(m);
+        wbase = m.wbase[KIND];
+        wlen = m.wlen[KIND];
+        W = Wk;
+        pos = m.cur[KIND];
+        const uint64_t c0 = pos / CH;
+        last = (pos + 64ull * calls - 1) / CH;
+        cover(c0, min(last, c0 + PIPE_DEPTH));
+        put(c0, raw_load(c0));
+        next = c0 + 1;
+        static_for<0, PIPE_DEPTH>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            if (next + j <= last) pf[j] = raw_load(next + j);
+        });
+    }
+    // Before blocks sb .. sb + PIPE_DEPTH - 1: the window must hold the
+    // chunks they will prefetch.
+    __device__ __forceinline__ void prepare(uint64_t sb) {
+        const uint64_t c = next + sb + PIPE_DEPTH;
+        if (c <= last) cover(c, min(last, c + PIPE_DEPTH - 1));
+    }
+    // Before block b (J = b % PIPE_DEPTH): stage chunk next + b from register
+    // slot J and load chunk next + b + PIPE_DEPTH into it.
+    template <int J>
+    __device__ __forceinline__ void advance(uint64_t b) {
+        const uint64_t c = next + b;
+        if (c <= last) put(c, pf[J]);
+        if (c + PIPE_DEPTH <= last) pf[J] = raw_load(c + PIPE_DEPTH);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // advance() for a block known to be inside the run with its prefetch
+    // inside it too: no conditions at all.
+    template <int J>
+    __device__ __forceinline__ void advance_fast(uint64_t b) {
+        const uint64_t c = next + b;
+        put(c, pf[J]);
+        pf[J] = raw_load(c + PIPE_DEPTH);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // Number of leading blocks for which advance_fast is valid.
+    __device__ __forceinline__ uint64_t fast_blocks() const {
+        return (last >= next + PIPE_DEPTH) ? last - next - PIPE_DEPTH + 1 : 0;
+    }
+    // Entry of call i of the current block for this lane.
+    __device__ __forceinline__ T get(int i) const {
+        return ring[(pos + 64u * (uint32_t)i + lane_id()) & (R - 1)];
+    }
+    __device__ __forceinline__ void consume(uint32_t calls) { pos += 64ull * calls; }
+    __device__ void close(Meta& m) const {
+        if (lane_id() == 0) {
+            m.cur[KIND] = pos;
             m.wbase[KIND] = wbase;
             m.wlen[KIND] = wlen;
         }

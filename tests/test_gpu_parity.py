@@ -166,9 +166,9 @@ def test_step_dirichlet_ragged(dev):
         b.brng_destroy(ctx)
 
 
-def _gibbs(ctx, model, n, state, steps, seed, dev, trace=None, trace2=None, stride=0, **kw):
+def _gibbs(ctx, model, n, state, max_steps, seed, dev, trace=None, trace2=None, stride=0, **kw):
     b = _b()
-    d = b.gibbs_desc(model, n, state, max_steps=steps, seed=seed, trace=trace, trace2=trace2,
+    d = b.gibbs_desc(model, n, state, max_steps=max_steps, seed=seed, trace=trace, trace2=trace2,
                      trace_stride=stride, **kw)
     b.brng_run_gibbs(ctx, d)
 
@@ -196,12 +196,18 @@ def test_triangle_full_size_bit_exact(dev):
         b.brng_destroy(ctx)
 
 
-def test_normexp_chains(dev):
+NORMEXP_WINDOWS = [[512, 512, 512, 512], [0, 4096, 4096, 0], [0, 65536, 65536, 0]]
+
+
+@pytest.mark.parametrize("window", NORMEXP_WINDOWS)
+def test_normexp_chains(dev, window):
+    """Windows below 2,304 entries take the general (ballot) path, larger
+    ones the pipelined full-wave path; both must match the oracle."""
     import torch
     b = _b()
-    n, steps, seed = 2048 + 40, 300, 5
-    _say("normexp", n, steps, seed)
-    ctx = _ctx(seed, n, W_SMALL)
+    n, steps, seed = 2048 + 40, 301, 5
+    _say("normexp", n, steps, seed, window)
+    ctx = _ctx(seed, n, window)
     st = torch.zeros(n, dtype=torch.float32, device=dev)
     ts = torch.zeros((steps, n), dtype=torch.float32, device=dev)
     te = torch.zeros((steps, n), dtype=torch.float32, device=dev)
@@ -211,20 +217,45 @@ def test_normexp_chains(dev):
         gs, ge = _np(ts), _np(te)
         ok_s = within(gs, r["strace"], r["stol"])
         ok_e = within(ge, r["etrace"], r["etol"])
-        frac = 1.0 - (ok_s.mean() + ok_e.mean()) / 2
-        print("normexp out-of-bound fraction", frac, flush=True)
         assert ok_s.all() and ok_e.all()
         assert np.array_equal(b.brng_get_cursors(ctx), r["cursors"])
     finally:
         b.brng_destroy(ctx)
 
 
-def test_expchain(dev):
+def test_normexp_paths_bitwise_equal(dev):
+    """The general and the pipelined path give the same bits, also when a
+    run is resumed from the other path's cursors, and for an unaligned
+    trace stride (scalar stores)."""
     import torch
     b = _b()
-    n, steps, seed = 640, 200, 8
-    _say("expchain", n, steps, seed)
-    ctx = _ctx(seed, n, W_SMALL)
+    n, seed = 64 * 20, 17
+    outs = []
+    for window, stride in (([0, 512, 512, 0], n), ([0, 2560, 2560, 0], n), ([0, 65536, 65536, 0], n + 1)):
+        _say("normexp paths", window, stride)
+        ctx = _ctx(seed, n, window)
+        st = torch.zeros(n, dtype=torch.float32, device=dev)
+        ts = torch.zeros((150, stride), dtype=torch.float32, device=dev)
+        te = torch.zeros((150, stride), dtype=torch.float32, device=dev)
+        try:
+            _gibbs(ctx, b.BRNG_MODEL_NORMEXP, n, st, 77, seed, dev, ts, te, stride)
+            _gibbs(ctx, b.BRNG_MODEL_NORMEXP, n, st, 73, seed, dev, ts[77:], te[77:], stride,
+                   flags=b.BRNG_FLAG_RESUME)
+            outs.append((_np(ts)[:, :n], _np(te)[:, :n], _np(st), b.brng_get_cursors(ctx)))
+        finally:
+            b.brng_destroy(ctx)
+    for o in outs[1:]:
+        for x, y in zip(o, outs[0]):
+            assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("window", [[512, 512, 512, 512], [0, 0, 2560, 0]])
+def test_expchain(dev, window):
+    import torch
+    b = _b()
+    n, steps, seed = 640, 203, 8
+    _say("expchain", n, steps, seed, window)
+    ctx = _ctx(seed, n, window)
     st = torch.zeros(n, dtype=torch.float32, device=dev)
     te = torch.zeros((steps, n), dtype=torch.float32, device=dev)
     try:
@@ -343,9 +374,9 @@ def test_step_api_equals_chain_kernel(dev):
         b.brng_destroy(ctx)
 
 
-def test_batched_equals_alone_and_resume(dev):
-    """Two requests in one persistent launch give the same bits as each run
-    alone; a run split in two with RESUME equals the straight run."""
+def test_multi_request_equals_alone_and_resume(dev):
+    """Two requests in one call give the same bits as each run alone; a run
+    split in two with RESUME equals the straight run."""
     import torch
     b = _b()
     seed_a, seed_b = 41, 42
@@ -367,7 +398,7 @@ def test_batched_equals_alone_and_resume(dev):
         finally:
             b.brng_destroy(ctx)
 
-    _say("batched mix")
+    _say("multi-request")
     ga, ala = alone_gamma()
     sb, stb = alone_normexp()
     units_a = (n_a + 63) // 64
@@ -398,3 +429,42 @@ def test_batched_equals_alone_and_resume(dev):
         assert np.array_equal(_np(st_c), stb)
     finally:
         b.brng_destroy(ctx)
+
+
+def _grid_words(seed, low_random=True):
+    """All 2^23 uniform grid points (top 23 bits), random low 9 bits."""
+    k = np.arange(1 << 23, dtype=np.uint64) << np.uint64(9)
+    low = np.random.default_rng(seed).integers(0, 512, size=k.size, dtype=np.uint64)
+    return (k | low).astype(np.uint32)
+
+
+def _convert_gpu(dev, kind, words):
+    import torch
+    b = _b()
+    n = words.size
+    tw = _t(words.view(np.int32), dev)
+    out = torch.zeros(n // 2 if kind == 3 else n, dtype=torch.float64 if kind == 3 else torch.float32,
+                      device=dev)
+    b.brng_convert(kind, tw, n, out, torch.cuda.current_stream())
+    return _np(out)
+
+
+def test_conversions_exhaustive_grid(dev):
+    """Every uniform grid value through each conversion: U bit-exact; -ln U
+    within the fp32 bar at every grid point; Box-Muller with each word of the
+    pair running over the whole grid."""
+    _say("convert grid")
+    w = _grid_words(1)
+    assert np.array_equal(_convert_gpu(dev, 0, w).astype(np.float64), oracle.convert(0, w))
+    ref = oracle.convert(2, w)
+    got = _convert_gpu(dev, 2, w)
+    bad = ~within(got, ref, tol_of(ref))
+    assert not bad.any(), (np.flatnonzero(bad)[:5], got[bad][:5], ref[bad][:5])
+    rnd = np.random.default_rng(2).integers(0, 2**32, size=w.size, dtype=np.uint64).astype(np.uint32)
+    for pair in (np.stack([w, rnd], 1).ravel(), np.stack([rnd, w], 1).ravel()):
+        ref = oracle.convert(1, pair)
+        got = _convert_gpu(dev, 1, pair)
+        bad = ~within(got, ref, tol_of(ref))
+        assert not bad.any(), (np.flatnonzero(bad)[:5], got[bad][:5], ref[bad][:5])
+    pair = np.random.default_rng(3).integers(0, 2**32, size=1 << 22, dtype=np.uint64).astype(np.uint32)
+    assert np.array_equal(_convert_gpu(dev, 3, pair), oracle.convert(3, pair))

@@ -90,3 +90,12 @@ def test_pools_of_different_kinds_are_independent():
     e = oracle.entries(4, 0, K_E, 0, 50_000)
     # E is not a function of the same-index uniform (different counter word)
     assert abs(stats.spearmanr(u, e).statistic) < 5 / math.sqrt(u.size)
+
+
+def test_convert_matches_pool_entries():
+    """Converting a block's words by hand gives the pool entries."""
+    for kind in (K_U, K_N, K_E, K_U64):
+        w = oracle.words(321, 7, kind, 100, 64)
+        per_block = 2 if kind == K_U64 else 4
+        e = oracle.entries(321, 7, kind, 100 * per_block, 64 * per_block)
+        assert np.array_equal(oracle.convert(kind, w), e)
