@@ -5,23 +5,29 @@ Default workload (normal/exponential chains): 65,536 chains x 1,000 steps,
 s' ~ N(0.9 s, 0.5 + |s|) then e ~ Exp(1 + s'^2), fp32, Philox4x32-10 pools
 with a window of 4,096 entries per unit (64 chains) per kind, refilled on
 exhaustion.  One timed step is the whole hot path over that batch: bulk
-refill of the Gaussian and exponential windows (one 128-bit store per Philox
-block) followed by one launch that runs every chain for all 1,000 steps from
-the pools (regenerating each window in place when it runs out), writing both
-outputs of every step.  Chains continue from step to step.
+refill of the pool windows (one 128-bit store per Philox block) followed by
+one launch that runs every chain for all its steps from the pools
+(regenerating each window in place when it runs out), writing every output
+of every step.  Chains continue from step to step.
+
+Other workloads (--workload): triangle (Eq. 1 / Fig. 1, 1,024 chains x 10,000
+iterations, fp64), gamma (262,144 chains of uneven length 50..1,000 with
+alpha_{t+1} = 0.1 + g_t), lda (16,384 documents, Dirichlet + multinomial,
+100 sweeps).
 
 Prints one JSON line: deviates/s, the roofline of the dominant kernel
 (algorithmic bytes over its event-timed duration against 8 TB/s), and the
-CPU oracle timed on the host over the same workload.
+CPU oracle timed on the host over the workload or a stated sample of it.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -30,125 +36,254 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
-def _round_up(x, m):
-    return (x + m - 1) // m * m
-
-
-class Timer:
-    """HIP events on the library's stream, per named kernel launch."""
+class Events:
+    """HIP events recorded on the library's stream (torch's current stream)."""
 
     def __init__(self, torch):
         self.torch = torch
-        self.marks = []
+        self.pairs = {}
 
-    def mark(self, name):
-        e = self.torch.cuda.Event(enable_timing=True)
-        e.record()
-        self.marks.append((name, e))
+    def span(self, name):
+        t = self.torch
+        a = t.cuda.Event(enable_timing=True)
+        b = t.cuda.Event(enable_timing=True)
+        a.record()
+        self.pairs.setdefault(name, []).append((a, b))
+        return b
 
-    def per_name(self):
-        out = {}
-        for (name, a), (_, b) in zip(self.marks[:-1], self.marks[1:]):
-            if name is None:
-                continue
-            out.setdefault(name, []).append(a.elapsed_time(b))
-        return out
+    def ms(self, name):
+        return [a.elapsed_time(b) for a, b in self.pairs.get(name, [])]
+
+
+def _slices(units, workers):
+    per = (units + workers - 1) // workers
+    return [(w * per, min(units, (w + 1) * per)) for w in range(workers) if w * per < units]
+
+
+def _pool_run(fn, jobs):
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(len(jobs)) as pool:
+        busy = pool.map(fn, jobs)
+    return time.perf_counter() - t0, sum(busy)
 
 
 # ---------------------------------------------------------------------------
-# workloads
+# CPU oracle legs (test infrastructure; timed on the host cores)
+# ---------------------------------------------------------------------------
+
+def _cpu_normexp(a):
+    seed, u0, n, steps = a
+    import oracle
+    t = time.perf_counter()
+    oracle.normexp(seed, n, steps, unit0=u0)
+    return time.perf_counter() - t
+
+
+def _cpu_triangle(a):
+    seed, u0, n, iters = a
+    import oracle
+    t = time.perf_counter()
+    oracle.triangle(seed, n, iters, unit0=u0, trace=False)
+    return time.perf_counter() - t
+
+
+def _cpu_gamma(a):
+    seed, u0, alpha0, steps = a
+    import oracle
+    t = time.perf_counter()
+    oracle.gamma_chain(seed, alpha0, steps, perm=np.arange(alpha0.size, dtype=np.int32),
+                       unit0=u0)
+    return time.perf_counter() - t
+
+
+def _cpu_lda(a):
+    seed, d0, offsets, ntok, sweeps = a
+    import oracle
+    t = time.perf_counter()
+    oracle.lda(seed, offsets, ntok, sweeps, unit0=d0)
+    return time.perf_counter() - t
+
+
+# ---------------------------------------------------------------------------
+# workloads: each returns the context, the fresh and resume requests, the
+# kinds it draws, entry sizes, windows, deviates and output bytes per step,
+# its description and the CPU leg
 # ---------------------------------------------------------------------------
 
 def setup_normexp(torch, b, args):
     n, steps = args.chains or 65536, args.chain_steps or 1000
-    # pool window per unit (64 chains) per kind: 4,096 entries, refilled on
-    # exhaustion inside the chain kernel
     W = args.window or 4096
     dev = torch.device("cuda:0")
     ctx = b.brng_create(args.seed, n, [0, W, W, 0], stream=torch.cuda.current_stream())
     st = torch.zeros(n, dtype=torch.float32, device=dev)
     ts = torch.empty((steps, n), dtype=torch.float32, device=dev)
     te = torch.empty((steps, n), dtype=torch.float32, device=dev)
-    fresh = b.gibbs_desc(b.BRNG_MODEL_NORMEXP, n, st, max_steps=steps, seed=args.seed,
-                         trace=ts, trace2=te, trace_stride=n)
-    resume = b.gibbs_desc(b.BRNG_MODEL_NORMEXP, n, st, max_steps=steps, seed=args.seed,
-                          trace=ts, trace2=te, trace_stride=n, flags=b.BRNG_FLAG_RESUME)
+    kw = dict(max_steps=steps, seed=args.seed, trace=ts, trace2=te, trace_stride=n)
+    fresh = b.gibbs_desc(b.BRNG_MODEL_NORMEXP, n, st, **kw)
+    resume = b.gibbs_desc(b.BRNG_MODEL_NORMEXP, n, st, flags=b.BRNG_FLAG_RESUME, **kw)
     units = (n + 63) // 64
-    state = {"first": True}
-
-    def step(timer):
-        if state["first"]:
-            # fresh start: streams at 0, s_0 is each chain's first Gaussian
-            timer.mark(None)
-            b.brng_run_gibbs(ctx, fresh)
-            state["first"] = False
-            timer.mark(None)
-            return
-        timer.mark("fill")
-        b.brng_fill_base(ctx, b.BRNG_N)
-        b.brng_fill_base(ctx, b.BRNG_E)
-        timer.mark("chains")
-        b.brng_run_gibbs(ctx, resume)
-        timer.mark(None)
-
-    deviates = 2 * n * steps
-    consumed = 2 * n * steps  # one N and one E entry per chain-step
-    # algorithmic bytes: every consumed pool entry is written once and read
-    # once (4 B each), every output is written once (4 B).  The bulk fill
-    # writes the first window of each unit and kind; the chain kernel writes
-    # the rest (its in-kernel refills) and does all reads and output writes.
-    per_unit_kind = 64 * steps
-    fill_written = 2 * units * min(W, per_unit_kind)
-    bytes_ = {
-        "fill": fill_written * 4,
-        "chains": (consumed - fill_written) * 4 + consumed * 4 + deviates * 4,
-    }
-    launches = {"fill": 2, "chains": 1}
-    cfg = {"workload": "normal/exponential chains: s'~N(0.9s,0.5+|s|), e~Exp(1+s'^2)",
-           "chains": n, "steps": steps, "window_per_unit_per_kind": W, "unit_chains": 64,
-           "precision": "fp32", "generator": "Philox4x32-10"}
 
     def cpu(workers):
-        return cpu_normexp(args.seed, n, steps, workers)
+        jobs = [(args.seed, u0, min(n, u1 * 64) - u0 * 64, steps) for u0, u1 in _slices(units, workers)]
+        wall, busy = _pool_run(_cpu_normexp, jobs)
+        dv = 2 * n * steps
+        return {"value": dv / wall, "unit": "deviates/s", "cores": len(jobs), "kind": "oracle",
+                "sample": "whole workload (%d chains x %d steps, %.3g deviates) split by unit "
+                          "over %d processes; %.1f s of CPU work" % (n, steps, dv, len(jobs), busy)}
 
-    return dict(ctx=ctx, step=step, deviates=deviates, bytes=bytes_, launches=launches,
-                config=cfg, cpu=cpu, dtype="f32",
-                kernels={"fill": "k_fill", "chains": "k_gibbs<NORMEXP>"})
+    return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_N, b.BRNG_E],
+                entry_bytes={b.BRNG_N: 4, b.BRNG_E: 4}, windows={b.BRNG_N: W, b.BRNG_E: W},
+                deviates=2 * n * steps, out_bytes=2 * n * steps * 4, dtype="f32", cpu=cpu,
+                kernel="k_gibbs<NORMEXP>",
+                config={"workload": "normal/exponential chains: s'~N(0.9s,0.5+|s|), e~Exp(1+s'^2)",
+                        "chains": n, "steps": steps, "window_per_unit_per_kind": W,
+                        "unit_chains": 64, "precision": "fp32", "generator": "Philox4x32-10"})
 
 
-def _normexp_slice(args):
-    seed, unit0, n, steps = args
-    import oracle
-    t = time.perf_counter()
-    oracle.normexp(seed, n, steps, unit0=unit0)
-    return time.perf_counter() - t
-
-
-def cpu_normexp(seed, n, steps, workers):
-    """The oracle over the whole workload, unit ranges split across processes."""
-    import multiprocessing as mp
-
+def setup_triangle(torch, b, args):
+    n, iters = args.chains or 1024, args.chain_steps or 10000
+    W = args.window or 4096
+    dev = torch.device("cuda:0")
+    ctx = b.brng_create(args.seed, n, [0, 0, 0, W], stream=torch.cuda.current_stream())
+    st = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+    tx = torch.empty((iters, n), dtype=torch.float64, device=dev)
+    ty = torch.empty((iters, n), dtype=torch.float64, device=dev)
+    kw = dict(max_steps=iters, seed=args.seed, trace=tx, trace2=ty, trace_stride=n)
+    fresh = b.gibbs_desc(b.BRNG_MODEL_TRIANGLE_F64, n, st, **kw)
+    resume = b.gibbs_desc(b.BRNG_MODEL_TRIANGLE_F64, n, st, flags=b.BRNG_FLAG_RESUME, **kw)
     units = (n + 63) // 64
-    per = (units + workers - 1) // workers
-    jobs = []
-    for w in range(workers):
-        u0, u1 = w * per, min(units, (w + 1) * per)
-        if u0 >= u1:
-            continue
-        jobs.append((seed, u0, min(n, u1 * 64) - u0 * 64, steps))
-    ctx = mp.get_context("fork")
-    t0 = time.perf_counter()
-    with ctx.Pool(len(jobs)) as pool:
-        busy = pool.map(_normexp_slice, jobs)
-    wall = time.perf_counter() - t0
-    dev = 2 * n * steps
-    return {"value": dev / wall, "unit": "deviates/s", "cores": len(jobs), "kind": "oracle",
-            "sample": "whole workload (%d chains x %d steps, %.2e deviates) split by unit "
-                      "over %d processes; %.1f s of CPU work" % (n, steps, dev, len(jobs),
-                                                                 sum(busy))}
+
+    def cpu(workers):
+        jobs = [(args.seed, u0, min(n, u1 * 64) - u0 * 64, iters) for u0, u1 in _slices(units, workers)]
+        wall, busy = _pool_run(_cpu_triangle, jobs)
+        dv = 2 * n * iters
+        return {"value": dv / wall, "unit": "deviates/s", "cores": len(jobs), "kind": "oracle",
+                "sample": "whole workload (%d chains x %d iterations) split by unit over %d "
+                          "processes; %.1f s of CPU work" % (n, iters, len(jobs), busy)}
+
+    return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_U64],
+                entry_bytes={b.BRNG_U64: 8}, windows={b.BRNG_U64: W},
+                deviates=2 * n * iters, out_bytes=2 * n * iters * 8, dtype="f64", cpu=cpu,
+                kernel="k_gibbs<TRIANGLE>",
+                config={"workload": "triangle Gibbs sampler of Eq. 1 / Fig. 1: x~U(0,1-y), y~U(0,1-x)",
+                        "chains": n, "iterations": iters, "window_per_unit": W,
+                        "precision": "fp64", "generator": "Philox4x32-10"})
 
 
-WORKLOADS = {"normexp": setup_normexp}
+def setup_gamma(torch, b, args):
+    from paper_1412_4825_amd import workloads
+    n = args.chains or 262144
+    wl = workloads.gamma_chain(n_chains=n, seed=args.seed)
+    W = args.window or 4096
+    dev = torch.device("cuda:0")
+    ctx = b.brng_create(args.seed, n, [0, W, W, 0], stream=torch.cuda.current_stream())
+    perm = b.brng_sort_by_length(wl["steps"])
+    smax = int(wl["steps"].max())
+    st = torch.from_numpy(wl["alpha0"]).to(dev)
+    tg = torch.empty((smax, n), dtype=torch.float32, device=dev)
+    tsteps = torch.from_numpy(wl["steps"]).to(dev)
+    tperm = torch.from_numpy(perm).to(dev)
+    kw = dict(max_steps=smax, seed=args.seed, trace=tg, trace_stride=n, steps=tsteps, perm=tperm)
+    fresh = b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, n, st, **kw)
+    resume = b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, n, st, flags=b.BRNG_FLAG_RESUME, **kw)
+    draws = int(wl["steps"].sum())
+    units = (n + 63) // 64
+
+    def cpu(workers):
+        # a sample: the first units of the length-sorted slot order
+        su = min(units, args.cpu_units or 1024)
+        jobs = []
+        for u0, u1 in _slices(su, workers):
+            sl = perm[u0 * 64:min(n, u1 * 64)]
+            jobs.append((args.seed, u0, wl["alpha0"][sl].astype(np.float64), wl["steps"][sl]))
+        wall, busy = _pool_run(_cpu_gamma, jobs)
+        dv = int(wl["steps"][perm[:su * 64]].sum())
+        return {"value": dv / wall, "unit": "deviates/s", "cores": len(jobs), "kind": "oracle",
+                "sample": "%d of %d units (the longest chains first, %.3g gamma draws) over %d "
+                          "processes; %.1f s of CPU work" % (su, units, dv, len(jobs), busy)}
+
+    def oaat(events):
+        """The same shapes drawn with one launch per step (brng_step_gamma)."""
+        c2 = b.brng_create(args.seed + 1, n, [0, W, W, 0], stream=torch.cuda.current_stream())
+        a = torch.from_numpy(wl["alpha0"][perm]).to(dev)
+        out = torch.empty(n, dtype=torch.float32, device=dev)
+        k = args.oaat_steps
+        for _ in range(3):
+            b.brng_step_gamma(c2, a, out)
+        torch.cuda.synchronize()
+        e0 = events.span("oaat")
+        for _ in range(k):
+            b.brng_step_gamma(c2, a, out)
+            torch.add(out, 0.1, out=a)
+        e0.record()
+        torch.cuda.synchronize()
+        b.brng_destroy(c2)
+        ms = events.ms("oaat")[0]
+        return {"value": n * k / (ms / 1e3), "unit": "deviates/s", "launches": 2 * k,
+                "note": "one brng_step_gamma launch per step over all %d chains, alpha update "
+                        "on the stream between launches" % n}
+
+    return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_N, b.BRNG_E],
+                entry_bytes={b.BRNG_N: 4, b.BRNG_E: 4}, windows={b.BRNG_N: W, b.BRNG_E: W},
+                deviates=draws, out_bytes=draws * 4, dtype="f32", cpu=cpu, oaat=oaat,
+                kernel="k_gibbs<GAMMA_CHAIN>",
+                config={"workload": "varying-shape gamma chains: g~Gamma(alpha,1), alpha'=0.1+g, "
+                                    "Marsaglia-Tsang with the alpha<1 boost",
+                        "chains": n, "steps": "U{50..1000}", "draws_per_step": draws,
+                        "window_per_unit_per_kind": W, "precision": "fp32",
+                        "generator": "Philox4x32-10"})
+
+
+def setup_lda(torch, b, args):
+    from paper_1412_4825_amd import workloads
+    nd = args.chains or 16384
+    sweeps = args.chain_steps or 100
+    wl = workloads.lda(n_docs=nd, sweeps=sweeps, seed=args.seed)
+    W = args.window or 4096
+    dev = torch.device("cuda:0")
+    ctx = b.brng_create(args.seed, nd, [W, W, W, 0], layout=b.BRNG_LAYOUT_ITEMS,
+                        stream=torch.cuda.current_stream())
+    total = int(wl["offsets"][-1])
+    counts = torch.zeros(total, dtype=torch.int32, device=dev)
+    th = torch.empty((sweeps, total), dtype=torch.float32, device=dev)
+    ct = torch.empty((sweeps, total), dtype=torch.int32, device=dev)
+    toff = torch.from_numpy(wl["offsets"]).to(dev)
+    tntok = torch.from_numpy(wl["ntok"]).to(dev)
+    kw = dict(max_steps=sweeps, seed=args.seed, trace=th, trace2=ct, trace_stride=total,
+              offsets=toff, ntok=tntok)
+    fresh = b.gibbs_desc(b.BRNG_MODEL_LDA, nd, counts, **kw)
+    resume = b.gibbs_desc(b.BRNG_MODEL_LDA, nd, counts, flags=b.BRNG_FLAG_RESUME, **kw)
+    dv = sweeps * (total + int(wl["ntok"].sum()))
+
+    def cpu(workers):
+        sd = min(nd, args.cpu_units or 2048)
+        jobs = []
+        for d0, d1 in _slices(sd, workers):
+            off = wl["offsets"][d0:d1 + 1] - wl["offsets"][d0]
+            jobs.append((args.seed, d0, off.astype(np.int32), wl["ntok"][d0:d1], sweeps))
+        wall, busy = _pool_run(_cpu_lda, jobs)
+        sdv = sweeps * (int(wl["offsets"][sd]) + int(wl["ntok"][:sd].sum()))
+        return {"value": sdv / wall, "unit": "deviates/s", "cores": len(jobs), "kind": "oracle",
+                "sample": "%d of %d documents x %d sweeps (%.3g deviates) over %d processes; "
+                          "%.1f s of CPU work" % (sd, nd, sweeps, sdv, len(jobs), busy)}
+
+    return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_U, b.BRNG_N, b.BRNG_E],
+                entry_bytes={b.BRNG_U: 4, b.BRNG_N: 4, b.BRNG_E: 4},
+                windows={b.BRNG_U: W, b.BRNG_N: W, b.BRNG_E: W},
+                deviates=dv, out_bytes=sweeps * total * 8, dtype="f32", cpu=cpu,
+                kernel="k_gibbs<LDA>",
+                config={"workload": "LDA-style Dirichlet resampling: theta~Dir(0.1+counts), "
+                                    "counts~Mult(n_d, theta)",
+                        "documents": nd, "sweeps": sweeps, "K": "{8,16,64,256}",
+                        "tokens": "Poisson(200)", "components": total,
+                        "window_per_unit_per_kind": W, "precision": "fp32 deviates, int32 counts",
+                        "generator": "Philox4x32-10"})
+
+
+WORKLOADS = {"normexp": setup_normexp, "triangle": setup_triangle, "gamma": setup_gamma,
+             "lda": setup_lda}
 
 
 def main():
@@ -164,6 +299,8 @@ def main():
     ap.add_argument("--wpb", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0)
+    ap.add_argument("--cpu-units", type=int, default=0)
+    ap.add_argument("--oaat-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this library has no multi-GPU path "
@@ -178,43 +315,55 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    W = WORKLOADS[args.workload](torch, b, args)
-    b.brng_set_launch(W["ctx"], args.wpb)
-    step = W["step"]
+    Wk = WORKLOADS[args.workload](torch, b, args)
+    ctx = Wk["ctx"]
+    b.brng_set_launch(ctx, args.wpb)
+    ev = Events(torch)
 
-    warm = Timer(torch)
-    for _ in range(max(1, args.warmup)):
-        step(warm)
+    def step():
+        for k in Wk["kinds"]:
+            b.brng_fill_base(ctx, k)
+        e = ev.span("chains")
+        b.brng_run_gibbs(ctx, Wk["resume"])
+        e.record()
+
+    b.brng_run_gibbs(ctx, Wk["fresh"])  # fresh start: streams at 0
+    for _ in range(max(0, args.warmup - 1)):
+        step()
     torch.cuda.synchronize()
-    timer = Timer(torch)
+    ev.pairs.clear()
+    cur0 = b.brng_get_cursors(ctx)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(args.steps):
-        step(timer)
+        step()
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_total = start.elapsed_time(stop)
-    ms_step = ms_total / args.steps
-    value = W["deviates"] / (ms_step / 1e3)
+    cur1 = b.brng_get_cursors(ctx)
+    ms_step = start.elapsed_time(stop) / args.steps
+    value = Wk["deviates"] / (ms_step / 1e3)
 
-    per = timer.per_name()
-    kern = {}
-    for name, times in per.items():
-        avg_ms = sum(times) / len(times) / W["launches"][name]
-        gbs = W["bytes"][name] / W["launches"][name] / (avg_ms / 1e3) / 1e9
-        kern[name] = {"kernel": W["kernels"][name], "ms_per_launch": avg_ms,
-                      "launches_per_step": W["launches"][name],
-                      "alg_bytes_per_launch": W["bytes"][name] / W["launches"][name],
-                      "GBps": gbs}
-    dom = max(kern, key=lambda k: kern[k]["ms_per_launch"] * kern[k]["launches_per_step"])
-    roof = {"bound": "hbm", "achieved": round(kern[dom]["GBps"], 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(kern[dom]["GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": kern[dom]["kernel"]}
-    step_bytes = sum(W["bytes"].values())
+    # algorithmic bytes from the entries actually consumed (cursor deltas):
+    # each consumed entry is written once and read once; the bulk fill writes
+    # the first window of each unit and kind, the chain kernel the rest
+    delta = (cur1 - cur0).astype(np.float64) / args.steps  # per step, [unit][kind]
+    fill_b = 0.0
+    pool_b = 0.0
+    for k in Wk["kinds"]:
+        eb = Wk["entry_bytes"][k]
+        pool_b += 2.0 * eb * delta[:, k].sum()
+        fill_b += eb * np.minimum(delta[:, k], Wk["windows"][k]).sum()
+    step_b = pool_b + Wk["out_bytes"]
+    chain_b = step_b - fill_b
+    chain_ms = float(np.mean(ev.ms("chains")))
+    gbs = chain_b / (chain_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": Wk["kernel"],
+            "kernel_ms": round(chain_ms, 4), "alg_bytes_per_launch": chain_b}
     out = {
         "metric": "varying-param deviates/s + % HBM roofline",
         "value": value,
@@ -226,19 +375,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": W["dtype"],
+        "dtype": Wk["dtype"],
         "data": "synthetic",
-        "config": W["config"],
+        "config": Wk["config"],
         "roofline": roof,
-        "step_alg_bytes": step_bytes,
-        "step_hbm_frac": round(step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-        "kernels": kern,
+        "step_alg_bytes": step_b,
+        "step_hbm_frac": round(step_b / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "entries_per_step": {int(k): float(delta[:, k].sum()) for k in Wk["kinds"]},
         "wall_s": wall,
     }
+    if "oaat" in Wk:
+        out["one_launch_per_step"] = Wk["oaat"](ev)
     if not args.no_cpu:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = W["cpu"](workers)
-    b.brng_destroy(W["ctx"])
+        out["cpu_baseline"] = Wk["cpu"](workers)
+    b.brng_destroy(ctx)
     print(json.dumps(out), flush=True)
 
 
