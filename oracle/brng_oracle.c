@@ -304,20 +304,25 @@ void or_step_exp(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, uint
 /* v = (1 + c x)^3; if 1 + c x <= 0 draw again.  Otherwise draw u and       */
 /* accept d v when ln u < x^2/2 + d - d v + d ln v.  Here ln u = -E with E  */
 /* from the exponential pool.  For alpha < 1 the draw is made with shape    */
-/* alpha + 1 and multiplied by u'^(1/alpha) = exp(-E'/alpha).               */
+/* alpha + 1 and multiplied by u'^(1/alpha) = exp(-E'/alpha).  A shape      */
+/* outside (0, 2^64) has no draw: its value is NaN and it consumes nothing. */
 /*                                                                          */
-/* Consumption order within one call over the slots of a unit: rounds of    */
-/* (a Gaussian for every pending slot, ascending; an exponential for every  */
-/* pending slot whose 1 + c x > 0, ascending; accepted slots retire), until */
-/* no slot is pending; then one exponential for every slot with alpha < 1,  */
-/* ascending.                                                               */
+/* Consumption order: the slots of a unit share the pools and work in       */
+/* rounds.  Each slot holds at most one draw.  In a round: a Gaussian for   */
+/* every slot holding a draw with a valid shape (ascending slots); an       */
+/* exponential for each of those whose 1 + c x > 0 (ascending); the accept  */
+/* test; an exponential for every accepted draw with alpha < 1 (ascending); */
+/* then, in ascending slot order, every slot whose draw is complete         */
+/* (accepted, or with an invalid shape) hands its value on and takes its    */
+/* next draw, if any.  So a slot whose draw is accepted starts its next     */
+/* draw in the next round instead of waiting for the other slots.           */
 /*                                                                          */
-/* Besides the value the oracle reports, per slot:                          */
+/* Besides the value the oracle reports, per draw:                          */
 /*   tol    : bound on |gpu - oracle| (local rounding + the effect of an    */
 /*            error bound `abound` carried by alpha itself),                */
 /*   dg     : d g / d alpha (same base deviates),                           */
 /*   margin : the smallest |decision value| / its tolerance over the        */
-/*            slot's decisions; a value <= 1 means an fp32 implementation   */
+/*            draw's decisions; a value <= 1 means an fp32 implementation   */
 /*            may legitimately decide the other way,                        */
 /*   nN, nE : entries consumed.                                             */
 /* ------------------------------------------------------------------------ */
@@ -334,55 +339,65 @@ static double qfun(double y) { return 3.0 * log1p(y) - 3.0 * y + 1.5 * y * y - y
 
 #define OR_MAXSLOT 256
 
-static void or_gamma_call(stream_t *s, int nslots, const uint8_t *active,
-                   const double *alpha, const double *abound, gdraw_t *res)
+/* Where the draws of a unit come from and where they go. */
+typedef struct gsrc gsrc_t;
+struct gsrc {
+    /* give slot k its next draw: 1 and the shape (and its error bound), or 0 */
+    int (*next)(gsrc_t *g, int k, double *alpha, double *abound);
+    /* slot k's draw is complete */
+    void (*done)(gsrc_t *g, int k, const gdraw_t *r);
+    void *ctx;
+};
+
+static int shape_ok(double a) { return a > 0.0 && a < 0x1p64; }
+
+static void or_gamma_rounds(stream_t *s, int nslots, gsrc_t *src)
 {
-    double d[OR_MAXSLOT], c[OR_MAXSLOT], x[OR_MAXSLOT], v0[OR_MAXSLOT];
+    double alpha[OR_MAXSLOT], ab[OR_MAXSLOT], d[OR_MAXSLOT], c[OR_MAXSLOT];
+    double x[OR_MAXSLOT], v0[OR_MAXSLOT];
     double kx[OR_MAXSLOT]; /* |d ln(g)/d ln(x)| of the accepted draw */
-    uint8_t pending[OR_MAXSLOT];
+    uint8_t hold[OR_MAXSLOT], acc[OR_MAXSLOT];
+    gdraw_t res[OR_MAXSLOT];
     int any = 0;
     for (int k = 0; k < nslots; k++) {
-        pending[k] = active[k];
-        res[k].g = 0.0; res[k].tol = 0.0; res[k].dg = 0.0;
-        res[k].margin = INFINITY; res[k].nN = 0; res[k].nE = 0;
-        kx[k] = 0.0;
-        if (!active[k])
-            continue;
-        if (!(alpha[k] > 0.0 && alpha[k] < 0x1p64)) { /* no valid gamma: NaN */
-            pending[k] = 0;
-            res[k].g = NAN;
-            continue;
-        }
-        double a = alpha[k] < 1.0 ? alpha[k] + 1.0 : alpha[k];
-        d[k] = a - 1.0 / 3.0;
-        c[k] = 1.0 / sqrt(9.0 * d[k]);
-        any = 1;
+        hold[k] = (uint8_t)src->next(src, k, &alpha[k], &ab[k]);
+        any |= hold[k];
     }
+    /* per-draw setup */
+#define SETUP(k)                                                                 \
+    do {                                                                         \
+        res[k].g = 0.0; res[k].tol = 0.0; res[k].dg = 0.0;                      \
+        res[k].margin = INFINITY; res[k].nN = 0; res[k].nE = 0;                  \
+        kx[k] = 0.0;                                                             \
+        if (shape_ok(alpha[k])) {                                                \
+            double a_ = alpha[k] < 1.0 ? alpha[k] + 1.0 : alpha[k];              \
+            d[k] = a_ - 1.0 / 3.0;                                               \
+            c[k] = 1.0 / sqrt(9.0 * d[k]);                                       \
+        }                                                                        \
+    } while (0)
+    for (int k = 0; k < nslots; k++)
+        if (hold[k])
+            SETUP(k);
     while (any) {
-        /* a Gaussian for every pending slot, ascending */
+        /* a Gaussian for every slot holding a valid draw, ascending */
         for (int k = 0; k < nslots; k++) {
-            if (!pending[k])
+            acc[k] = 0;
+            if (!hold[k] || !shape_ok(alpha[k]))
                 continue;
             x[k] = take(s, OR_N);
             res[k].nN++;
             v0[k] = 1.0 + c[k] * x[k];
             /* sign decision on 1 + c x */
             double y = c[k] * x[k];
-            double ab = abound ? abound[k] : 0.0;
-            double t = or_tol(dmax(1.0, fabs(y))) + fabs(y / (2.0 * d[k])) * ab;
+            double t = or_tol(dmax(1.0, fabs(y))) + fabs(y / (2.0 * d[k])) * ab[k];
             double m = fabs(v0[k]) / t;
             if (m < res[k].margin)
                 res[k].margin = m;
         }
-        /* an exponential for every pending slot with 1 + c x > 0, ascending */
-        any = 0;
+        /* an exponential for each of those with 1 + c x > 0, ascending */
         for (int k = 0; k < nslots; k++) {
-            if (!pending[k])
+            if (!hold[k] || !shape_ok(alpha[k]) || !(v0[k] > 0.0))
                 continue;
-            if (v0[k] <= 0.0) {
-                any = 1;
-                continue;
-            }
             double e = take(s, OR_E);
             res[k].nE++;
             double v = v0[k] * v0[k] * v0[k];
@@ -392,38 +407,71 @@ static void or_gamma_call(stream_t *s, int nslots, const uint8_t *active,
             double y = c[k] * x[k];
             double dq = d[k] * qfun(y);
             double cond = d[k] * 3.0 * pow(y, 4) / (1.0 + y);
-            double ab = abound ? abound[k] : 0.0;
             double dstat = qfun(y) + 1.5 * pow(y, 4) / (1.0 + y);
-            double t = or_tol(e + fabs(dq) + fabs(cond)) + fabs(dstat) * ab;
+            double t = or_tol(e + fabs(dq) + fabs(cond)) + fabs(dstat) * ab[k];
             double m = fabs(stat) / t;
             if (m < res[k].margin)
                 res[k].margin = m;
             if (stat > 0.0) { /* ln u = -E < x^2/2 + d(1 - v + ln v) */
-                pending[k] = 0;
+                acc[k] = 1;
                 res[k].g = d[k] * v;
                 kx[k] = fabs(3.0 * y / (1.0 + y));
                 res[k].dg = (1.0 + y) * (1.0 + y) * (1.0 - 0.5 * y);
-                res[k].tol = or_tol(res[k].g * (1.0 + kx[k])) + fabs(res[k].dg) * ab;
-            } else {
-                any = 1;
+                res[k].tol = or_tol(res[k].g * (1.0 + kx[k])) + fabs(res[k].dg) * ab[k];
             }
         }
+        /* the boost for accepted draws with alpha < 1, ascending */
+        for (int k = 0; k < nslots; k++) {
+            if (!acc[k] || !(alpha[k] < 1.0))
+                continue;
+            double e = take(s, OR_E);
+            res[k].nE++;
+            double f = exp(-e / alpha[k]);
+            double g1 = res[k].g;
+            double dg1 = res[k].dg;
+            res[k].g = g1 * f;
+            res[k].dg = f * dg1 + res[k].g * e / (alpha[k] * alpha[k]);
+            double kappa = kx[k] + e / alpha[k];
+            res[k].tol = or_tol(res[k].g * (1.0 + kappa)) + fabs(res[k].dg) * ab[k];
+        }
+        /* complete draws hand on their value and take the next, ascending */
+        any = 0;
+        for (int k = 0; k < nslots; k++) {
+            if (hold[k] && (acc[k] || !shape_ok(alpha[k]))) {
+                if (!shape_ok(alpha[k]))
+                    res[k].g = NAN;
+                src->done(src, k, &res[k]);
+                hold[k] = (uint8_t)src->next(src, k, &alpha[k], &ab[k]);
+                if (hold[k])
+                    SETUP(k);
+            }
+            any |= hold[k];
+        }
     }
-    /* boost for alpha < 1: multiply by exp(-E'/alpha), ascending */
-    for (int k = 0; k < nslots; k++) {
-        if (!active[k] || !(alpha[k] > 0.0 && alpha[k] < 1.0))
-            continue;
-        double e = take(s, OR_E);
-        res[k].nE++;
-        double f = exp(-e / alpha[k]);
-        double g1 = res[k].g;
-        double dg1 = res[k].dg;
-        res[k].g = g1 * f;
-        res[k].dg = f * dg1 + res[k].g * e / (alpha[k] * alpha[k]);
-        double ab = abound ? abound[k] : 0.0;
-        double kappa = kx[k] + e / alpha[k];
-        res[k].tol = or_tol(res[k].g * (1.0 + kappa)) + fabs(res[k].dg) * ab;
-    }
+#undef SETUP
+}
+
+/* One draw per slot (the one-at-a-time call). */
+typedef struct {
+    const double *alpha;
+    uint8_t *given;
+    gdraw_t *out;
+} one_each_t;
+
+static int one_each_next(gsrc_t *g, int k, double *alpha, double *abound)
+{
+    one_each_t *o = (one_each_t *)g->ctx;
+    if (o->given[k])
+        return 0;
+    o->given[k] = 1;
+    *alpha = o->alpha[k];
+    *abound = 0.0;
+    return 1;
+}
+
+static void one_each_done(gsrc_t *g, int k, const gdraw_t *r)
+{
+    ((one_each_t *)g->ctx)->out[k] = *r;
 }
 
 /* One gamma draw per chain, chains grouped into units of `width`. */
@@ -434,16 +482,17 @@ void or_step_gamma(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, ui
     if (width == 0 || width > OR_MAXSLOT)
         return;
     uint32_t nu = (n + width - 1) / width;
-    uint8_t act[OR_MAXSLOT];
+    uint8_t given[OR_MAXSLOT];
     gdraw_t res[OR_MAXSLOT];
     for (uint32_t u = 0; u < nu; u++) {
         stream_t s = {seed, unit0 + u, cursors + 4 * (size_t)u};
         uint32_t lo, hi;
         unit_range(n, width, u, &lo, &hi);
         int ns = (int)(hi - lo);
-        for (int k = 0; k < ns; k++)
-            act[k] = 1;
-        or_gamma_call(&s, ns, act, alpha + lo, NULL, res);
+        memset(given, 0, sizeof(given));
+        one_each_t o = {alpha + lo, given, res};
+        gsrc_t src = {one_each_next, one_each_done, &o};
+        or_gamma_rounds(&s, ns, &src);
         for (int k = 0; k < ns; k++) {
             out[lo + k] = res[k].g;
             if (tol) tol[lo + k] = res[k].tol;
@@ -456,32 +505,55 @@ void or_step_gamma(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, ui
 
 /* ------------------------------------------------------------------------ */
 /* Dirichlet (Sec. 1, footnote): y_k ~ Gamma(alpha_k, 1), x_k = y_k / sum.  */
-/* One item (a unit) holds K components; they are drawn in batches of 64    */
-/* slots, one gamma call per batch, in ascending batch order.               */
+/* One item (a unit) holds K components, drawn by 64 slots in gamma rounds: */
+/* the slots start with components 0..63, and a slot whose draw completes   */
+/* takes the lowest component not yet started.                             */
 /* ------------------------------------------------------------------------ */
 
 #define OR_BATCH 64
+
+typedef struct {
+    int K, next;
+    const double *alpha;
+    int comp[OR_BATCH];
+    double *y, *ytol, mmin;
+} comps_t;
+
+static int comps_next(gsrc_t *g, int k, double *alpha, double *abound)
+{
+    comps_t *c = (comps_t *)g->ctx;
+    if (c->next >= c->K)
+        return 0;
+    c->comp[k] = c->next++;
+    *alpha = c->alpha[c->comp[k]];
+    *abound = 0.0;
+    return 1;
+}
+
+static void comps_done(gsrc_t *g, int k, const gdraw_t *r)
+{
+    comps_t *c = (comps_t *)g->ctx;
+    c->y[c->comp[k]] = r->g;
+    c->ytol[c->comp[k]] = r->tol;
+    if (r->margin < c->mmin)
+        c->mmin = r->margin;
+}
 
 /* Draw theta for one item; y/ytol are scratch of length K. Returns the
  * smallest decision margin. tol: bound on |gpu theta - oracle theta|. */
 static double dirichlet_item(stream_t *s, int K, const double *alpha,
                              double *theta, double *tol, double *y, double *ytol)
 {
-    uint8_t act[OR_BATCH];
-    gdraw_t res[OR_BATCH];
-    double mmin = INFINITY;
-    for (int b0 = 0; b0 < K; b0 += OR_BATCH) {
-        int nb = (K - b0 < OR_BATCH) ? K - b0 : OR_BATCH;
-        for (int k = 0; k < nb; k++)
-            act[k] = 1;
-        or_gamma_call(s, nb, act, alpha + b0, NULL, res);
-        for (int k = 0; k < nb; k++) {
-            y[b0 + k] = res[k].g;
-            ytol[b0 + k] = res[k].tol;
-            if (res[k].margin < mmin)
-                mmin = res[k].margin;
-        }
-    }
+    comps_t cs;
+    cs.K = K;
+    cs.next = 0;
+    cs.alpha = alpha;
+    cs.y = y;
+    cs.ytol = ytol;
+    cs.mmin = INFINITY;
+    gsrc_t src = {comps_next, comps_done, &cs};
+    or_gamma_rounds(s, OR_BATCH, &src);
+    double mmin = cs.mmin;
     double S = 0.0, St = 0.0;
     for (int k = 0; k < K; k++) {
         S += y[k];
@@ -739,71 +811,81 @@ void or_expchain(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, uint
 }
 
 /* Varying-shape gamma chain: alpha_{t+1} = 0.1 + g_t, g_t ~ Gamma(alpha_t, 1).
+ * Each slot of a unit runs its own chain through the gamma rounds: when its
+ * draw is accepted it starts the chain's next step in the next round.
  * alpha (user order) in: alpha_0, out: the next shape.  Slots follow perm,
- * steps[c] per chain.  gtr/gtol/gmar are [t][slot] (NaN where a slot is
- * idle). */
+ * steps[c] per chain.  gtr/gtol/gmar are [t][slot] (left untouched where a
+ * chain has no step t). */
+typedef struct {
+    int L[OR_MAXSLOT], t[OR_MAXSLOT];
+    double a[OR_MAXSLOT], ab[OR_MAXSLOT];
+    uint32_t n, lo;
+    double *gtr, *gtol, *gmar;
+} chains_t;
+
+static int chains_next(gsrc_t *g, int k, double *alpha, double *abound)
+{
+    chains_t *c = (chains_t *)g->ctx;
+    if (c->t[k] >= c->L[k])
+        return 0;
+    *alpha = c->a[k];
+    *abound = c->ab[k];
+    return 1;
+}
+
+static void chains_done(gsrc_t *g, int k, const gdraw_t *r)
+{
+    chains_t *c = (chains_t *)g->ctx;
+    size_t o = (size_t)c->t[k] * c->n + c->lo + (size_t)k;
+    if (c->gtr) c->gtr[o] = r->g;
+    if (c->gtol) c->gtol[o] = r->tol;
+    if (c->gmar) c->gmar[o] = r->margin;
+    double an = 0.1 + r->g;
+    /* the next shape carries g's bound plus the fp32 rounding of 0.1 + g
+     * and of the constant 0.1 itself */
+    c->ab[k] = r->tol + ulp32(an) + 2e-9;
+    c->a[k] = an;
+    c->t[k]++;
+}
+
 void or_gamma_chain(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, const int32_t *perm,
                     const int32_t *steps, double *alpha, uint64_t *cursors,
                     double *gtr, double *gtol, double *gmar)
 {
     if (width == 0 || width > OR_MAXSLOT)
         return;
-    int32_t smax = 0;
-    for (uint32_t c = 0; c < n; c++)
-        if (steps[c] > smax)
-            smax = steps[c];
     uint32_t nu = (n + width - 1) / width;
+    chains_t *cs = (chains_t *)malloc(sizeof(chains_t));
     for (uint32_t u = 0; u < nu; u++) {
         stream_t st = {seed, unit0 + u, cursors + 4 * (size_t)u};
         uint32_t lo, hi;
         unit_range(n, width, u, &lo, &hi);
         int ns = (int)(hi - lo);
-        double a[OR_MAXSLOT], ab[OR_MAXSLOT];
-        uint8_t act[OR_MAXSLOT];
-        gdraw_t res[OR_MAXSLOT];
+        cs->n = n;
+        cs->lo = lo;
+        cs->gtr = gtr;
+        cs->gtol = gtol;
+        cs->gmar = gmar;
         for (int k = 0; k < ns; k++) {
             uint32_t ch = perm ? (uint32_t)perm[lo + k] : lo + k;
-            a[k] = alpha[ch];
-            ab[k] = 0.0;
+            cs->a[k] = alpha[ch];
+            cs->ab[k] = 0.0;
+            cs->t[k] = 0;
+            cs->L[k] = steps[ch];
         }
-        for (int32_t t = 0; t < smax; t++) {
-            int any = 0;
-            for (int k = 0; k < ns; k++) {
-                uint32_t ch = perm ? (uint32_t)perm[lo + k] : lo + k;
-                act[k] = (uint8_t)(t < steps[ch]);
-                any |= act[k];
-            }
-            if (!any)
-                break;
-            or_gamma_call(&st, ns, act, a, ab, res);
-            for (int k = 0; k < ns; k++) {
-                size_t o = (size_t)t * n + lo + k;
-                if (!act[k]) {
-                    if (gtr) gtr[o] = NAN;
-                    if (gtol) gtol[o] = NAN;
-                    if (gmar) gmar[o] = NAN;
-                    continue;
-                }
-                if (gtr) gtr[o] = res[k].g;
-                if (gtol) gtol[o] = res[k].tol;
-                if (gmar) gmar[o] = res[k].margin;
-                double an = 0.1 + res[k].g;
-                /* the next shape carries g's bound plus the fp32 rounding of
-                 * 0.1 + g and of the constant 0.1 itself */
-                ab[k] = res[k].tol + ulp32(an) + 2e-9;
-                a[k] = an;
-            }
-        }
+        gsrc_t src = {chains_next, chains_done, cs};
+        or_gamma_rounds(&st, ns, &src);
         for (int k = 0; k < ns; k++) {
             uint32_t ch = perm ? (uint32_t)perm[lo + k] : lo + k;
-            alpha[ch] = a[k];
+            alpha[ch] = cs->a[k];
         }
     }
+    free(cs);
 }
 
 /* LDA-style Dirichlet resampling.  Unit = document d (key unit id d).
  * Per sweep: alpha_k = 0.1 + counts_k; theta ~ Dirichlet(alpha) (gamma
- * calls per 64-component batch); counts ~ Multinomial(n_d, theta) with the
+ * rounds over the components); counts ~ Multinomial(n_d, theta) with the
  * integer rule above.  counts (in/out) and the traces are laid out by the
  * component offsets; thtr/thtol/cntr are [sweep][total components],
  * gmar/mmar are [sweep][doc]. */
