@@ -155,14 +155,19 @@ __global__ __launch_bounds__(512) void k_step_gamma(Meta* meta, Pools P, uint32_
     DirectReader<KIND_E> re;
     rn.open(meta[unit], P.n + (size_t)unit * P.W[KIND_N], P.W[KIND_N]);
     re.open(meta[unit], P.e + (size_t)unit * P.W[KIND_E], P.W[KIND_E]);
-    const float g = gamma_call(rn, re, act, act ? alpha[c] : 1.0f);
-    if (act) out[c] = g;
+    OneEachSrc src;
+    src.act = act;
+    src.alpha = act ? alpha[c] : 1.0f;
+    src.g = 0.0f;
+    gamma_rounds(rn, re, src, 4096u);
+    if (act) out[c] = src.g;
     rn.close(meta[unit]);
     re.close(meta[unit]);
 }
 
-// Dirichlet: one wave per item, any K (gammas go to `out`, then are scaled
-// by the sum, which is accumulated in the same order as in the LDA model).
+// Dirichlet: one wave per item, any K (the component gammas go to `out`,
+// then are scaled by their sum, accumulated in the same order as in the LDA
+// model).
 __global__ __launch_bounds__(512) void k_step_dirichlet(Meta* meta, Pools P, uint32_t n_items,
                                                         const int32_t* offsets,
                                                         const float* alpha, float* out) {
@@ -176,15 +181,18 @@ __global__ __launch_bounds__(512) void k_step_dirichlet(Meta* meta, Pools P, uin
     DirectReader<KIND_E> re;
     rn.open(meta[item], P.n + (size_t)item * P.W[KIND_N], P.W[KIND_N]);
     re.open(meta[item], P.e + (size_t)item * P.W[KIND_E], P.W[KIND_E]);
+    CompSrc src;
+    src.K = K;
+    src.alpha = alpha + off;
+    src.cnt = nullptr;
+    src.y = out + off;
+    gamma_rounds(rn, re, src, 4096u + 64u * (uint32_t)min(K, 1 << 24));
+    // component gammas were written by whichever lane drew them
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     float part = 0.0f;
     for (int b0 = 0; b0 < K; b0 += 64) {
         const int k = b0 + (int)lane;
-        const bool act = k < K;
-        const float y = gamma_call(rn, re, act, act ? alpha[off + k] : 1.0f);
-        if (act) {
-            out[off + k] = y;
-            part += y;
-        }
+        if (k < K) part += out[off + k];
     }
     const float S = wave_sum(part);
     for (int b0 = 0; b0 < K; b0 += 64) {

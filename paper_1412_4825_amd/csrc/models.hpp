@@ -34,9 +34,9 @@ struct DescDev {
 enum : int32_t { M_TRIANGLE = 0, M_NORMEXP = 1, M_GAMMA = 2, M_LDA = 3, M_EXPCHAIN = 4 };
 enum : uint32_t { FLAG_RESUME = 1u };
 
-// Per-wave LDS: three rings and an auxiliary area (LDA bin boundaries and
-// counts).
-constexpr int AUX_BYTES = 2048;
+// Per-wave LDS: three rings and an auxiliary area (LDA bin boundaries,
+// counts and component gammas).
+constexpr int AUX_BYTES = 3072;
 constexpr int WAVE_LDS_BYTES = 3 * RING_BYTES + AUX_BYTES;
 
 struct Pools {
@@ -409,6 +409,8 @@ __device__ void unit_expchain(const DescDev& D, Meta* mp, const Pools& P, uint32
 
 // ---------------------------------------------------------------------------
 // Varying-shape gamma chain: g_t ~ Gamma(alpha_t, 1), alpha_{t+1} = 0.1 + g_t.
+// Each lane runs its chain through the gamma rounds and starts its next step
+// as soon as a draw is accepted.
 // ---------------------------------------------------------------------------
 __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t local,
                            unsigned char* lds) {
@@ -416,8 +418,8 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
     const uint32_t slot = local * 64 + lane;
     const bool in0 = slot < D.n_chains;
     const uint32_t chain = in0 ? (D.perm ? (uint32_t)D.perm[slot] : slot) : 0;
-    const bool in = in0 && chain < D.n_chains;  // a bad permutation entry idles the lane
-    const int32_t L = in ? (D.steps ? D.steps[chain] : D.max_steps) : 0;
+    const bool in = in0 && chain < D.n_chains;
+    const int32_t L = in ? min(D.steps ? D.steps[chain] : D.max_steps, D.max_steps) : 0;
     const Meta m = open_meta(D, mp, local);
     const uint32_t gu = D.unit_base + local;
     StagedReader<KIND_N> rn;
@@ -426,49 +428,21 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
     re.open(m, P.e + (size_t)gu * P.W[KIND_E], P.W[KIND_E],
             reinterpret_cast<float*>(lds + RING_BYTES));
     float* st = reinterpret_cast<float*>(D.state);
-    float alpha = in ? st[chain] : 1.0f;
-    float* tg = reinterpret_cast<float*>(D.trace);
-    for (int32_t t = 0; t < D.max_steps; ++t) {
-        const bool act = in && t < L;
-        if (wave_ballot(act) == 0) break;
-        const float g = gamma_call(rn, re, act, alpha);
-        if (act) {
-            if (tg) tg[(size_t)t * D.stride + slot] = g;
-            alpha = 0.1f + g;
-        }
-    }
-    if (in) st[chain] = alpha;
+    ChainSrc src;
+    src.t = 0;
+    src.L = L;
+    src.alpha = in ? st[chain] : 1.0f;
+    src.out = D.trace ? reinterpret_cast<float*>(D.trace) + slot : nullptr;
+    src.stride = D.stride;
+    const uint32_t smax = (uint32_t)min(D.max_steps, 1 << 24);
+    gamma_rounds(rn, re, src, 4096u + 64u * smax);
+    if (in) st[chain] = src.alpha;
     rn.close(*mp);
     re.close(*mp);
     store_key(mp, m);
 }
 
-// ---------------------------------------------------------------------------
-// Dirichlet for one item of K components (batches of 64 lanes, one gamma
-// call per batch, ascending), normalised by the sum (Sec. 1, footnote).
-// y holds up to 4 batches (K <= 256) in registers; larger K reads alpha per
-// batch and keeps y in the output array.
-// ---------------------------------------------------------------------------
 constexpr int LDA_KMAX = 256;
-
-template <class RN, class RE>
-__device__ __forceinline__ float dirichlet_sum4(RN& rn, RE& re, int K, const float* alpha_of,
-                                                float y[4]) {
-    const uint32_t lane = lane_id();
-    float part = 0.0f;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int k = b * 64 + (int)lane;
-        if (b * 64 < K) {
-            const bool act = k < K;
-            y[b] = gamma_call(rn, re, act, act ? alpha_of[b] : 1.0f);
-            if (act) part += y[b];
-        } else {
-            y[b] = 0.0f;
-        }
-    }
-    return wave_sum(part);
-}
 
 // ---------------------------------------------------------------------------
 // LDA-style document: per sweep, theta ~ Dirichlet(0.1 + counts), then
@@ -476,6 +450,7 @@ __device__ __forceinline__ float dirichlet_sum4(RN& rn, RE& re, int K, const flo
 //   q_k = rint(theta_k 2^24), Q = sum q_k (all q_k = 1 when Q = 0),
 //   C_k = q_0 + ... + q_k; token i takes u_i from the U pool,
 //   j = (u_i 2^24 - 1) / 2, t = (j Q) >> 23, bin = first k with t < C_k.
+// LDS holds the bin ends, the counts and the component gammas (K <= 256).
 // ---------------------------------------------------------------------------
 __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t doc,
                          unsigned char* lds) {
@@ -495,20 +470,37 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
             reinterpret_cast<float*>(lds + 2 * RING_BYTES));
     int32_t* Cs = reinterpret_cast<int32_t*>(lds + 3 * RING_BYTES);  // 256 bin ends
     int32_t* cnt = Cs + LDA_KMAX;                                      // 256 counts
+    float* yv = reinterpret_cast<float*>(cnt + LDA_KMAX);              // 256 gammas
     int32_t* counts = reinterpret_cast<int32_t*>(D.state) + off;
     float* th_tr = reinterpret_cast<float*>(D.trace);
     int32_t* ct_tr = reinterpret_cast<int32_t*>(D.trace2);
-    int32_t c[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int k = b * 64 + (int)lane;
-        c[b] = (k < K) ? counts[k] : 0;
+        if (k < K) cnt[k] = counts[k];
     }
     for (int32_t sw = 0; sw < D.max_steps; ++sw) {
-        float al[4], y[4];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        CompSrc src;
+        src.K = K;
+        src.alpha = nullptr;
+        src.cnt = cnt;
+        src.y = yv;
+        gamma_rounds(rn, re, src, 4096u + 64u * (uint32_t)K);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float y[4];
+        float part = 0.0f;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) al[b] = 0.1f + (float)c[b];
-        const float S = dirichlet_sum4(rn, re, K, al, y);
+        for (int b = 0; b < 4; ++b) {
+            const int k = b * 64 + (int)lane;
+            y[b] = (k < K) ? yv[k] : 0.0f;
+            if (k < K) part += y[b];
+        }
+        const float S = wave_sum(part);
         // theta, quantised weights and their prefix sums
         int32_t carry = 0;
         float th[4];
@@ -566,16 +558,15 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
         for (int b = 0; b < 4; ++b) {
             const int k = b * 64 + (int)lane;
             if (k < K) {
-                c[b] = cnt[k];
                 if (th_tr) th_tr[(size_t)sw * D.stride + off + k] = th[b];
-                if (ct_tr) ct_tr[(size_t)sw * D.stride + off + k] = c[b];
+                if (ct_tr) ct_tr[(size_t)sw * D.stride + off + k] = cnt[k];
             }
         }
     }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int k = b * 64 + (int)lane;
-        if (k < K) counts[k] = c[b];
+        if (k < K) counts[k] = cnt[k];
     }
     rn.close(*mp);
     re.close(*mp);

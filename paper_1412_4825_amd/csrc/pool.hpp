@@ -184,7 +184,7 @@ struct StagedReader {
         const uint32_t n = (uint32_t)__popcll(m);
         const uint32_t r = mask_rank(m);
         ensure(cur + n);
-        const T v = ring[(cur + r) & (R - 1)];
+        const T v = ring[((uint32_t)cur + r) & (R - 1)];
         cur += n;
         return active ? v : T(0);
     }

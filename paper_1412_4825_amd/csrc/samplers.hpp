@@ -44,56 +44,184 @@ __device__ __noinline__ bool mt_accept64(float a, float x, float e) {
 }
 
 // Shapes outside (0, 2^64) would never be accepted (or are meaningless);
-// such lanes return NaN instead of looping.
+// such draws complete at once with NaN and consume nothing.
 __device__ __forceinline__ bool gamma_shape_ok(float alpha) {
     return alpha > 0.0f && alpha < 0x1p64f;
 }
 
-constexpr int MT_MAX_ROUNDS = 4096;  // never reached for valid shapes
+// Per-lane constants of the draw a lane holds.
+struct GammaLane {
+    float alpha, a, d, c;
+    bool valid, boost;
+    __device__ __forceinline__ void setup(float al) {
+        alpha = al;
+        valid = gamma_shape_ok(al);
+        boost = valid && al < 1.0f;
+        a = valid ? (boost ? al + 1.0f : al) : 1.0f;
+        d = a - (1.0f / 3.0f);
+        c = __builtin_amdgcn_rsqf(9.0f * d);  // 1 / sqrt(9 d)
+    }
+};
 
-// One gamma call over the lanes of a wave (active lanes draw one deviate
-// each).  RN / RE are the readers of the Gaussian and exponential pools.
-template <class RN, class RE>
-__device__ __forceinline__ float gamma_call(RN& rn, RE& re, bool active, float alpha) {
-    const bool valid = active && gamma_shape_ok(alpha);
-    const bool boost = valid && alpha < 1.0f;
-    const float a = valid ? (boost ? alpha + 1.0f : alpha) : 1.0f;
-    const float d = a - (1.0f / 3.0f);
-    const float c = 1.0f / (3.0f * sqrtf(d));
-    bool pending = valid;
-    float g = __builtin_nanf("");
-    for (int round = 0; round < MT_MAX_ROUNDS; ++round) {
-        if (wave_ballot(pending) == 0) break;
-        const float x = rn.take(pending);
-        const float y = c * x;
+// The accept decision E + d q(y) > 0 for a lane with 1 + c x = v0 > 0.
+// q(y) <= 0 and, from q'(y) = -3y^3/(1+y), -q(y) <= (3/4) y^4 for y >= 0 and
+// -q(y) <= (3/4) y^4 / (1+y) for -1 < y < 0; so E above that bound (with a
+// margin far above its fp32 error) accepts with no logarithm.  Otherwise the
+// statistic is evaluated in fp32 and, when it is within its fp32 error bound
+// of zero, again in fp64.
+__device__ __forceinline__ bool mt_certain(float d, float y, float v0, float e) {
+    const float y2 = y * y;
+    float bnd = 0.75f * d * (y2 * y2);
+    if (y < 0.0f) bnd *= __builtin_amdgcn_rcpf(v0);
+    return e > bnd * 1.00002f;
+}
+
+// ln(1 + y) for y > -1: the logarithm of the rounded sum u = 1 + y plus the
+// first-order correction for the rounding (y - (u - 1)) / u.
+__device__ __forceinline__ float log1p_fast(float y) {
+    const float u = 1.0f + y;
+    const float corr = (y - (u - 1.0f)) * __builtin_amdgcn_rcpf(u);
+    return fmaf(__builtin_amdgcn_logf(u), 0.693147180559945309f, corr);
+}
+
+__device__ __forceinline__ bool mt_decide(float a, float d, float x, float y, float v0, float e) {
+    const float l = log1p_fast(y);
+    const float y2 = y * y;
+    const float y3 = y2 * y;
+    const float q = (3.0f * l - 3.0f * y) + (1.5f * y2 - y3);
+    const float stat = e + d * q;
+    // bound on the fp32 evaluation error (terms' magnitudes times a few ulp,
+    // plus the effect of y's own rounding)
+    const float mag = e + d * (3.0f * fabsf(l) + 3.0f * fabsf(y) + 1.5f * y2 + fabsf(y3) +
+                               3.0f * y2 * y2 * __builtin_amdgcn_rcpf(v0));
+    if (fabsf(stat) > 2e-6f * mag) return stat > 0.0f;
+    return mt_accept64(a, x, e);
+}
+
+// Gamma draws in rounds over the 64 lanes of a wave.  Each lane holds at most
+// one draw.  Per round: a Gaussian for every lane holding a valid draw, an
+// exponential for those with 1 + c x > 0, the accept test, an exponential for
+// accepted draws with alpha < 1 (the boost), each call handing entries to
+// lanes in lane order; then every lane whose draw is complete hands its value
+// to the source and takes its next draw.  Src provides:
+//   bool first(float& alpha)            initial draw of this lane
+//   bool complete(bool done, float g, float& alpha)
+//                                       called by every lane; for lanes whose
+//                                       draw is done: take g and return
+//                                       whether a next draw follows (with its
+//                                       shape); other lanes' answers are unused
+template <class RN, class RE, class Src>
+__device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t max_rounds) {
+    GammaLane L;
+    float al = 1.0f;
+    bool hold = src.first(al);
+    L.setup(hold ? al : 1.0f);
+    for (uint32_t round = 0; round < max_rounds; ++round) {
+        if (wave_ballot(hold) == 0) break;
+        const bool pend = hold && L.valid;
+        const float x = rn.take(pend);
+        const float y = L.c * x;
         const float v0 = 1.0f + y;
-        const bool need_e = pending && v0 > 0.0f;
+        const bool need_e = pend && v0 > 0.0f;
         const float e = re.take(need_e);
-        if (need_e) {
-            const float l = log1pf(y);
-            const float y2 = y * y;
-            const float y3 = y2 * y;
-            const float q = (3.0f * l - 3.0f * y) + (1.5f * y2 - y3);
-            const float stat = e + d * q;
-            // bound on the fp32 evaluation error (terms' magnitudes times a
-            // few ulp, plus the effect of y's own rounding)
-            const float mag = e + d * (3.0f * fabsf(l) + 3.0f * fabsf(y) + 1.5f * y2 + fabsf(y3) +
-                                       3.0f * y2 * y2 / v0);
-            bool acc;
-            if (fabsf(stat) > 1e-6f * mag)
-                acc = stat > 0.0f;
-            else
-                acc = mt_accept64(a, x, e);
-            if (acc) {
-                g = d * (v0 * v0 * v0);
-                pending = false;
-            }
+        bool acc = need_e && mt_certain(L.d, y, v0, e);
+        if (need_e && !acc) acc = mt_decide(L.a, L.d, x, y, v0, e);
+        float g = L.d * (v0 * v0 * v0);
+        const bool b = acc && L.boost;
+        const float e2 = re.take(b);
+        // boost: g exp(-E'/alpha) = 2^(log2 g - E' log2(e) / alpha), one
+        // exponential whose result underflows only when the product does
+        if (b)
+            g = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(g) -
+                                       e2 * (1.44269504088896341f * __builtin_amdgcn_rcpf(L.alpha)));
+        const bool done = hold && (acc || !L.valid);
+        if (done && !L.valid) g = __builtin_nanf("");
+        // every lane calls complete (it may use wave-wide operations); only
+        // lanes whose draw completed take its answer
+        const bool next_hold = src.complete(done, g, al);
+        if (done) {
+            hold = next_hold;
+            if (hold) L.setup(al);
         }
     }
-    const float e2 = re.take(boost);
-    if (boost) g = g * expf(-e2 / alpha);
-    return g;
 }
+
+// One draw per lane (the one-at-a-time call).
+struct OneEachSrc {
+    bool act;
+    float alpha;
+    float g;
+    __device__ __forceinline__ bool first(float& a) {
+        a = alpha;
+        return act;
+    }
+    __device__ __forceinline__ bool complete(bool done, float gv, float&) {
+        if (done) g = gv;
+        return false;
+    }
+};
+
+// Components of one Dirichlet item: lanes start with components 0..63 and a
+// lane whose draw completes takes the lowest component not yet started.
+// y receives component k's gamma at y[k].
+struct CompSrc {
+    int K;
+    uint32_t next;  // wave-uniform
+    int comp;
+    const float* alpha;  // per component, or null: 0.1 + cnt[k]
+    const int32_t* cnt;
+    float* y;
+    __device__ __forceinline__ float shape(int k) const {
+        return alpha ? alpha[k] : 0.1f + (float)cnt[k];
+    }
+    __device__ __forceinline__ bool first(float& a) {
+        comp = (int)lane_id();
+        next = (uint32_t)min(K, 64);
+        if (comp < K) {
+            a = shape(comp);
+            return true;
+        }
+        return false;
+    }
+    __device__ __forceinline__ bool complete(bool done, float gv, float& a) {
+        if (done) y[comp] = gv;
+        const uint64_t freed = wave_ballot(done);
+        const uint32_t r = mask_rank(freed);
+        bool h = false;
+        if (done) {
+            const uint32_t nc = next + r;
+            comp = (int)nc;
+            h = nc < (uint32_t)K;
+            if (h) a = shape(comp);
+        }
+        next += (uint32_t)__popcll(freed);
+        return h;
+    }
+};
+
+// One chain per lane: g_t ~ Gamma(alpha_t, 1), alpha_{t+1} = 0.1 + g_t; the
+// lane starts its next step as soon as a draw is accepted.
+struct ChainSrc {
+    int32_t t, L;
+    float alpha;
+    float* out;      // this lane's entry of the trace row of step t, or null
+    int64_t stride;  // trace elements between steps
+    __device__ __forceinline__ bool first(float& a) {
+        a = alpha;
+        return t < L;
+    }
+    __device__ __forceinline__ bool complete(bool done, float gv, float& a) {
+        if (!done) return false;
+        if (out) {
+            *out = gv;
+            out += stride;
+        }
+        alpha = 0.1f + gv;
+        ++t;
+        a = alpha;
+        return t < L;
+    }
+};
 
 // Sum over the wave, identical in every lane (fixed butterfly order, then
 // lane 0's value broadcast).

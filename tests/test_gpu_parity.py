@@ -350,25 +350,44 @@ def test_window_length_invariance(dev):
 
 
 def test_step_api_equals_chain_kernel(dev):
-    """A host loop of one-at-a-time gamma calls reproduces the chain kernel
-    bit for bit (same streams, same consumption order)."""
+    """A host loop of one-at-a-time calls (normal then exponential, the
+    parameters computed between launches) follows the same streams as the
+    normal/exponential chain kernel: s' bit for bit, e to 2 ulp (the loop
+    forms 1 + s'^2 with two roundings, the kernel with one), same cursors."""
     import torch
     b = _b()
     n, steps, seed = 640, 40, 12
-    w = workloads.gamma_chain(n_chains=n, lmin=steps, lmax=steps, seed=2)
     _say("step loop vs chain", n, steps)
-    g, alpha, cur, perm = _run_gamma_chain(dev, w, seed, W_SMALL)
+    ctx = _ctx(seed, n, W_SMALL)
+    st = torch.zeros(n, dtype=torch.float32, device=dev)
+    ts = torch.zeros((steps, n), dtype=torch.float32, device=dev)
+    te = torch.zeros((steps, n), dtype=torch.float32, device=dev)
+    try:
+        _gibbs(ctx, b.BRNG_MODEL_NORMEXP, n, st, steps, seed, dev, ts, te, n)
+        S, E, cur = _np(ts), _np(te), b.brng_get_cursors(ctx)
+    finally:
+        b.brng_destroy(ctx)
     ctx = _ctx(seed, n, W_SMALL)
     try:
-        a = _t(w["alpha0"][perm], dev)
-        out = torch.zeros(n, dtype=torch.float32, device=dev)
-        rows = []
+        zeros = torch.zeros(n, dtype=torch.float32, device=dev)
+        ones = torch.ones(n, dtype=torch.float32, device=dev)
+        s = torch.zeros(n, dtype=torch.float32, device=dev)
+        b.brng_step_normal(ctx, zeros, ones, s)  # s_0: the first Gaussian
+        rs, re_ = [], []
         for t in range(steps):
-            b.brng_step_gamma(ctx, a, out)
-            rows.append(out.clone())
-            a = torch.tensor(0.1, dtype=torch.float32, device=dev) + out
-        G = _np(torch.stack(rows))
-        assert np.array_equal(G, g)
+            mu = s * 0.9
+            sigma = s.abs() + 0.5
+            sp = torch.empty_like(s)
+            b.brng_step_normal(ctx, mu, sigma, sp)
+            lam = sp * sp + 1.0
+            e = torch.empty_like(s)
+            b.brng_step_exp(ctx, lam, e)
+            rs.append(sp)
+            re_.append(e)
+            s = sp
+        assert np.array_equal(_np(torch.stack(rs)), S)
+        ge = _np(torch.stack(re_)).astype(np.float64)
+        assert np.all(np.abs(ge - E) <= 2 * np.spacing(np.abs(E).astype(np.float32)))
         assert np.array_equal(b.brng_get_cursors(ctx), cur)
     finally:
         b.brng_destroy(ctx)
