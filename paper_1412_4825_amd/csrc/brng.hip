@@ -156,7 +156,7 @@ __global__ __launch_bounds__(512) void k_step_gamma(Meta* meta, Pools P, uint32_
     rn.open(meta[unit], P.n + (size_t)unit * P.W[KIND_N], P.W[KIND_N]);
     re.open(meta[unit], P.e + (size_t)unit * P.W[KIND_E], P.W[KIND_E]);
     OneEachSrc src;
-    src.act = act;
+    src.want = act ? 1 : 0;
     src.alpha = act ? alpha[c] : 1.0f;
     src.g = 0.0f;
     gamma_rounds(rn, re, src, 4096u);
@@ -215,10 +215,10 @@ __device__ __forceinline__ void run_unit(const DescDev& D, Meta* meta, const Poo
 }
 
 __host__ __device__ constexpr int model_lds_bytes(int model) {
-    return model == M_LDA        ? WAVE_LDS_BYTES
+    return model == M_LDA        ? LDA_LDS_BYTES
            : model == M_NORMEXP  ? NORMEXP_LDS_BYTES
            : model == M_EXPCHAIN ? EXPCHAIN_LDS_BYTES
-           : model == M_GAMMA    ? 2 * RING_BYTES
+           : model == M_GAMMA    ? GAMMA_LDS_BYTES
                                  : RING_BYTES;
 }
 
@@ -523,9 +523,18 @@ static DescDev to_dev(const brng_gibbs_desc& d) {
     return D;
 }
 
+// Waves per block for a model: the configured count, halved while a block's
+// LDS would exceed 64 KiB.
+static int model_wpb(const brng_ctx* c, int model) {
+    int w = c->wpb;
+    while (w > 1 && (size_t)w * model_lds_bytes(model) > 65536) w >>= 1;
+    return w;
+}
+
 static brng_status launch_plain(brng_ctx* c, const DescDev& D) {
-    const dim3 grid = unit_grid(c, D.n_units), block(64 * c->wpb);
-    const size_t lds = (size_t)c->wpb * model_lds_bytes(D.model);
+    const int wpb = model_wpb(c, D.model);
+    const dim3 grid((D.n_units + wpb - 1) / wpb), block(64 * wpb);
+    const size_t lds = (size_t)wpb * model_lds_bytes(D.model);
     const Pools P = make_pools(c);
     switch (D.model) {
         case M_TRIANGLE:

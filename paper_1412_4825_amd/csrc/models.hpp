@@ -34,10 +34,9 @@ struct DescDev {
 enum : int32_t { M_TRIANGLE = 0, M_NORMEXP = 1, M_GAMMA = 2, M_LDA = 3, M_EXPCHAIN = 4 };
 enum : uint32_t { FLAG_RESUME = 1u };
 
-// Per-wave LDS: three rings and an auxiliary area (LDA bin boundaries,
-// counts and component gammas).
+// LDA's per-wave auxiliary LDS area: bin boundaries, counts and component
+// gammas (256 each).
 constexpr int AUX_BYTES = 3072;
-constexpr int WAVE_LDS_BYTES = 3 * RING_BYTES + AUX_BYTES;
 
 struct Pools {
     float* u;
@@ -412,6 +411,11 @@ __device__ void unit_expchain(const DescDev& D, Meta* mp, const Pools& P, uint32
 // Each lane runs its chain through the gamma rounds and starts its next step
 // as soon as a draw is accepted.
 // ---------------------------------------------------------------------------
+using GammaRN = EpochReader<KIND_N, 1>;
+using GammaRE = EpochReader<KIND_E, 2>;
+constexpr int GAMMA_OBUF_BYTES = (int)EPOCH_ROUNDS * 64 * 4;
+constexpr int GAMMA_LDS_BYTES = GammaRN::LDS_BYTES + GammaRE::LDS_BYTES + GAMMA_OBUF_BYTES;
+
 __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t local,
                            unsigned char* lds) {
     const uint32_t lane = lane_id();
@@ -422,18 +426,20 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
     const int32_t L = in ? min(D.steps ? D.steps[chain] : D.max_steps, D.max_steps) : 0;
     const Meta m = open_meta(D, mp, local);
     const uint32_t gu = D.unit_base + local;
-    StagedReader<KIND_N> rn;
-    StagedReader<KIND_E> re;
+    GammaRN rn;
+    GammaRE re;
     rn.open(m, P.n + (size_t)gu * P.W[KIND_N], P.W[KIND_N], reinterpret_cast<float*>(lds));
     re.open(m, P.e + (size_t)gu * P.W[KIND_E], P.W[KIND_E],
-            reinterpret_cast<float*>(lds + RING_BYTES));
+            reinterpret_cast<float*>(lds + GammaRN::LDS_BYTES));
     float* st = reinterpret_cast<float*>(D.state);
     ChainSrc src;
     src.t = 0;
     src.L = L;
     src.alpha = in ? st[chain] : 1.0f;
-    src.out = D.trace ? reinterpret_cast<float*>(D.trace) + slot : nullptr;
+    src.trace = D.trace != nullptr;
+    src.out = src.trace ? reinterpret_cast<float*>(D.trace) + slot : nullptr;
     src.stride = D.stride;
+    src.obuf = reinterpret_cast<float*>(lds + GammaRN::LDS_BYTES + GammaRE::LDS_BYTES) + lane;
     const uint32_t smax = (uint32_t)min(D.max_steps, 1 << 24);
     gamma_rounds(rn, re, src, 4096u + 64u * smax);
     if (in) st[chain] = src.alpha;
@@ -443,6 +449,11 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
 }
 
 constexpr int LDA_KMAX = 256;
+using LdaRN = EpochReader<KIND_N, 1>;
+using LdaRE = EpochReader<KIND_E, 1>;
+using LdaRU = EpochReader<KIND_U, 1>;
+constexpr int LDA_RINGS_BYTES = LdaRN::LDS_BYTES + LdaRE::LDS_BYTES + LdaRU::LDS_BYTES;
+constexpr int LDA_LDS_BYTES = LDA_RINGS_BYTES + AUX_BYTES;
 
 // ---------------------------------------------------------------------------
 // LDA-style document: per sweep, theta ~ Dirichlet(0.1 + counts), then
@@ -460,15 +471,15 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
     const int32_t off = D.offsets[doc];
     const int K = D.offsets[doc + 1] - off;
     const int ntok = D.ntok[doc];
-    StagedReader<KIND_N> rn;
-    StagedReader<KIND_E> re;
-    StagedReader<KIND_U> ru;
+    LdaRN rn;
+    LdaRE re;
+    LdaRU ru;
     rn.open(m, P.n + (size_t)gu * P.W[KIND_N], P.W[KIND_N], reinterpret_cast<float*>(lds));
     re.open(m, P.e + (size_t)gu * P.W[KIND_E], P.W[KIND_E],
-            reinterpret_cast<float*>(lds + RING_BYTES));
+            reinterpret_cast<float*>(lds + LdaRN::LDS_BYTES));
     ru.open(m, P.u + (size_t)gu * P.W[KIND_U], P.W[KIND_U],
-            reinterpret_cast<float*>(lds + 2 * RING_BYTES));
-    int32_t* Cs = reinterpret_cast<int32_t*>(lds + 3 * RING_BYTES);  // 256 bin ends
+            reinterpret_cast<float*>(lds + LdaRN::LDS_BYTES + LdaRE::LDS_BYTES));
+    int32_t* Cs = reinterpret_cast<int32_t*>(lds + LDA_RINGS_BYTES);  // 256 bin ends
     int32_t* cnt = Cs + LDA_KMAX;                                      // 256 counts
     float* yv = reinterpret_cast<float*>(cnt + LDA_KMAX);              // 256 gammas
     int32_t* counts = reinterpret_cast<int32_t*>(D.state) + off;

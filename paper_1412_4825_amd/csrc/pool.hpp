@@ -49,7 +49,7 @@ __device__ __forceinline__ uint32_t mask_rank(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -100,20 +100,32 @@ struct DirectReader {
         cur = m.cur[KIND];
         W = Wk;
     }
-    __device__ __forceinline__ T take(bool active) {
-        const uint64_t m = wave_ballot(active);
-        const uint32_t n = (uint32_t)__popcll(m);
-        const uint32_t r = mask_rank(m);
+    // Make entries [cur, cur + n) readable.
+    __device__ __forceinline__ void reserve(uint32_t n) {
         if (cur < wbase || cur + n > wbase + wlen) {
             const uint64_t first = cur & ~(uint64_t)(CH - 1);
             refill_window<KIND>(win, key, first, W);
             wbase = first;
             wlen = W;
         }
-        const T v = active ? win[cur + r - wbase] : T(0);
-        cur += n;
+    }
+    // Entry cur + r; r up to 64 is safe after reserve (clamped to the window).
+    __device__ __forceinline__ T peek(uint32_t r) const {
+        const uint64_t i = cur + r;
+        return win[(i < wbase + wlen ? i : wbase + wlen - 1) - wbase];
+    }
+    __device__ __forceinline__ void advance(uint32_t n) { cur += n; }
+    __device__ __forceinline__ T take(bool active) {
+        const uint64_t m = wave_ballot(active);
+        const uint32_t n = (uint32_t)__popcll(m);
+        reserve(n);
+        const T v = active ? peek(mask_rank(m)) : T(0);
+        advance(n);
         return v;
     }
+    __device__ __forceinline__ bool room() const { return false; }
+    __device__ __forceinline__ void put() {}
+    __device__ __forceinline__ void prefetch() {}
     __device__ void close(Meta& m) const {
         if (lane_id() == 0) {
             m.cur[KIND] = cur;
@@ -178,16 +190,21 @@ struct StagedReader {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    __device__ __forceinline__ void reserve(uint32_t n) { ensure(cur + n); }
+    __device__ __forceinline__ T peek(uint32_t r) const { return ring[((uint32_t)cur + r) & (R - 1)]; }
+    __device__ __forceinline__ void advance(uint32_t n) { cur += n; }
     // One call: every active lane gets the next entry, in lane order.
     __device__ __forceinline__ T take(bool active) {
         const uint64_t m = wave_ballot(active);
         const uint32_t n = (uint32_t)__popcll(m);
-        const uint32_t r = mask_rank(m);
-        ensure(cur + n);
-        const T v = ring[((uint32_t)cur + r) & (R - 1)];
-        cur += n;
+        reserve(n);
+        const T v = peek(mask_rank(m));
+        advance(n);
         return active ? v : T(0);
     }
+    __device__ __forceinline__ bool room() const { return false; }
+    __device__ __forceinline__ void put() {}
+    __device__ __forceinline__ void prefetch() {}
     __device__ void close(Meta& m) const {
         if (lane_id() == 0) {
             m.cur[KIND] = cur;
@@ -204,6 +221,165 @@ __device__ __forceinline__ void static_for(F&& f) {
         f(std::integral_constant<int, I>{});
         static_for<I + 1, N>(f);
     }
+}
+
+// Native four-word vector (kept in registers where HIP's uint4 struct is not).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Epoch reader: the staged reader for rejection loops, where the number of
+// entries a call takes is only known at the call.  On gfx9 one counter
+// tracks every outstanding vector memory operation, loads and stores alike,
+// so waiting for a prefetched chunk also waits for whatever was issued after
+// it.  The caller therefore stages all its readers together at fixed points
+// ("epochs", every few rounds of its loop) and issues its own global stores
+// right after them: each wait then covers only operations issued one epoch
+// earlier.  A chunk is CHV 16-byte loads per lane (CH entries); the LDS ring
+// holds two chunks and the next chunk waits in registers.  A chunk is
+// prefetched only when it lies inside the current window; otherwise the
+// window is regenerated (the blocking refill) when that chunk is staged.
+// If a call needs more than the ring holds, it stages at once (correct,
+// only slower); sized so that an epoch's worst case fits, that never happens.
+// ---------------------------------------------------------------------------
+template <uint32_t KIND, int CHV>
+struct EpochReader {
+    using T = typename KindTraits<KIND>::T;
+    static constexpr int EPB = KindTraits<KIND>::EPB;
+    static constexpr uint32_t CH = 64u * EPB * CHV;
+    static constexpr uint32_t R = 2 * CH;
+    // the ring, then a copy of its first 64 entries, so that the 64 entries
+    // from any position are contiguous
+    static constexpr int LDS_BYTES = (int)((R + 64) * sizeof(T));
+    T* win;
+    T* ring;  // LDS, R + 64 entries
+    Key key;
+    uint64_t wbase, cur, staged;  // ring holds entries [.., staged)
+    uint32_t wlen, W;
+    int32_t avail;  // staged - cur
+    bool inflight;  // pf holds chunk `staged`
+    u32x4 pf[CHV];
+
+    __device__ __forceinline__ bool in_window(uint64_t f) const {
+        return f >= wbase && f + CH <= wbase + wlen;
+    }
+    __device__ __forceinline__ void load(uint64_t f) {
+        const u32x4* src = reinterpret_cast<const u32x4*>(win + (f - wbase)) + lane_id();
+#pragma unroll
+        for (int j = 0; j < CHV; ++j) pf[j] = src[j * 64];
+    }
+    // Whether the ring has room for the waiting chunk.
+    __device__ __forceinline__ bool room() const { return avail <= (int32_t)(R - CH); }
+    // Move chunk `staged` into the ring (needs room()).  Without a prefetched
+    // copy the window is regenerated first and the chunk read at once.
+    __device__ __forceinline__ void put() {
+        const uint32_t off = (uint32_t)staged & (R - 1);
+        u32x4* dst = reinterpret_cast<u32x4*>(ring + off) + lane_id();
+        u32x4 head;
+        if (inflight) {
+#pragma unroll
+            for (int j = 0; j < CHV; ++j) dst[j * 64] = pf[j];
+            head = pf[0];
+        } else {
+            // Regenerate the window from `staged`.  The chunk's own blocks
+            // are the first CHV blocks each lane generates, so they go to the
+            // ring straight from registers.  Later loads of the window are
+            // issued after these stores by the same wave, which sees them (one
+            // vector L1 per CU, operations performed in order); the fence only
+            // keeps the compiler from moving memory operations across.
+            const uint32_t lane = lane_id();
+            const uint64_t b0 = staged / EPB;
+            const uint32_t nblk = W / EPB;
+            uint4* wd = reinterpret_cast<uint4*>(win);
+            u32x4 tmp[CHV];
+#pragma unroll
+            for (int j = 0; j < CHV; ++j) {
+                const uint4 v = gen_block<KIND>(key, b0 + (uint32_t)(j * 64) + lane);
+                wd[j * 64 + lane] = v;
+                tmp[j] = u32x4{v.x, v.y, v.z, v.w};
+            }
+            for (uint32_t b = (uint32_t)(CHV * 64) + lane; b < nblk; b += 64)
+                wd[b] = gen_block<KIND>(key, b0 + b);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            wbase = staged;
+            wlen = W;
+#pragma unroll
+            for (int j = 0; j < CHV; ++j) dst[j * 64] = tmp[j];
+            head = tmp[0];
+        }
+        // the mirror: entries 0..63 of the ring are lanes 0 .. 64/EPB - 1 of
+        // the first load of the chunk at offset 0
+        if (off == 0 && lane_id() < 64u / EPB) reinterpret_cast<u32x4*>(ring + R)[lane_id()] = head;
+        staged += CH;
+        avail += (int32_t)CH;
+    }
+    // Prefetch chunk `staged`.  The load is issued unconditionally (outside
+    // the window it reads the window's first chunk, a value never used), so
+    // its registers are the ones put() writes out, with no copy in between.
+    __device__ __forceinline__ void prefetch() {
+        inflight = in_window(staged);
+        load(inflight ? staged : wbase);
+    }
+    __device__ __forceinline__ void stage() {
+        put();
+        prefetch();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __device__ __forceinline__ void open(const Meta& m, T* pool_unit, uint32_t Wk, T* lds_ring) {
+        win = pool_unit;
+        ring = lds_ring;
+        key = meta_key(m);
+        wbase = m.wbase[KIND];
+        wlen = m.wlen[KIND];
+        W = Wk;
+        cur = m.cur[KIND];
+        staged = cur & ~(uint64_t)(CH - 1);
+        avail = -(int32_t)(cur - staged);
+        prefetch();
+        stage();
+    }
+    // Make entries [cur, cur + n) readable (n <= 64).
+    __device__ __forceinline__ void reserve(uint32_t n) {
+        while ((int32_t)n > avail) stage();
+    }
+    // Entry cur + r (r < 64, after reserve).
+    __device__ __forceinline__ T peek(uint32_t r) const { return ring[((uint32_t)cur & (R - 1)) + r]; }
+    __device__ __forceinline__ void advance(uint32_t n) {
+        cur += n;
+        avail -= (int32_t)n;
+    }
+    // One call: every active lane gets the next entry, in lane order.
+    __device__ __forceinline__ T take(bool active) {
+        const uint64_t m = wave_ballot(active);
+        const uint32_t n = (uint32_t)__popcll(m);
+        reserve(n);
+        const T v = peek(mask_rank(m));
+        advance(n);
+        return active ? v : T(0);
+    }
+    __device__ void close(Meta& m) const {
+        if (lane_id() == 0) {
+            m.cur[KIND] = cur;
+            m.wbase[KIND] = wbase;
+            m.wlen[KIND] = wlen;
+        }
+    }
+};
+
+// Epoch point for a set of readers: every ring with room takes its waiting
+// chunk, and only then are the next chunks requested, so that no reader's
+// wait (for its own, epoch-old prefetch) also waits for a load just issued.
+template <class... Rs>
+__device__ __forceinline__ void epoch_point(Rs&... rs) {
+    const bool go[] = {rs.room()...};
+    int i = 0;
+    ((go[i++] ? rs.put() : void()), ...);
+    i = 0;
+    ((go[i++] ? rs.prefetch() : void()), ...);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ---------------------------------------------------------------------------

@@ -51,7 +51,7 @@ __device__ __forceinline__ bool gamma_shape_ok(float alpha) {
 
 // Per-lane constants of the draw a lane holds.
 struct GammaLane {
-    float alpha, a, d, c;
+    float alpha, a, d, c, dq;
     bool valid, boost;
     __device__ __forceinline__ void setup(float al) {
         alpha = al;
@@ -60,6 +60,7 @@ struct GammaLane {
         a = valid ? (boost ? al + 1.0f : al) : 1.0f;
         d = a - (1.0f / 3.0f);
         c = __builtin_amdgcn_rsqf(9.0f * d);  // 1 / sqrt(9 d)
+        dq = d * 0.750015f;                   // (3/4) d, times the squeeze margin 1.00002
     }
 };
 
@@ -68,12 +69,12 @@ struct GammaLane {
 // -q(y) <= (3/4) y^4 / (1+y) for -1 < y < 0; so E above that bound (with a
 // margin far above its fp32 error) accepts with no logarithm.  Otherwise the
 // statistic is evaluated in fp32 and, when it is within its fp32 error bound
-// of zero, again in fp64.
-__device__ __forceinline__ bool mt_certain(float d, float y, float v0, float e) {
+// of zero, again in fp64.  dq = (3/4) d times the margin.
+__device__ __forceinline__ bool mt_certain(float dq, float y, float v0, float e) {
     const float y2 = y * y;
-    float bnd = 0.75f * d * (y2 * y2);
-    if (y < 0.0f) bnd *= __builtin_amdgcn_rcpf(v0);
-    return e > bnd * 1.00002f;
+    const float b = dq * (y2 * y2);
+    const float bn = b * __builtin_amdgcn_rcpf(v0);
+    return e > (y < 0.0f ? bn : b);
 }
 
 // ln(1 + y) for y > -1: the logarithm of the rounded sum u = 1 + y plus the
@@ -103,62 +104,101 @@ __device__ __forceinline__ bool mt_decide(float a, float d, float x, float y, fl
 // exponential for those with 1 + c x > 0, the accept test, an exponential for
 // accepted draws with alpha < 1 (the boost), each call handing entries to
 // lanes in lane order; then every lane whose draw is complete hands its value
-// to the source and takes its next draw.  Src provides:
-//   bool first(float& alpha)            initial draw of this lane
-//   bool complete(bool done, float g, float& alpha)
-//                                       called by every lane; for lanes whose
-//                                       draw is done: take g and return
-//                                       whether a next draw follows (with its
-//                                       shape); other lanes' answers are unused
+// to the source and takes its next draw.  Every EPOCH_ROUNDS rounds the
+// readers stage their next chunks and the source flushes what it buffered
+// (the readers' epoch points).
+//
+// The loop carries only numbers (the shape of the draw each lane holds and
+// the source's counters); the per-lane conditions are derived from them at
+// the top of each round, which keeps lane-mask bookkeeping out of the loop.
+// Src provides:
+//   float first()                 shape of this lane's first draw (any
+//                                 value if it holds none)
+//   bool holding()                whether this lane holds a draw
+//   float complete(bool done, float g, float alpha)
+//                                 called by every lane; a lane whose draw is
+//                                 done hands over g; returns the shape of the
+//                                 lane's draw for the next round
+//   void flush()                  epoch point (global stores go here)
+constexpr uint32_t EPOCH_ROUNDS = 4;
+
 template <class RN, class RE, class Src>
 __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t max_rounds) {
-    GammaLane L;
-    float al = 1.0f;
-    bool hold = src.first(al);
-    L.setup(hold ? al : 1.0f);
+    float al = src.first();
+    // Let every load issued so far land here, once: otherwise the first use
+    // of a loaded value inside the loop makes the compiler wait for all
+    // memory operations in flight at that point of every round.
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     for (uint32_t round = 0; round < max_rounds; ++round) {
+        const bool hold = src.holding();
         if (wave_ballot(hold) == 0) break;
+        if ((round & (EPOCH_ROUNDS - 1)) == 0) {
+            epoch_point(rn, re);
+            src.flush();
+        }
+        GammaLane L;
+        L.setup(al);
         const bool pend = hold && L.valid;
-        const float x = rn.take(pend);
+        // The Gaussian call and the exponential call hand entries to the
+        // same lanes whenever every pending lane has 1 + c x > 0, which is
+        // nearly always: both are read with the same ranks at once, and the
+        // exponential call is redone with its own ranks when it is not so.
+        const uint64_t mp = wave_ballot(pend);
+        const uint32_t np = (uint32_t)__popcll(mp);
+        rn.reserve(np);
+        re.reserve(np);
+        const uint32_t rk = mask_rank(mp);
+        const float xr = rn.peek(rk);
+        float e = re.peek(rk);
+        rn.advance(np);
+        const float x = pend ? xr : 0.0f;
         const float y = L.c * x;
         const float v0 = 1.0f + y;
         const bool need_e = pend && v0 > 0.0f;
-        const float e = re.take(need_e);
-        bool acc = need_e && mt_certain(L.d, y, v0, e);
-        if (need_e && !acc) acc = mt_decide(L.a, L.d, x, y, v0, e);
+        const uint64_t me = wave_ballot(need_e);
+        if (me == mp) {
+            re.advance(np);
+        } else {
+            const uint32_t ne = (uint32_t)__popcll(me);
+            e = re.peek(mask_rank(me));
+            re.advance(ne);
+        }
+        const bool sure = mt_certain(L.dq, y, v0, e);
+        bool acc = need_e && sure;
+        if (wave_ballot(need_e && !sure) != 0) {
+            const bool r = mt_decide(L.a, L.d, x, y, v0, e);
+            acc = need_e && (sure || r);
+        }
         float g = L.d * (v0 * v0 * v0);
         const bool b = acc && L.boost;
-        const float e2 = re.take(b);
         // boost: g exp(-E'/alpha) = 2^(log2 g - E' log2(e) / alpha), one
         // exponential whose result underflows only when the product does
-        if (b)
-            g = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(g) -
-                                       e2 * (1.44269504088896341f * __builtin_amdgcn_rcpf(L.alpha)));
-        const bool done = hold && (acc || !L.valid);
-        if (done && !L.valid) g = __builtin_nanf("");
-        // every lane calls complete (it may use wave-wide operations); only
-        // lanes whose draw completed take its answer
-        const bool next_hold = src.complete(done, g, al);
-        if (done) {
-            hold = next_hold;
-            if (hold) L.setup(al);
+        if (wave_ballot(b) != 0) {
+            const float e2 = re.take(b);
+            const float gb = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(g) -
+                                                    e2 * (1.44269504088896341f * __builtin_amdgcn_rcpf(al)));
+            g = b ? gb : g;
         }
+        const bool done = hold && (acc || !L.valid);
+        g = L.valid ? g : __builtin_nanf("");
+        al = src.complete(done, g, al);
     }
+    src.flush();
 }
 
 // One draw per lane (the one-at-a-time call).
 struct OneEachSrc {
-    bool act;
+    int32_t want;  // 1 while this lane's draw is pending
     float alpha;
     float g;
-    __device__ __forceinline__ bool first(float& a) {
-        a = alpha;
-        return act;
+    __device__ __forceinline__ float first() { return want ? alpha : 1.0f; }
+    __device__ __forceinline__ bool holding() const { return want != 0; }
+    __device__ __forceinline__ float complete(bool done, float gv, float al) {
+        g = done ? gv : g;
+        want = done ? 0 : want;
+        return al;
     }
-    __device__ __forceinline__ bool complete(bool done, float gv, float&) {
-        if (done) g = gv;
-        return false;
-    }
+    __device__ __forceinline__ void flush() {}
 };
 
 // Components of one Dirichlet item: lanes start with components 0..63 and a
@@ -174,52 +214,67 @@ struct CompSrc {
     __device__ __forceinline__ float shape(int k) const {
         return alpha ? alpha[k] : 0.1f + (float)cnt[k];
     }
-    __device__ __forceinline__ bool first(float& a) {
+    __device__ __forceinline__ float first() {
         comp = (int)lane_id();
         next = (uint32_t)min(K, 64);
-        if (comp < K) {
-            a = shape(comp);
-            return true;
-        }
-        return false;
+        return comp < K ? shape(comp) : 1.0f;
     }
-    __device__ __forceinline__ bool complete(bool done, float gv, float& a) {
+    __device__ __forceinline__ bool holding() const { return comp < K; }
+    __device__ __forceinline__ float complete(bool done, float gv, float al) {
         if (done) y[comp] = gv;
         const uint64_t freed = wave_ballot(done);
         const uint32_t r = mask_rank(freed);
-        bool h = false;
+        float a = al;
         if (done) {
-            const uint32_t nc = next + r;
-            comp = (int)nc;
-            h = nc < (uint32_t)K;
-            if (h) a = shape(comp);
+            comp = (int)(next + r);
+            if (comp < K) a = shape(comp);
         }
         next += (uint32_t)__popcll(freed);
-        return h;
+        return a;
     }
+    __device__ __forceinline__ void flush() {}
 };
 
 // One chain per lane: g_t ~ Gamma(alpha_t, 1), alpha_{t+1} = 0.1 + g_t; the
-// lane starts its next step as soon as a draw is accepted.
+// lane starts its next step as soon as a draw is accepted.  Trace values wait
+// in LDS (at most EPOCH_ROUNDS per lane, one per round) and go out at the
+// epoch points.
 struct ChainSrc {
     int32_t t, L;
     float alpha;
-    float* out;      // this lane's entry of the trace row of step t, or null
+    bool trace;      // wave-uniform: write the trace
+    float* out;      // this lane's entry of the trace row of the next flushed step
     int64_t stride;  // trace elements between steps
-    __device__ __forceinline__ bool first(float& a) {
-        a = alpha;
-        return t < L;
+    float* obuf;     // LDS, EPOCH_ROUNDS x 64 values; this lane's column
+    uint32_t nb;     // values buffered by this lane
+    __device__ __forceinline__ float first() {
+        nb = 0;
+        return alpha;
     }
-    __device__ __forceinline__ bool complete(bool done, float gv, float& a) {
-        if (!done) return false;
-        if (out) {
-            *out = gv;
-            out += stride;
+    __device__ __forceinline__ bool holding() const { return t < L; }
+    // Branch-free: every lane writes its value to its next buffer slot, and
+    // only lanes whose draw completed move on (a slot written by a lane that
+    // did not is overwritten before it is flushed).
+    __device__ __forceinline__ float complete(bool done, float gv, float) {
+        if (trace) {
+            obuf[nb * 64] = gv;
+            nb += done ? 1u : 0u;
         }
-        alpha = 0.1f + gv;
-        ++t;
-        a = alpha;
-        return t < L;
+        alpha = done ? 0.1f + gv : alpha;
+        t += done ? 1 : 0;
+        return alpha;
+    }
+    __device__ __forceinline__ void flush() {
+        if (trace) {
+            static_for<0, (int)EPOCH_ROUNDS>([&](auto jc) {
+                constexpr uint32_t j = decltype(jc)::value;
+                if (j < nb) {
+                    *out = obuf[j * 64];
+                    out += stride;
+                }
+            });
+        }
+        nb = 0;
     }
 };
 
