@@ -220,6 +220,90 @@ brng_status brng_get_info(const brng_ctx *ctx, uint32_t *n_units, uint32_t *wind
  * Errors: BRNG_E_ARG. */
 brng_status brng_set_launch(brng_ctx *ctx, int32_t waves_per_block, int32_t reserved);
 
+/* ---------------------------------------------------------------------- */
+/* Served form: a request loop with continuous batching.  Requests (one    */
+/* brng_gibbs_desc each) arrive at any time; the server admits them while  */
+/* device memory within its budget and a slot are free, keeps their unit   */
+/* tables and pools on the device, and advances every admitted request by  */
+/* a time slice per tick, the requests of one model sharing a launch.  A   */
+/* request's results do not depend on what else runs (its streams are its */
+/* own: units keyed by (request-local unit id, request seed), Sec. 2.2's   */
+/* buffers kept per request), so they equal a plain brng_run_gibbs of the  */
+/* same request.  Suggested by the paper's asynchronous-service outlook    */
+/* (Sec. 3).                                                               */
+/* ---------------------------------------------------------------------- */
+typedef struct brng_server brng_server;
+
+typedef struct {
+    uint64_t hbm_budget;  /* bytes of device memory for admitted requests'
+                             unit tables and pools (counted per request:
+                             its footprint), allocated once at open */
+    uint32_t max_active;  /* requests admitted at once (slots), >= 1 */
+    uint32_t tick_steps;  /* steps per tick for chain models, >= 1 */
+    uint32_t tick_sweeps; /* sweeps per tick for LDA, >= 1 */
+    uint32_t window[4];   /* pool window per unit per kind for every request
+                             (as brng_config.window; kinds a model needs must
+                             be non-zero) */
+    uint32_t pad;
+    void *hip_stream;     /* hipStream_t for all server work, NULL = default */
+} brng_serve_config;
+
+typedef struct {
+    uint64_t ticket;      /* from brng_serve_submit */
+    uint64_t t_arrive_ns; /* arrival time given at submit (brng_serve_now) */
+    uint64_t t_admit_ns;  /* when the server admitted it */
+    uint64_t t_done_ns;   /* when the server saw its last tick complete */
+    int32_t status;       /* BRNG_OK, or the error that ended it */
+    int32_t pad;
+} brng_serve_done;
+
+typedef struct {
+    uint32_t waiting;     /* submitted, not yet admitted */
+    uint32_t active;      /* admitted, not finished */
+    uint32_t ticks_in_flight;
+    uint32_t pad;
+    uint64_t bytes_in_use;   /* footprints of admitted requests */
+    uint64_t bytes_peak;     /* largest bytes_in_use so far (<= hbm_budget) */
+    uint64_t ticks;          /* ticks launched so far */
+    uint64_t completed;      /* requests finished so far */
+} brng_serve_stats;
+
+/* Open a server: allocates the budget and creates its events.
+ * Errors: BRNG_E_ARG, BRNG_E_NOMEM, BRNG_E_HIP; *out is NULL on error. */
+brng_status brng_serve_open(const brng_serve_config *cfg, brng_server **out);
+
+/* Steady-clock time in ns, the clock of the brng_serve_done stamps. */
+uint64_t brng_serve_now(void);
+
+/* Queue one request.  *h_desc is copied; unit_base must be 0 and flags 0
+ * (a served request starts fresh: cursors 0, the model's initial state; for
+ * GAMMA and LDA d_state holds alpha_0 / the initial counts).  Its device
+ * arrays (state, steps, perm, traces, offsets, ntok) are the caller's and
+ * must stay valid until the request is done; the state is updated in place.
+ * t_arrive_ns is its arrival time (0: now).  Requests are admitted in
+ * submission order.  Footprint = unit tables + pools of the kinds the model
+ * uses.  Errors: BRNG_E_ARG (invalid request), BRNG_E_KIND_DISABLED (the
+ * server's windows lack a kind the model needs), BRNG_E_NOMEM (footprint
+ * above the whole budget: it could never be admitted). */
+brng_status brng_serve_submit(brng_server *srv, const brng_gibbs_desc *h_desc,
+                              uint64_t t_arrive_ns, uint64_t *ticket);
+
+/* Do the server's work once: retire finished ticks (their finished requests
+ * become done and free their memory), admit waiting requests that fit, and
+ * launch the next tick when fewer than two are in flight.  wait = 1 blocks
+ * until the oldest tick in flight has finished before retiring.
+ * Errors: BRNG_E_ARG, BRNG_E_HIP. */
+brng_status brng_serve_progress(brng_server *srv, int32_t wait);
+
+/* Move up to `cap` finished requests, oldest first, to h_out; *n gets the
+ * count.  Errors: BRNG_E_ARG. */
+brng_status brng_serve_poll(brng_server *srv, brng_serve_done *h_out, uint32_t cap, uint32_t *n);
+
+brng_status brng_serve_stats_get(const brng_server *srv, brng_serve_stats *h_out);
+
+/* Finish every queued request, then free the server.  NULL is a no-op. */
+brng_status brng_serve_close(brng_server *srv);
+
 /* Human-readable status. Never NULL. */
 const char *brng_status_string(brng_status s);
 /* hipError_t of the last BRNG_E_HIP in this thread (0 if none). */

@@ -31,7 +31,8 @@ EXPORTS = [
     "brng_step_exp", "brng_step_gamma", "brng_step_dirichlet", "brng_run_gibbs",
     "brng_sort_by_length", "brng_get_cursors", "brng_set_cursors", "brng_get_window",
     "brng_get_info", "brng_set_launch", "brng_status_string", "brng_last_hip_error",
-    "brng_convert",
+    "brng_convert", "brng_serve_open", "brng_serve_now", "brng_serve_submit",
+    "brng_serve_progress", "brng_serve_poll", "brng_serve_stats_get", "brng_serve_close",
 ]
 
 
@@ -66,6 +67,42 @@ class brng_gibbs_desc(C.Structure):
     ]
 
 
+class brng_serve_config(C.Structure):
+    _fields_ = [
+        ("hbm_budget", C.c_uint64),
+        ("max_active", C.c_uint32),
+        ("tick_steps", C.c_uint32),
+        ("tick_sweeps", C.c_uint32),
+        ("window", C.c_uint32 * 4),
+        ("pad", C.c_uint32),
+        ("hip_stream", C.c_void_p),
+    ]
+
+
+class brng_serve_done(C.Structure):
+    _fields_ = [
+        ("ticket", C.c_uint64),
+        ("t_arrive_ns", C.c_uint64),
+        ("t_admit_ns", C.c_uint64),
+        ("t_done_ns", C.c_uint64),
+        ("status", C.c_int32),
+        ("pad", C.c_int32),
+    ]
+
+
+class brng_serve_stats(C.Structure):
+    _fields_ = [
+        ("waiting", C.c_uint32),
+        ("active", C.c_uint32),
+        ("ticks_in_flight", C.c_uint32),
+        ("pad", C.c_uint32),
+        ("bytes_in_use", C.c_uint64),
+        ("bytes_peak", C.c_uint64),
+        ("ticks", C.c_uint64),
+        ("completed", C.c_uint64),
+    ]
+
+
 class BrngError(RuntimeError):
     def __init__(self, status: int, where: str):
         msg = _lib.brng_status_string(status).decode() if _lib is not None else str(status)
@@ -77,6 +114,13 @@ class BrngError(RuntimeError):
 
 
 def _load():
+    # PyTorch brings its own HIP runtime (same soname as the system one).  It
+    # is loaded first so that this library binds to it: a process must not
+    # hold two HIP runtimes, or the second finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             "libbrng.so not built (expected at %s); run `python -m paper_1412_4825_amd.build`"
@@ -101,6 +145,16 @@ def _load():
     L.brng_get_info.argtypes = [vp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
     L.brng_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
     L.brng_convert.argtypes = [C.c_int32, vp, C.c_uint64, vp, vp]
+    L.brng_serve_open.argtypes = [C.POINTER(brng_serve_config), C.POINTER(vp)]
+    L.brng_serve_now.argtypes = []
+    L.brng_serve_now.restype = C.c_uint64
+    L.brng_serve_submit.argtypes = [vp, C.POINTER(brng_gibbs_desc), C.c_uint64,
+                                    C.POINTER(C.c_uint64)]
+    L.brng_serve_progress.argtypes = [vp, C.c_int32]
+    L.brng_serve_poll.argtypes = [vp, C.POINTER(brng_serve_done), C.c_uint32,
+                                  C.POINTER(C.c_uint32)]
+    L.brng_serve_stats_get.argtypes = [vp, C.POINTER(brng_serve_stats)]
+    L.brng_serve_close.argtypes = [vp]
     L.brng_status_string.argtypes = [C.c_int32]
     L.brng_status_string.restype = C.c_char_p
     L.brng_last_hip_error.argtypes = []
@@ -272,3 +326,57 @@ def brng_convert(kind: int, words, n_words: int, out, stream=None) -> None:
 
 def brng_status_string(status: int) -> str:
     return _lib.brng_status_string(status).decode()
+
+
+# ---------------------------------------------------------------------------
+# served form
+# ---------------------------------------------------------------------------
+
+def brng_serve_open(hbm_budget: int, window, *, max_active: int = 64, tick_steps: int = 64,
+                    tick_sweeps: int = 2, stream=None) -> int:
+    cfg = brng_serve_config()
+    cfg.hbm_budget = hbm_budget
+    cfg.max_active = max_active
+    cfg.tick_steps = tick_steps
+    cfg.tick_sweeps = tick_sweeps
+    for k in range(4):
+        cfg.window[k] = int(window[k])
+    cfg.hip_stream = _stream_handle(stream)
+    out = C.c_void_p()
+    _check(_lib.brng_serve_open(C.byref(cfg), C.byref(out)), "brng_serve_open")
+    return out.value
+
+
+def brng_serve_now() -> int:
+    return int(_lib.brng_serve_now())
+
+
+def brng_serve_submit(srv: int, desc: brng_gibbs_desc, t_arrive_ns: int = 0) -> int:
+    t = C.c_uint64()
+    _check(_lib.brng_serve_submit(srv, C.byref(desc), t_arrive_ns, C.byref(t)),
+           "brng_serve_submit")
+    return t.value
+
+
+def brng_serve_progress(srv: int, wait: bool = False) -> None:
+    _check(_lib.brng_serve_progress(srv, 1 if wait else 0), "brng_serve_progress")
+
+
+def brng_serve_poll(srv: int, cap: int = 256):
+    """Finished requests as a list of dicts (ticket, t_arrive_ns, t_admit_ns,
+    t_done_ns, status)."""
+    buf = (brng_serve_done * cap)()
+    n = C.c_uint32()
+    _check(_lib.brng_serve_poll(srv, buf, cap, C.byref(n)), "brng_serve_poll")
+    return [{f: getattr(buf[i], f) for f, _ in brng_serve_done._fields_ if f != "pad"}
+            for i in range(n.value)]
+
+
+def brng_serve_stats_get(srv: int) -> dict:
+    o = brng_serve_stats()
+    _check(_lib.brng_serve_stats_get(srv, C.byref(o)), "brng_serve_stats_get")
+    return {f: getattr(o, f) for f, _ in brng_serve_stats._fields_ if f != "pad"}
+
+
+def brng_serve_close(srv: int) -> None:
+    _check(_lib.brng_serve_close(srv), "brng_serve_close")

@@ -15,7 +15,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "brng.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("brng.hip", "serve.hip")]
 LIB = os.path.join(HERE, "libbrng.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -35,7 +35,7 @@ FLAGS = [
 def build(verbose: bool = False) -> str:
     """Compile libbrng.so (always recompiles)."""
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + [SRC, "-o", tmp]
+    cmd = [HIPCC] + FLAGS + SRCS + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -18,6 +18,7 @@
 
 #include "../../include/brng.h"
 #include "models.hpp"
+#include "slots.hpp"
 
 using namespace brng;
 
@@ -242,6 +243,32 @@ __global__ __launch_bounds__(512) void k_gibbs(DescDev D, Meta* meta, Pools P) {
     run_unit<MODEL>(D, meta, P, local, lds_all + w * model_lds_bytes(MODEL));
 }
 
+// Batched and served form: the units of up to MULTI_MAX requests in one
+// launch; a wave finds its request by binary search over the slots' unit
+// prefix (wave-uniform, in the kernel-argument segment).
+template <int MODEL>
+__global__ __launch_bounds__(512) void k_multi(const SlotTable T) {
+    extern __shared__ __align__(16) unsigned char lds_all[];
+    const uint32_t w = wave_in_block();
+    const uint32_t g = blockIdx.x * (blockDim.x >> 6) + w;
+    if (g >= T.total_units) return;
+    uint32_t lo = 0, hi = T.n - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (T.s[mid].unit_end > g)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    const uint32_t first = lo ? T.s[lo - 1].unit_end : 0u;
+    const DescDev D = T.s[lo].D;
+    const Pools P = T.s[lo].P;
+    Meta* meta = T.s[lo].meta;
+    const uint32_t local = g - first;
+    if (MODEL == M_LDA && !lda_doc_ok(D, local)) return;
+    run_unit<MODEL>(D, meta, P, local, lds_all + w * model_lds_bytes(MODEL));
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -319,6 +346,66 @@ static void free_ctx(brng_ctx* c) {
     if (c->meta) (void)hipFree(c->meta);
     delete c;
 }
+
+namespace brng {
+
+int model_lds_bytes_host(int model) { return model_lds_bytes(model); }
+
+uint32_t desc_unit_count(const brng_gibbs_desc& d) {
+    return d.model == BRNG_MODEL_LDA ? d.n_chains : (d.n_chains + 63) / 64;
+}
+
+DescDev desc_to_device(const brng_gibbs_desc& d) {
+    DescDev D;
+    D.model = d.model;
+    D.n_chains = d.n_chains;
+    D.unit_base = d.unit_base;
+    D.flags = d.flags;
+    D.seed = d.seed;
+    D.max_steps = d.max_steps;
+    D.n_units = desc_unit_count(d);
+    D.steps = d.d_steps;
+    D.perm = d.d_perm;
+    D.state = d.d_state;
+    D.trace = d.d_trace;
+    D.trace2 = d.d_trace2;
+    D.stride = d.trace_stride;
+    D.offsets = d.d_offsets;
+    D.ntok = d.d_ntok;
+    D.step0 = 0;
+    D.max_rounds = 0;
+    D.progress = nullptr;
+    D.unit_done = nullptr;
+    return D;
+}
+
+brng_status launch_slots(int model, const SlotTable& T, hipStream_t stream, int wpb) {
+    if (T.n == 0 || T.total_units == 0) return BRNG_OK;
+    while (wpb > 1 && (size_t)wpb * model_lds_bytes(model) > 65536) wpb >>= 1;
+    const dim3 grid((T.total_units + wpb - 1) / wpb), block(64 * wpb);
+    const size_t lds = (size_t)wpb * model_lds_bytes(model);
+    switch (model) {
+        case M_TRIANGLE:
+            hipLaunchKernelGGL(k_multi<M_TRIANGLE>, grid, block, lds, stream, T);
+            break;
+        case M_NORMEXP:
+            hipLaunchKernelGGL(k_multi<M_NORMEXP>, grid, block, lds, stream, T);
+            break;
+        case M_GAMMA:
+            hipLaunchKernelGGL(k_multi<M_GAMMA>, grid, block, lds, stream, T);
+            break;
+        case M_LDA:
+            hipLaunchKernelGGL(k_multi<M_LDA>, grid, block, lds, stream, T);
+            break;
+        default:
+            hipLaunchKernelGGL(k_multi<M_EXPCHAIN>, grid, block, lds, stream, T);
+            break;
+    }
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
+}  // namespace brng
 
 extern "C" {
 
@@ -472,14 +559,11 @@ brng_status brng_step_dirichlet(brng_ctx* c, const int32_t* offsets, const float
     return BRNG_OK;
 }
 
-static uint32_t desc_units(const brng_gibbs_desc& d) {
-    return d.model == BRNG_MODEL_LDA ? d.n_chains : (d.n_chains + 63) / 64;
-}
 
 static brng_status check_desc(const brng_ctx* c, const brng_gibbs_desc& d) {
     if (d.model < 0 || d.model >= BRNG_NMODELS) return BRNG_E_ARG;
     if (d.n_chains == 0 || d.max_steps < 0 || !d.d_state) return BRNG_E_ARG;
-    const uint64_t nu = desc_units(d);
+    const uint64_t nu = desc_unit_count(d);
     if ((uint64_t)d.unit_base + nu > c->n_units) return BRNG_E_ARG;
     const int64_t width = d.model == BRNG_MODEL_LDA ? 0 : (int64_t)d.n_chains;
     if ((d.d_trace || d.d_trace2) && d.trace_stride < width) return BRNG_E_ARG;
@@ -503,25 +587,6 @@ static brng_status check_desc(const brng_ctx* c, const brng_gibbs_desc& d) {
     return BRNG_OK;
 }
 
-static DescDev to_dev(const brng_gibbs_desc& d) {
-    DescDev D;
-    D.model = d.model;
-    D.n_chains = d.n_chains;
-    D.unit_base = d.unit_base;
-    D.flags = d.flags;
-    D.seed = d.seed;
-    D.max_steps = d.max_steps;
-    D.n_units = desc_units(d);
-    D.steps = d.d_steps;
-    D.perm = d.d_perm;
-    D.state = d.d_state;
-    D.trace = d.d_trace;
-    D.trace2 = d.d_trace2;
-    D.stride = d.trace_stride;
-    D.offsets = d.d_offsets;
-    D.ntok = d.d_ntok;
-    return D;
-}
 
 // Waves per block for a model: the configured count, halved while a block's
 // LDS would exceed 64 KiB.
@@ -557,6 +622,37 @@ static brng_status launch_plain(brng_ctx* c, const DescDev& D) {
     return BRNG_OK;
 }
 
+
+// Batched form: requests grouped by model, MULTI_MAX per launch, in the
+// order given within each model.
+static brng_status launch_batched(brng_ctx* c, const brng_gibbs_desc* descs, uint32_t n_desc) {
+    const Pools P = make_pools(c);
+    for (int model = 0; model < BRNG_NMODELS; ++model) {
+        SlotTable T;
+        T.n = 0;
+        T.total_units = 0;
+        for (uint32_t i = 0; i <= n_desc; ++i) {
+            const bool flush = (i == n_desc) || T.n == (uint32_t)MULTI_MAX;
+            if (flush && T.n) {
+                brng_status s = launch_slots(model, T, c->stream, c->wpb);
+                if (s != BRNG_OK) return s;
+                T.n = 0;
+                T.total_units = 0;
+            }
+            if (i == n_desc) break;
+            if (descs[i].model != model) continue;
+            SlotDev& S = T.s[T.n++];
+            S.D = desc_to_device(descs[i]);
+            S.meta = c->meta;
+            S.P = P;
+            T.total_units += S.D.n_units;
+            S.unit_end = T.total_units;
+            S.pad = 0;
+        }
+    }
+    return BRNG_OK;
+}
+
 brng_status brng_run_gibbs(brng_ctx* c, const brng_gibbs_desc* descs, uint32_t n_desc) {
     if (!c || !descs || n_desc == 0) return BRNG_E_ARG;
     for (uint32_t i = 0; i < n_desc; ++i) {
@@ -566,17 +662,13 @@ brng_status brng_run_gibbs(brng_ctx* c, const brng_gibbs_desc* descs, uint32_t n
     // requests must not share units
     std::vector<std::pair<uint32_t, uint32_t>> ranges(n_desc);
     for (uint32_t i = 0; i < n_desc; ++i)
-        ranges[i] = {descs[i].unit_base, descs[i].unit_base + desc_units(descs[i])};
+        ranges[i] = {descs[i].unit_base, descs[i].unit_base + desc_unit_count(descs[i])};
     std::sort(ranges.begin(), ranges.end());
     for (uint32_t i = 1; i < n_desc; ++i)
         if (ranges[i].first < ranges[i - 1].second) return BRNG_E_ARG;
-    // several requests: each runs its own chain kernel, back to back on the
-    // context's stream (requests are independent: their units are disjoint)
-    for (uint32_t i = 0; i < n_desc; ++i) {
-        brng_status s = launch_plain(c, to_dev(descs[i]));
-        if (s != BRNG_OK) return s;
-    }
-    return BRNG_OK;
+    if (n_desc == 1) return launch_plain(c, desc_to_device(descs[0]));
+    // several requests (independent: their units are disjoint) share launches
+    return launch_batched(c, descs, n_desc);
 }
 
 brng_status brng_sort_by_length(uint32_t n, const int32_t* steps, int32_t* perm) {

@@ -29,6 +29,14 @@ struct DescDev {
     int64_t stride;
     const int32_t* offsets;
     const int32_t* ntok;
+    int32_t step0;  // steps already taken (time-sliced runs): per-chain
+                    // lengths count from here; traces start at row 0
+    // Round-sliced gamma chains (the served form): steps done per slot,
+    // rounds to run (0: until every chain is done) and, per unit, 1 once all
+    // its chains are done (host-visible memory); null/0 in plain runs.
+    int32_t max_rounds;
+    int32_t* progress;
+    uint8_t* unit_done;
 };
 
 enum : int32_t { M_TRIANGLE = 0, M_NORMEXP = 1, M_GAMMA = 2, M_LDA = 3, M_EXPCHAIN = 4 };
@@ -87,7 +95,7 @@ __device__ void unit_triangle(const DescDev& D, Meta* mp, const Pools& P, uint32
     const bool in0 = slot < D.n_chains;
     const uint32_t chain = in0 ? (D.perm ? (uint32_t)D.perm[slot] : slot) : 0;
     const bool in = in0 && chain < D.n_chains;  // a bad permutation entry idles the lane
-    const int32_t L = in ? (D.steps ? D.steps[chain] : D.max_steps) : 0;
+    const int32_t L = in ? (D.steps ? D.steps[chain] - D.step0 : D.max_steps) : 0;
     const Meta m = open_meta(D, mp, local);
     const uint32_t gu = D.unit_base + local;
     StagedReader<KIND_U64> ru;
@@ -156,7 +164,7 @@ __device__ void unit_normexp(const DescDev& D, Meta* mp, const Pools& P, uint32_
     const bool in0 = slot < D.n_chains;
     const uint32_t chain = in0 ? (D.perm ? (uint32_t)D.perm[slot] : slot) : 0;
     const bool in = in0 && chain < D.n_chains;  // a bad permutation entry idles the lane
-    const int32_t L = in ? (D.steps ? D.steps[chain] : D.max_steps) : 0;
+    const int32_t L = in ? (D.steps ? D.steps[chain] - D.step0 : D.max_steps) : 0;
     const bool fresh = !(D.flags & FLAG_RESUME);
     Meta m = open_meta(D, mp, local);
     const uint32_t gu = D.unit_base + local;
@@ -303,7 +311,7 @@ __device__ void unit_expchain(const DescDev& D, Meta* mp, const Pools& P, uint32
     const bool in0 = slot < D.n_chains;
     const uint32_t chain = in0 ? (D.perm ? (uint32_t)D.perm[slot] : slot) : 0;
     const bool in = in0 && chain < D.n_chains;
-    const int32_t L = in ? (D.steps ? D.steps[chain] : D.max_steps) : 0;
+    const int32_t L = in ? (D.steps ? D.steps[chain] - D.step0 : D.max_steps) : 0;
     const bool fresh = !(D.flags & FLAG_RESUME);
     Meta m = open_meta(D, mp, local);
     const uint32_t gu = D.unit_base + local;
@@ -423,7 +431,7 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
     const bool in0 = slot < D.n_chains;
     const uint32_t chain = in0 ? (D.perm ? (uint32_t)D.perm[slot] : slot) : 0;
     const bool in = in0 && chain < D.n_chains;
-    const int32_t L = in ? min(D.steps ? D.steps[chain] : D.max_steps, D.max_steps) : 0;
+    const int32_t L = in ? min(D.steps ? D.steps[chain] - D.step0 : D.max_steps, D.max_steps) : 0;
     const Meta m = open_meta(D, mp, local);
     const uint32_t gu = D.unit_base + local;
     GammaRN rn;
@@ -433,16 +441,24 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
             reinterpret_cast<float*>(lds + GammaRN::LDS_BYTES));
     float* st = reinterpret_cast<float*>(D.state);
     ChainSrc src;
-    src.t = 0;
+    // steps already done by this slot (round-sliced runs continue a chain
+    // mid-way; the round sequence is the same as in one straight run)
+    const int32_t t0 = (D.progress && in) ? D.progress[slot] : 0;
+    src.t = t0;
     src.L = L;
     src.alpha = in ? st[chain] : 1.0f;
     src.trace = D.trace != nullptr;
-    src.out = src.trace ? reinterpret_cast<float*>(D.trace) + slot : nullptr;
+    src.out = src.trace ? reinterpret_cast<float*>(D.trace) + (int64_t)t0 * D.stride + slot : nullptr;
     src.stride = D.stride;
     src.obuf = reinterpret_cast<float*>(lds + GammaRN::LDS_BYTES + GammaRE::LDS_BYTES) + lane;
     const uint32_t smax = (uint32_t)min(D.max_steps, 1 << 24);
-    gamma_rounds(rn, re, src, 4096u + 64u * smax);
+    gamma_rounds(rn, re, src, D.max_rounds > 0 ? (uint32_t)D.max_rounds : 4096u + 64u * smax);
     if (in) st[chain] = src.alpha;
+    if (D.progress && in) D.progress[slot] = src.t;
+    if (D.unit_done) {
+        const bool all = wave_ballot(src.holding()) == 0;
+        if (lane == 0) D.unit_done[local] = all ? 1 : 0;
+    }
     rn.close(*mp);
     re.close(*mp);
     store_key(mp, m);

@@ -31,8 +31,10 @@ def test_every_declared_function_is_exported():
 
 def test_struct_layouts_match_header(tmp_path):
     """ctypes layouts equal what a C compiler makes of include/brng.h."""
-    fields = {"brng_config": [f[0] for f in b.brng_config._fields_],
-              "brng_gibbs_desc": [f[0] for f in b.brng_gibbs_desc._fields_]}
+    classes = {"brng_config": b.brng_config, "brng_gibbs_desc": b.brng_gibbs_desc,
+               "brng_serve_config": b.brng_serve_config, "brng_serve_done": b.brng_serve_done,
+               "brng_serve_stats": b.brng_serve_stats}
+    fields = {k: [f[0] for f in c._fields_] for k, c in classes.items()}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "brng.h"', "int main(void){"]
     for st, fs in fields.items():
         lines.append('printf("%%zu\\n", sizeof(%s));' % st)
@@ -45,7 +47,7 @@ def test_struct_layouts_match_header(tmp_path):
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     want = []
-    for st, cls in (("brng_config", b.brng_config), ("brng_gibbs_desc", b.brng_gibbs_desc)):
+    for st, cls in classes.items():
         want.append(ctypes.sizeof(cls))
         want += [getattr(cls, f).offset for f in fields[st]]
     assert got == want
@@ -78,3 +80,22 @@ def test_sort_by_length_matches_contract():
     rng = np.random.default_rng(0)
     steps = rng.integers(1, 30, size=5000).astype(np.int32)
     assert np.array_equal(b.brng_sort_by_length(steps), oracle.sort_by_length(steps))
+
+
+def test_serve_arguments_checked_without_device():
+    for kw in (dict(hbm_budget=0), dict(max_active=0), dict(tick_steps=0), dict(tick_sweeps=0)):
+        args = dict(hbm_budget=1 << 20, max_active=4, tick_steps=8, tick_sweeps=1)
+        args.update(kw)
+        budget = args.pop("hbm_budget")
+        with pytest.raises(b.BrngError) as e:
+            b.brng_serve_open(budget, [0, 4096, 4096, 0], **args)
+        assert e.value.status == b.BRNG_E_ARG
+    with pytest.raises(b.BrngError) as e:
+        b.brng_serve_open(1 << 20, [0, 100, 4096, 0])
+    assert e.value.status == b.BRNG_E_ARG
+    for fn, args in ((b._lib.brng_serve_progress, (None, 0)),
+                     (b._lib.brng_serve_stats_get, (None, None))):
+        assert fn(*args) == b.BRNG_E_ARG
+    assert b._lib.brng_serve_close(None) == b.BRNG_OK
+    t0 = b.brng_serve_now()
+    assert b.brng_serve_now() >= t0 > 0

@@ -1,0 +1,221 @@
+"""Served form on the GPU: each request's results are the same alone (a plain
+brng_run_gibbs) and in a served mix; admission never exceeds the budget; the
+time stamps are ordered.  Also the batched form with more requests of one
+model than one launch takes.
+
+Every test prints its case before the GPU calls."""
+import numpy as np
+import pytest
+
+from paper_1412_4825_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+W_SERVE = [512, 512, 512, 512]      # small windows: many in-kernel refills
+W_PLAIN = [4096, 4096, 4096, 4096]  # results do not depend on the window
+
+
+def _b():
+    from paper_1412_4825_amd import binding
+    return binding
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _requests(dev):
+    """A mix of every model with traces, uneven lengths and several sizes.
+    Returns (descs, arrays-to-check) per request; the arrays are the state and
+    traces the request writes."""
+    import torch
+    b = _b()
+    reqs = []
+
+    def add(desc, arrays, keep):
+        reqs.append((desc, arrays, keep))
+
+    # triangle, fp64, with both traces
+    n, s = 100, 300
+    st = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+    tx = torch.zeros((s, n), dtype=torch.float64, device=dev)
+    ty = torch.zeros((s, n), dtype=torch.float64, device=dev)
+    add(b.gibbs_desc(b.BRNG_MODEL_TRIANGLE_F64, n, st, max_steps=s, seed=11, trace=tx, trace2=ty,
+                     trace_stride=n), [st, tx, ty], None)
+    # normal/exponential chain with both traces
+    n, s = 200, 150
+    st = torch.zeros(n, dtype=torch.float32, device=dev)
+    ts = torch.zeros((s, n), dtype=torch.float32, device=dev)
+    te = torch.zeros((s, n), dtype=torch.float32, device=dev)
+    add(b.gibbs_desc(b.BRNG_MODEL_NORMEXP, n, st, max_steps=s, seed=12, trace=ts, trace2=te,
+                     trace_stride=n), [st, ts, te], None)
+    # gamma chains of uneven lengths, slot order sorted by length
+    w = workloads.gamma_chain(n_chains=130, lmin=5, lmax=90, seed=3)
+    perm = b.brng_sort_by_length(w["steps"])
+    s = int(w["steps"].max())
+    st = _t(w["alpha0"], dev)
+    tg = torch.full((s, 130), float("nan"), dtype=torch.float32, device=dev)
+    keep = (_t(w["steps"], dev), _t(perm, dev), st.clone())
+    add(b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, 130, st, max_steps=s, seed=13, trace=tg,
+                     trace_stride=130, steps=keep[0], perm=keep[1]), [st, tg], keep)
+    # exponential chain
+    n, s = 70, 257
+    st = torch.zeros(n, dtype=torch.float32, device=dev)
+    tr = torch.zeros((s, n), dtype=torch.float32, device=dev)
+    add(b.gibbs_desc(b.BRNG_MODEL_EXP_CHAIN, n, st, max_steps=s, seed=14, trace=tr,
+                     trace_stride=n), [st, tr], None)
+    # LDA documents of every K
+    wl = workloads.lda(n_docs=20, sweeps=7, seed=6)
+    tot = int(wl["offsets"][-1])
+    cnt = torch.zeros(tot, dtype=torch.int32, device=dev)
+    th = torch.zeros((7, tot), dtype=torch.float32, device=dev)
+    ct = torch.zeros((7, tot), dtype=torch.int32, device=dev)
+    keep = (_t(wl["offsets"], dev), _t(wl["ntok"], dev))
+    add(b.gibbs_desc(b.BRNG_MODEL_LDA, 20, cnt, max_steps=7, seed=15, trace=th, trace2=ct,
+                     trace_stride=tot, offsets=keep[0], ntok=keep[1]), [cnt, th, ct], keep)
+    # a second, larger gamma request (several units)
+    w2 = workloads.gamma_chain(n_chains=700, lmin=30, lmax=60, seed=8)
+    st2 = _t(w2["alpha0"], dev)
+    keep2 = (_t(w2["steps"], dev), st2.clone())
+    add(b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, 700, st2, max_steps=60, seed=16,
+                     steps=keep2[0]), [st2], keep2)
+    return reqs
+
+
+def _alone(dev, desc, arrays, keep):
+    """Run one request by itself with the plain call; return copies of its
+    arrays."""
+    import torch
+    b = _b()
+    layout = 1 if desc.model == b.BRNG_MODEL_LDA else 0
+    ctx = b.brng_create(desc.seed, desc.n_chains, W_PLAIN, layout=layout,
+                        stream=torch.cuda.current_stream())
+    try:
+        b.brng_run_gibbs(ctx, desc)
+        return [_np(a).copy() for a in arrays]
+    finally:
+        b.brng_destroy(ctx)
+
+
+def test_served_equals_alone(dev):
+    import torch
+    b = _b()
+    _say("serve alone-vs-mix: 6 requests, 5 models")
+    alone = []
+    for desc, arrays, keep in _requests(dev):
+        alone.append(_alone(dev, desc, arrays, keep))
+    mix = _requests(dev)
+    budget = 3 * 1024 * 1024  # room for a few requests at a time
+    srv = b.brng_serve_open(budget, W_SERVE, max_active=3, tick_steps=16, tick_sweeps=2,
+                            stream=torch.cuda.current_stream())
+    try:
+        tickets = [b.brng_serve_submit(srv, d) for d, _, _ in mix]
+        done = []
+        while len(done) < len(mix):
+            b.brng_serve_progress(srv, wait=True)
+            st = b.brng_serve_stats_get(srv)
+            assert st["bytes_in_use"] <= budget and st["active"] <= 3
+            done += b.brng_serve_poll(srv)
+        st = b.brng_serve_stats_get(srv)
+        print("serve stats", st, flush=True)
+        assert st["bytes_peak"] <= budget and st["ticks"] > 10
+        assert sorted(d["ticket"] for d in done) == sorted(tickets)
+        for d in done:
+            assert d["status"] == 0
+            assert d["t_arrive_ns"] <= d["t_admit_ns"] <= d["t_done_ns"]
+    finally:
+        b.brng_serve_close(srv)
+    for i, ((desc, arrays, _), ref) in enumerate(zip(mix, alone)):
+        for j, (a, r) in enumerate(zip(arrays, ref)):
+            got = _np(a)
+            assert np.array_equal(got.view(np.uint8), r.view(np.uint8)), (i, desc.model, j)
+
+
+def test_serve_rejects_and_admits_by_footprint(dev):
+    import torch
+    b = _b()
+    _say("serve admission")
+    srv = b.brng_serve_open(1 << 20, W_SERVE, max_active=8, tick_steps=8, tick_sweeps=1,
+                            stream=torch.cuda.current_stream())
+    try:
+        # 200 units x 2 kinds x 512 floats = 800 KiB of pools: fits alone
+        n = 200 * 64
+        sts = [torch.ones(n, dtype=torch.float32, device=dev) for _ in range(3)]
+        ds = [b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, n, sts[i], max_steps=20, seed=100 + i)
+              for i in range(3)]
+        big = torch.ones(400 * 64, dtype=torch.float32, device=dev)
+        with pytest.raises(b.BrngError) as e:
+            b.brng_serve_submit(srv, b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, 400 * 64, big,
+                                                  max_steps=5, seed=1))
+        assert e.value.status == b.BRNG_E_NOMEM
+        with pytest.raises(b.BrngError) as e:
+            b.brng_serve_submit(srv, b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, 64, big,
+                                                  max_steps=5, seed=1, flags=1))
+        assert e.value.status == b.BRNG_E_ARG
+        for d in ds:
+            b.brng_serve_submit(srv, d)
+        seen_active = []
+        done = []
+        while len(done) < 3:
+            b.brng_serve_progress(srv, wait=True)
+            st = b.brng_serve_stats_get(srv)
+            seen_active.append(st["active"])
+            assert st["bytes_in_use"] <= (1 << 20)
+            done += b.brng_serve_poll(srv)
+        # one request's footprint is more than half the budget: one at a time
+        assert max(seen_active) <= 1
+        assert [d["ticket"] for d in done] == [1, 2, 3]
+    finally:
+        b.brng_serve_close(srv)
+
+
+def test_batched_many_requests_equal_alone(dev):
+    """More requests of one model than one launch holds (16): every request
+    equals its plain run."""
+    import torch
+    b = _b()
+    _say("batched: 21 gamma requests in one call")
+    n_req, per = 21, 90
+    ws = [workloads.gamma_chain(n_chains=per + 7 * i, lmin=3, lmax=40, seed=50 + i)
+          for i in range(n_req)]
+    refs = []
+    for i, w in enumerate(ws):
+        st = _t(w["alpha0"], dev)
+        tg = torch.full((40, w["n_chains"]), float("nan"), dtype=torch.float32, device=dev)
+        d = b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, w["n_chains"], st, max_steps=40,
+                         seed=500 + i, trace=tg, trace_stride=w["n_chains"],
+                         steps=_t(w["steps"], dev))
+        refs.append(_alone(dev, d, [st, tg], None))
+    units = [(w["n_chains"] + 63) // 64 for w in ws]
+    ctx = b.brng_create(9, 64 * (sum(units) + n_req), [0, 512, 512, 0],
+                        stream=torch.cuda.current_stream())
+    try:
+        descs, outs, base = [], [], 0
+        keep = []
+        for i, w in enumerate(ws):
+            st = _t(w["alpha0"], dev)
+            tg = torch.full((40, w["n_chains"]), float("nan"), dtype=torch.float32, device=dev)
+            stp = _t(w["steps"], dev)
+            keep.append(stp)
+            descs.append(b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, w["n_chains"], st, max_steps=40,
+                                      seed=500 + i, trace=tg, trace_stride=w["n_chains"],
+                                      steps=stp, unit_base=base))
+            outs.append((st, tg))
+            base += units[i] + 1
+        b.brng_run_gibbs(ctx, descs)
+        for i, ((st, tg), ref) in enumerate(zip(outs, refs)):
+            assert np.array_equal(_np(st), ref[0]), i
+            assert np.array_equal(_np(tg), ref[1], equal_nan=True), i
+    finally:
+        b.brng_destroy(ctx)
