@@ -13,11 +13,14 @@ of every step.  Chains continue from step to step.
 Other workloads (--workload): triangle (Eq. 1 / Fig. 1, 1,024 chains x 10,000
 iterations, fp64), gamma (262,144 chains of uneven length 50..1,000 with
 alpha_{t+1} = 0.1 + g_t), lda (16,384 documents, Dirichlet + multinomial,
-100 sweeps).
+100 sweeps), served (the mixed request stream alone).
 
 Prints one JSON line: deviates/s, the roofline of the dominant kernel
-(algorithmic bytes over its event-timed duration against 8 TB/s), and the
-CPU oracle timed on the host over the workload or a stated sample of it.
+(algorithmic bytes over its event-timed duration against 8 TB/s), the CPU
+oracle timed on the host over the workload or a stated sample of it, and
+(unless --no-served) the served form against per-request plain launches on
+a mixed request stream: throughput with every request queued, and p50/p99
+latency under Poisson arrivals at 70% of the plain capacity.
 """
 from __future__ import annotations
 
@@ -34,6 +37,36 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def kernel_sources_sha() -> str:
+    """Digest of the HIP sources and the C header (names and contents)."""
+    import glob
+    import hashlib
+    h = hashlib.sha1()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1412_4825_amd", "csrc", "*")))
+    for f in files + [os.path.join(ROOT, "include", "brng.h")]:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(label: str):
+    """HBM bytes per launch of kernel `label` (FETCH_SIZE + WRITE_SIZE, scaled
+    by a known-size copy) from the committed rocprof summaries under
+    profiles/, or None when the kernel sources have changed since."""
+    import glob
+    sha = kernel_sources_sha()
+    for p in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(p) as fh:
+            for line in fh:
+                f = line.split()
+                if len(f) == 5 and f[0] == "traffic" and f[1] == label:
+                    kv = dict(x.split("=", 1) for x in f[2:])
+                    if kv.get("sources") == sha:
+                        return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
+    return None
 
 
 class Events:
@@ -282,6 +315,84 @@ def setup_lda(torch, b, args):
                         "generator": "Philox4x32-10"})
 
 
+def served_section(torch, args, n_req):
+    """The served form against per-request plain launches on the same mixed
+    request stream: capacity (all requests queued at once) and latency
+    (Poisson arrivals at 70% of the plain capacity, measured on a
+    500-request prefix)."""
+    from paper_1412_4825_amd import serve, workloads
+    dev = torch.device("cuda:0")
+    qs = workloads.served_requests(n_req, chains_max=args.served_chains_max,
+                                   steps_max=args.served_steps_max, seed=args.seed)
+    reqs = [serve.Request(torch, q, dev) for q in qs]
+    W = [4096] * 4
+    deviates = sum(r.deviates for r in reqs)
+    for r in reqs:
+        r.reset()
+    service = serve.run_plain(torch, reqs, W)
+    k = min(500, n_req)
+    mu_p = k / service[:k].sum()
+    rate = 0.7 * mu_p
+    arrivals = workloads.poisson_arrivals(n_req, rate, seed=args.seed)
+    lat_plain = serve.fifo_latency(arrivals, service)
+    kw = dict(budget=args.served_budget_mb << 20, window=W, max_active=args.served_slots,
+              tick_steps=args.served_tick_steps, tick_sweeps=args.served_tick_sweeps)
+    for r in reqs:
+        r.reset()
+    _, makespan, st_sat = serve.run_served(torch, reqs, np.zeros(n_req), **kw)
+    for r in reqs:
+        r.reset()
+    lat_srv, span_srv, st = serve.run_served(torch, reqs, arrivals, **kw)
+
+    def pct(x):
+        return {"p50_ms": round(float(np.percentile(x, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(x, 99)) * 1e3, 3)}
+
+    kinds = {kd: sum(1 for q in qs if q["kind"] == kd) for kd in workloads.SERVED_KINDS}
+    return {
+        "requests": n_req, "kinds": kinds, "deviates": deviates,
+        "served": dict(capacity_deviates_per_s=deviates / makespan,
+                       makespan_s=round(makespan, 4), ticks=st_sat["ticks"],
+                       peak_bytes=st_sat["bytes_peak"], **pct(lat_srv)),
+        "plain": dict(capacity_deviates_per_s=deviates / service.sum(),
+                      busy_s=round(float(service.sum()), 4), **pct(lat_plain)),
+        "arrival_rate_per_s": round(rate, 2), "load": "0.7 x plain capacity (first %d requests)" % k,
+        "chains": "log-U[1, %d]" % args.served_chains_max,
+        "steps": "log-U[10, %d]" % args.served_steps_max,
+        "server": dict(budget_mb=args.served_budget_mb, slots=args.served_slots,
+                       tick_steps=args.served_tick_steps, tick_sweeps=args.served_tick_sweeps,
+                       window=W[0]),
+    }
+
+
+def served_main(torch, args):
+    t0 = time.perf_counter()
+    sec = served_section(torch, args, args.served_requests)
+    out = {
+        "metric": "served p50/p99 latency vs plain; deviates/s",
+        "value": sec["served"]["capacity_deviates_per_s"],
+        "unit": "deviates/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": sec["served"]["makespan_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "served mixed request stream (uniform/normal/exponential/gamma/"
+                               "Dirichlet chains), continuous batching vs per-request plain "
+                               "launches", "requests": sec["requests"], "chains": sec["chains"],
+                   "steps": sec["steps"]},
+        "roofline": None,
+        "cpu_baseline": None,
+        "served": sec,
+        "wall_s": round(time.perf_counter() - t0, 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 WORKLOADS = {"normexp": setup_normexp, "triangle": setup_triangle, "gamma": setup_gamma,
              "lda": setup_lda}
 
@@ -291,7 +402,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="normexp", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="normexp", choices=sorted(WORKLOADS) + ["served"])
     ap.add_argument("--chains", type=int, default=0)
     ap.add_argument("--chain-steps", type=int, default=0)
     ap.add_argument("--window", type=int, default=0)
@@ -301,6 +412,18 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--cpu-units", type=int, default=0)
     ap.add_argument("--oaat-steps", type=int, default=100)
+    ap.add_argument("--served-requests", type=int, default=2000)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one conversion of 2^26 words (256 MiB read, 256 MiB "
+                         "written): the known-size kernel that scales rocprof's "
+                         "FETCH_SIZE/WRITE_SIZE to bytes")
+    ap.add_argument("--served-chains-max", type=int, default=4096)
+    ap.add_argument("--served-steps-max", type=int, default=1000)
+    ap.add_argument("--served-budget-mb", type=int, default=4096)
+    ap.add_argument("--served-slots", type=int, default=64)
+    ap.add_argument("--served-tick-steps", type=int, default=256)
+    ap.add_argument("--served-tick-sweeps", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this library has no multi-GPU path "
@@ -315,6 +438,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "served":
+        served_main(torch, args)
+        return
     Wk = WORKLOADS[args.workload](torch, b, args)
     ctx = Wk["ctx"]
     b.brng_set_launch(ctx, args.wpb)
@@ -362,7 +488,8 @@ def main():
     chain_ms = float(np.mean(ev.ms("chains")))
     gbs = chain_b / (chain_ms / 1e3) / 1e9
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": Wk["kernel"],
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(Wk["kernel"]),
+            "kernel": Wk["kernel"],
             "kernel_ms": round(chain_ms, 4), "alg_bytes_per_launch": chain_b}
     out = {
         "metric": "varying-param deviates/s + % HBM roofline",
@@ -390,6 +517,17 @@ def main():
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = Wk["cpu"](workers)
     b.brng_destroy(ctx)
+    if args.copy_calibration:
+        nw = 1 << 26
+        words = torch.randint(-2**31, 2**31 - 1, (nw,), dtype=torch.int32, device="cuda")
+        conv = torch.empty(nw, dtype=torch.float32, device="cuda")
+        b.brng_convert(b.BRNG_U, words, nw, conv, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        del words, conv
+    if not args.no_served:
+        # the metric's second half: served latency and throughput against
+        # per-request plain launches on a mixed request stream
+        out["served"] = served_section(torch, args, args.served_requests)
     print(json.dumps(out), flush=True)
 
 

@@ -72,3 +72,49 @@ def dirichlet_items(n_items: int, kmin: int = 1, kmax: int = 300, seed: int = WO
     offsets[1:] = np.cumsum(K)
     alpha = np.exp(r.uniform(np.log(0.05), np.log(50.0), int(offsets[-1]))).astype(np.float32)
     return dict(offsets=offsets, alpha=alpha, K=K)
+
+
+SERVED_KINDS = ("uniform", "normal", "exponential", "gamma", "dirichlet")
+
+
+def _log_uniform_int(r: np.random.Generator, lo: int, hi: int, n: int) -> np.ndarray:
+    """round(exp(U ln lo + (1 - U) ln hi)), clamped to [lo, hi]."""
+    u = r.random(n)
+    v = np.rint(np.exp(u * np.log(lo) + (1.0 - u) * np.log(hi)))
+    return np.clip(v, lo, hi).astype(np.int64)
+
+
+def served_requests(n_requests: int, chains_max: int = 65536, steps_max: int = 10000,
+                    seed: int = WORKLOAD_SEED):
+    """A mixed request stream for the served form: per request a kind drawn
+    uniformly from SERVED_KINDS, chains log-uniform in [1, chains_max], steps
+    log-uniform in [10, steps_max], and a stream seed.  Per kind the chain
+    model: uniform -> the triangle chain (fp64), normal -> the s-chain with
+    its exponential, exponential -> e' ~ Exp(1 + e^2), gamma -> gamma chains
+    with alpha_0 log-uniform on [0.1, 100], dirichlet -> LDA documents (the
+    chains are documents, the steps sweeps) with K ~ U{8..256} and
+    n ~ Poisson(200) tokens.  Arrival times are not drawn here."""
+    r = _rng(seed, 9)
+    kind = r.integers(0, len(SERVED_KINDS), n_requests)
+    chains = _log_uniform_int(r, 1, chains_max, n_requests)
+    steps = _log_uniform_int(r, 10, steps_max, n_requests)
+    seeds = r.integers(0, 2**63, n_requests, dtype=np.int64).astype(np.uint64)
+    out = []
+    for i in range(n_requests):
+        q = dict(kind=SERVED_KINDS[kind[i]], chains=int(chains[i]), steps=int(steps[i]),
+                 seed=int(seeds[i]))
+        if q["kind"] == "gamma":
+            q["alpha0"] = (0.1 * np.power(1000.0, r.random(q["chains"]))).astype(np.float32)
+        elif q["kind"] == "dirichlet":
+            K = r.integers(8, 257, q["chains"]).astype(np.int32)
+            q["ntok"] = r.poisson(200.0, q["chains"]).astype(np.int32)
+            q["offsets"] = np.zeros(q["chains"] + 1, dtype=np.int32)
+            q["offsets"][1:] = np.cumsum(K)
+        out.append(q)
+    return out
+
+
+def poisson_arrivals(n: int, rate_per_s: float, seed: int = WORKLOAD_SEED) -> np.ndarray:
+    """Arrival offsets in seconds of a Poisson process at the given rate."""
+    r = _rng(seed, 10)
+    return np.cumsum(r.exponential(1.0 / rate_per_s, n))
