@@ -315,6 +315,50 @@ def setup_lda(torch, b, args):
                         "generator": "Philox4x32-10"})
 
 
+def autotune_launch(torch, b, args):
+    """Pick the pool window and waves per workgroup for the gamma/LDA
+    workloads by timing one step (bulk refills + the resumed chain launch)
+    per candidate (results do not depend on either)."""
+    import copy
+
+    from paper_1412_4825_amd import autotune
+    setup = WORKLOADS[args.workload]
+
+    def trial_factory():
+        cache = {}
+
+        def trial(window, wpb):
+            if window not in cache:
+                for old in cache.values():
+                    b.brng_destroy(old["ctx"])
+                cache.clear()
+                a2 = copy.copy(args)
+                a2.window = window
+                Wk = setup(torch, b, a2)
+                b.brng_run_gibbs(Wk["ctx"], Wk["fresh"])
+                cache[window] = Wk
+            Wk = cache[window]
+            b.brng_set_launch(Wk["ctx"], wpb)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()  # one whole step: the bulk refills and the chain launch
+            for k in Wk["kinds"]:
+                b.brng_fill_base(Wk["ctx"], k)
+            b.brng_run_gibbs(Wk["ctx"], Wk["resume"])
+            e1.record()
+            e1.synchronize()
+            return e0.elapsed_time(e1) / 1e3
+
+        return trial, cache
+
+    trial, cache = trial_factory()
+    best = autotune.pick(trial, windows=(2048, 4096, 16384), wpbs=(2, 4, 8), reps=2)
+    for Wk in cache.values():
+        b.brng_destroy(Wk["ctx"])
+    torch.cuda.synchronize()
+    return best
+
+
 def served_section(torch, args, n_req):
     """The served form against per-request plain launches on the same mixed
     request stream: capacity (all requests queued at once) and latency
@@ -412,8 +456,12 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--cpu-units", type=int, default=0)
     ap.add_argument("--oaat-steps", type=int, default=100)
+    ap.add_argument("--no-oaat", action="store_true",
+                    help="skip the one-launch-per-step comparison (gamma)")
     ap.add_argument("--served-requests", type=int, default=2000)
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="gamma/lda: use --window/--wpb as given instead of timing candidates")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one conversion of 2^26 words (256 MiB read, 256 MiB "
                          "written): the known-size kernel that scales rocprof's "
@@ -441,6 +489,10 @@ def main():
     if args.workload == "served":
         served_main(torch, args)
         return
+    tuned = None
+    if args.workload in ("gamma", "lda") and not args.no_autotune and not args.window:
+        tuned = autotune_launch(torch, b, args)
+        args.window, args.wpb = tuned["window"], tuned["wpb"]
     Wk = WORKLOADS[args.workload](torch, b, args)
     ctx = Wk["ctx"]
     b.brng_set_launch(ctx, args.wpb)
@@ -511,7 +563,11 @@ def main():
         "entries_per_step": {int(k): float(delta[:, k].sum()) for k in Wk["kinds"]},
         "wall_s": wall,
     }
-    if "oaat" in Wk:
+    if tuned is not None:
+        out["autotune"] = {"window": tuned["window"], "wpb": tuned["wpb"],
+                           "candidates_ms": {"%d/%d" % (t["window"], t["wpb"]): round(t["seconds"] * 1e3, 4)
+                                             for t in tuned["table"]}}
+    if "oaat" in Wk and not args.no_oaat:
         out["one_launch_per_step"] = Wk["oaat"](ev)
     if not args.no_cpu:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)

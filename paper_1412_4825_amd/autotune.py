@@ -1,0 +1,60 @@
+"""Autotuner for the chain kernels' launch shape and pool window.
+
+Results never depend on either (the stream contract makes window length and
+waves per workgroup speed knobs only; tests check this bit for bit), so the
+tuner just times candidates on the caller's workload and keeps the fastest.
+The paper notes that buffer length is a performance parameter (Sec. 2.4);
+here it is chosen per workload by measurement.  Choices can be cached in a
+JSON file keyed by a workload name.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Callable, Iterable
+
+WPB_CANDIDATES = (1, 2, 4, 8)
+WINDOW_CANDIDATES = (1024, 4096, 16384)
+
+
+def pick(trial: Callable[[int, int], float], windows: Iterable[int] = WINDOW_CANDIDATES,
+         wpbs: Iterable[int] = WPB_CANDIDATES, reps: int = 3) -> dict:
+    """Time trial(window, wpb) -> seconds for every candidate (best of
+    `reps`) and return {"window", "wpb", "seconds", "table"}.  Ties keep the
+    earlier candidate."""
+    table = []
+    best = None
+    for w in windows:
+        for k in wpbs:
+            t = min(trial(w, k) for _ in range(reps))
+            table.append({"window": w, "wpb": k, "seconds": t})
+            if best is None or t < best["seconds"]:
+                best = {"window": w, "wpb": k, "seconds": t}
+    best = dict(best)
+    best["table"] = table
+    return best
+
+
+def load(path: str, key: str):
+    """The cached choice for `key`, or None."""
+    try:
+        with open(path) as f:
+            return json.load(f).get(key)
+    except (OSError, ValueError):
+        return None
+
+
+def store(path: str, key: str, choice: dict) -> None:
+    data = {}
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        data = {}
+    data[key] = {k: v for k, v in choice.items() if k != "table"}
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)

@@ -160,7 +160,7 @@ __global__ __launch_bounds__(512) void k_step_gamma(Meta* meta, Pools P, uint32_
     src.want = act ? 1 : 0;
     src.alpha = act ? alpha[c] : 1.0f;
     src.g = 0.0f;
-    gamma_rounds(rn, re, src, 4096u);
+    gamma_rounds<false>(rn, re, src, 4096u);
     if (act) out[c] = src.g;
     rn.close(meta[unit]);
     re.close(meta[unit]);
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(512) void k_step_dirichlet(Meta* meta, Pools P, uin
     src.alpha = alpha + off;
     src.cnt = nullptr;
     src.y = out + off;
-    gamma_rounds(rn, re, src, 4096u + 64u * (uint32_t)min(K, 1 << 24));
+    gamma_rounds<false>(rn, re, src, 4096u + 64u * (uint32_t)min(K, 1 << 24));
     // component gammas were written by whichever lane drew them
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     float part = 0.0f;

@@ -423,6 +423,10 @@ using GammaRN = EpochReader<KIND_N, 1>;
 using GammaRE = EpochReader<KIND_E, 2>;
 constexpr int GAMMA_OBUF_BYTES = (int)EPOCH_ROUNDS * 64 * 4;
 constexpr int GAMMA_LDS_BYTES = GammaRN::LDS_BYTES + GammaRE::LDS_BYTES + GAMMA_OBUF_BYTES;
+// An epoch's worst case fits the rings (a round takes at most one Gaussian
+// and two exponentials per lane), so the rounds run without staging checks.
+static_assert(GammaRN::CH >= 64 * EPOCH_ROUNDS && GammaRE::CH >= 128 * EPOCH_ROUNDS,
+              "gamma rings must cover an epoch");
 
 __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t local,
                            unsigned char* lds) {
@@ -452,7 +456,7 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
     src.stride = D.stride;
     src.obuf = reinterpret_cast<float*>(lds + GammaRN::LDS_BYTES + GammaRE::LDS_BYTES) + lane;
     const uint32_t smax = (uint32_t)min(D.max_steps, 1 << 24);
-    gamma_rounds(rn, re, src, D.max_rounds > 0 ? (uint32_t)D.max_rounds : 4096u + 64u * smax);
+    gamma_rounds<true>(rn, re, src, D.max_rounds > 0 ? (uint32_t)D.max_rounds : 4096u + 64u * smax);
     if (in) st[chain] = src.alpha;
     if (D.progress && in) D.progress[slot] = src.t;
     if (D.unit_done) {
@@ -515,7 +519,7 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
         src.alpha = nullptr;
         src.cnt = cnt;
         src.y = yv;
-        gamma_rounds(rn, re, src, 4096u + 64u * (uint32_t)K);
+        gamma_rounds<false>(rn, re, src, 4096u + 64u * (uint32_t)K);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

@@ -51,7 +51,7 @@ __device__ __forceinline__ bool gamma_shape_ok(float alpha) {
 
 // Per-lane constants of the draw a lane holds.
 struct GammaLane {
-    float alpha, a, d, c, dq;
+    float alpha, a, d, c;
     bool valid, boost;
     __device__ __forceinline__ void setup(float al) {
         alpha = al;
@@ -60,22 +60,8 @@ struct GammaLane {
         a = valid ? (boost ? al + 1.0f : al) : 1.0f;
         d = a - (1.0f / 3.0f);
         c = __builtin_amdgcn_rsqf(9.0f * d);  // 1 / sqrt(9 d)
-        dq = d * 0.750015f;                   // (3/4) d, times the squeeze margin 1.00002
     }
 };
-
-// The accept decision E + d q(y) > 0 for a lane with 1 + c x = v0 > 0.
-// q(y) <= 0 and, from q'(y) = -3y^3/(1+y), -q(y) <= (3/4) y^4 for y >= 0 and
-// -q(y) <= (3/4) y^4 / (1+y) for -1 < y < 0; so E above that bound (with a
-// margin far above its fp32 error) accepts with no logarithm.  Otherwise the
-// statistic is evaluated in fp32 and, when it is within its fp32 error bound
-// of zero, again in fp64.  dq = (3/4) d times the margin.
-__device__ __forceinline__ bool mt_certain(float dq, float y, float v0, float e) {
-    const float y2 = y * y;
-    const float b = dq * (y2 * y2);
-    const float bn = b * __builtin_amdgcn_rcpf(v0);
-    return e > (y < 0.0f ? bn : b);
-}
 
 // ln(1 + y) for y > -1: the logarithm of the rounded sum u = 1 + y plus the
 // first-order correction for the rounding (y - (u - 1)) / u.
@@ -85,18 +71,21 @@ __device__ __forceinline__ float log1p_fast(float y) {
     return fmaf(__builtin_amdgcn_logf(u), 0.693147180559945309f, corr);
 }
 
-__device__ __forceinline__ bool mt_decide(float a, float d, float x, float y, float v0, float e) {
+// The accept statistic E + d q(y) in fp32 for a lane with 1 + c x = v0 > 0:
+// *acc is its sign, *unsure whether it lies within its fp32 error bound of
+// zero (term magnitudes times a few ulp, plus the effect of y's own
+// rounding), in which case the decision is taken again in fp64.
+__device__ __forceinline__ void mt_test(float d, float y, float v0, float e, bool* acc,
+                                        bool* unsure) {
     const float l = log1p_fast(y);
     const float y2 = y * y;
     const float y3 = y2 * y;
     const float q = (3.0f * l - 3.0f * y) + (1.5f * y2 - y3);
     const float stat = e + d * q;
-    // bound on the fp32 evaluation error (terms' magnitudes times a few ulp,
-    // plus the effect of y's own rounding)
     const float mag = e + d * (3.0f * fabsf(l) + 3.0f * fabsf(y) + 1.5f * y2 + fabsf(y3) +
                                3.0f * y2 * y2 * __builtin_amdgcn_rcpf(v0));
-    if (fabsf(stat) > 2e-6f * mag) return stat > 0.0f;
-    return mt_accept64(a, x, e);
+    *acc = stat > 0.0f;
+    *unsure = !(fabsf(stat) > 2e-6f * mag);
 }
 
 // Gamma draws in rounds over the 64 lanes of a wave.  Each lane holds at most
@@ -122,7 +111,9 @@ __device__ __forceinline__ bool mt_decide(float a, float d, float x, float y, fl
 //   void flush()                  epoch point (global stores go here)
 constexpr uint32_t EPOCH_ROUNDS = 4;
 
-template <class RN, class RE, class Src>
+// COVERED: the readers' rings hold an epoch's worst case (64 Gaussians and
+// 128 exponentials per round), so no call inside the rounds needs to stage.
+template <bool COVERED, class RN, class RE, class Src>
 __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t max_rounds) {
     float al = src.first();
     // Let every load issued so far land here, once: otherwise the first use
@@ -145,8 +136,10 @@ __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t 
         // exponential call is redone with its own ranks when it is not so.
         const uint64_t mp = wave_ballot(pend);
         const uint32_t np = (uint32_t)__popcll(mp);
-        rn.reserve(np);
-        re.reserve(np);
+        if (!COVERED) {
+            rn.reserve(np);
+            re.reserve(np);
+        }
         const uint32_t rk = mask_rank(mp);
         const float xr = rn.peek(rk);
         float e = re.peek(rk);
@@ -159,22 +152,30 @@ __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t 
         if (me == mp) {
             re.advance(np);
         } else {
-            const uint32_t ne = (uint32_t)__popcll(me);
             e = re.peek(mask_rank(me));
-            re.advance(ne);
+            re.advance((uint32_t)__popcll(me));
         }
-        const bool sure = mt_certain(L.dq, y, v0, e);
-        bool acc = need_e && sure;
-        if (wave_ballot(need_e && !sure) != 0) {
-            const bool r = mt_decide(L.a, L.d, x, y, v0, e);
-            acc = need_e && (sure || r);
+        // One lane in twenty-odd needs the logarithm in a round, so the wave
+        // nearly always does: every lane evaluates the test, and only lanes
+        // whose fp32 statistic is within its error bound of zero (rare)
+        // decide again in fp64.
+        bool acc, unsure;
+        mt_test(L.d, y, v0, e, &acc, &unsure);
+        acc = need_e && acc;
+        unsure = need_e && unsure;
+        if (wave_ballot(unsure) != 0) {
+            if (unsure) acc = mt_accept64(L.a, x, e);
         }
         float g = L.d * (v0 * v0 * v0);
         const bool b = acc && L.boost;
         // boost: g exp(-E'/alpha) = 2^(log2 g - E' log2(e) / alpha), one
         // exponential whose result underflows only when the product does
-        if (wave_ballot(b) != 0) {
-            const float e2 = re.take(b);
+        const uint64_t mb = wave_ballot(b);
+        if (mb != 0) {
+            const uint32_t nb = (uint32_t)__popcll(mb);
+            if (!COVERED) re.reserve(nb);
+            const float e2 = re.peek(mask_rank(mb));
+            re.advance(nb);
             const float gb = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(g) -
                                                     e2 * (1.44269504088896341f * __builtin_amdgcn_rcpf(al)));
             g = b ? gb : g;

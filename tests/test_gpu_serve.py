@@ -219,3 +219,81 @@ def test_batched_many_requests_equal_alone(dev):
             assert np.array_equal(_np(tg), ref[1], equal_nan=True), i
     finally:
         b.brng_destroy(ctx)
+
+
+def test_launch_shape_invariance_and_graph_replay(dev):
+    """Waves per workgroup change nothing; the batched form captured in a
+    graph (bulk refills + one multi-request launch) replays to the same bits
+    as the same calls made eagerly, with eager work between replays."""
+    import torch
+    b = _b()
+    _say("launch shape 1/2/4/8 and graph replay")
+    w = workloads.gamma_chain(n_chains=300, lmin=10, lmax=40, seed=21)
+    outs = []
+    for wpb in (1, 2, 4, 8):
+        ctx = b.brng_create(5, 300, [0, 512, 512, 0], stream=torch.cuda.current_stream())
+        try:
+            b.brng_set_launch(ctx, wpb)
+            st = _t(w["alpha0"], dev)
+            tg = torch.full((40, 300), float("nan"), dtype=torch.float32, device=dev)
+            b.brng_run_gibbs(ctx, b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, 300, st, max_steps=40,
+                                               seed=5, trace=tg, trace_stride=300,
+                                               steps=_t(w["steps"], dev)))
+            outs.append((_np(st), _np(tg)))
+        finally:
+            b.brng_destroy(ctx)
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1], equal_nan=True)
+
+    # graph: two requests (gamma + normal/exponential) resumed per replay
+    n1, n2, steps = 300, 200, 16
+
+    def make(stream):
+        ctx = b.brng_create(6, n1 + n2 + 64, [0, 1024, 1024, 0], stream=stream)
+        st1 = _t(w["alpha0"], dev)
+        st2 = torch.zeros(n2, dtype=torch.float32, device=dev)
+        t1 = torch.zeros((steps, n1), dtype=torch.float32, device=dev)
+        t2 = torch.zeros((steps, n2), dtype=torch.float32, device=dev)
+        base2 = (n1 + 63) // 64
+
+        def descs(flags):
+            return [b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, n1, st1, max_steps=steps, seed=61,
+                                 trace=t1, trace_stride=n1, flags=flags),
+                    b.gibbs_desc(b.BRNG_MODEL_NORMEXP, n2, st2, max_steps=steps, seed=62,
+                                 trace=t2, trace_stride=n2, unit_base=base2, flags=flags)]
+        return ctx, (st1, st2, t1, t2), descs
+
+    ref = []
+    ctx, arrs, descs = make(torch.cuda.current_stream())
+    try:
+        b.brng_run_gibbs(ctx, descs(0))
+        for _ in range(3):
+            b.brng_fill_base(ctx, b.BRNG_N)
+            b.brng_fill_base(ctx, b.BRNG_E)
+            b.brng_run_gibbs(ctx, descs(b.BRNG_FLAG_RESUME))
+            ref.append([_np(a).copy() for a in arrs])
+    finally:
+        b.brng_destroy(ctx)
+    s = torch.cuda.Stream()
+    ctx, arrs, descs = make(s)
+    try:
+        with torch.cuda.stream(s):
+            b.brng_run_gibbs(ctx, descs(0))
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        rd = descs(b.BRNG_FLAG_RESUME)
+        with torch.cuda.graph(g, stream=s):
+            b.brng_fill_base(ctx, b.BRNG_N)
+            b.brng_fill_base(ctx, b.BRNG_E)
+            b.brng_run_gibbs(ctx, rd)
+        junk = torch.zeros(1 << 20, device=dev)
+        for i in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            got = [_np(a) for a in arrs]
+            for a, r in zip(got, ref[i]):
+                assert np.array_equal(a, r), i
+            junk.add_(1.0)  # eager work between replays
+            torch.cuda.synchronize()
+    finally:
+        b.brng_destroy(ctx)
