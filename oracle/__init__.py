@@ -77,6 +77,10 @@ def _declare(L):
     L.or_step_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, _u64p, _dp, _dp, _dp, _dp]
     L.or_step_normal.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _dp, _dp, _dp]
     L.or_step_exp.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _dp, _dp]
+    L.or_step_laplace.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _dp,
+                                  _dp, _dp]
+    L.or_step_weibull.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _dp,
+                                  _dp, _dp]
     L.or_step_gamma.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _dp, _dp, _dp, _i32p, _i32p]
     L.or_step_dirichlet.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _u64p, _i32p, _dp, _dp, _dp, _dp]
     L.or_multinomial.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _u64p, _i32p, _i32p, _dp, _i32p]
@@ -173,6 +177,26 @@ def step_exp(seed, cursors, lam, width=UNIT_WIDTH, unit0=0):
     n = lam.size
     out, t = np.zeros(n), np.zeros(n)
     lib().or_step_exp(seed, unit0, n, width, _p(cursors, _u64p), _p(lam, _dp), _p(out, _dp), _p(t, _dp))
+    return out, t
+
+
+def step_laplace(seed, cursors, mu, b, width=UNIT_WIDTH, unit0=0):
+    """Laplace(mu, b) = mu + b (E1 - E2), one E call then another per unit."""
+    mu, b = _d(mu), _d(b)
+    n = mu.size
+    out, t = np.zeros(n), np.zeros(n)
+    lib().or_step_laplace(seed, unit0, n, width, _p(cursors, _u64p), _p(mu, _dp), _p(b, _dp),
+                          _p(out, _dp), _p(t, _dp))
+    return out, t
+
+
+def step_weibull(seed, cursors, lam, k, width=UNIT_WIDTH, unit0=0):
+    """Weibull(lambda, k) = lambda E^(1/k)."""
+    lam, k = _d(lam), _d(k)
+    n = lam.size
+    out, t = np.zeros(n), np.zeros(n)
+    lib().or_step_weibull(seed, unit0, n, width, _p(cursors, _u64p), _p(lam, _dp), _p(k, _dp),
+                          _p(out, _dp), _p(t, _dp))
     return out, t
 
 

@@ -297,6 +297,55 @@ void or_step_exp(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, uint
     }
 }
 
+/* Laplace(mu, b) (GetLaplace, Sec. 2.2, built on the reducible functions):  */
+/* mu + b (E1 - E2); the difference of two independent Exp(1) deviates is   */
+/* standard Laplace.  Two calls on the exponential pool: E1 for every chain  */
+/* of the unit, then E2 for every chain.                                    */
+void or_step_laplace(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, uint64_t *cursors,
+                     const double *mu, const double *b, double *out, double *tol)
+{
+    uint32_t nu = (n + width - 1) / width;
+    if (width > 256) { /* units wider than the scratch row: not supported */
+        for (uint32_t c = 0; c < n; c++) out[c] = NAN;
+        return;
+    }
+    for (uint32_t u = 0; u < nu; u++) {
+        stream_t s = {seed, unit0 + u, cursors + 4 * (size_t)u};
+        uint32_t lo, hi;
+        unit_range(n, width, u, &lo, &hi);
+        double e1[256];
+        for (uint32_t c = lo; c < hi; c++)
+            e1[c - lo] = take(&s, OR_E);
+        for (uint32_t c = lo; c < hi; c++) {
+            double e2 = take(&s, OR_E);
+            double p = b[c] * e1[c - lo], q = b[c] * e2;
+            out[c] = mu[c] + (p - q);
+            if (tol)
+                tol[c] = or_tol(dmax(dmax(fabs(out[c]), fabs(mu[c])), dmax(fabs(p), fabs(q))));
+        }
+    }
+}
+
+/* Weibull(lambda, k) (GetWeibull, Sec. 2.2): lambda E^(1/k), one call on   */
+/* the exponential pool.  The relative error of E and of the power grows    */
+/* by (1 + |ln E|)/k, which the tolerance carries.                          */
+void or_step_weibull(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, uint64_t *cursors,
+                     const double *lambda, const double *k, double *out, double *tol)
+{
+    uint32_t nu = (n + width - 1) / width;
+    for (uint32_t u = 0; u < nu; u++) {
+        stream_t s = {seed, unit0 + u, cursors + 4 * (size_t)u};
+        uint32_t lo, hi;
+        unit_range(n, width, u, &lo, &hi);
+        for (uint32_t c = lo; c < hi; c++) {
+            double e = take(&s, OR_E);
+            out[c] = lambda[c] * pow(e, 1.0 / k[c]);
+            if (tol)
+                tol[c] = or_tol(fabs(out[c]) * (1.0 + (1.0 + fabs(log(e))) / k[c]));
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Gamma(alpha, 1): Marsaglia & Tsang (2000).                               */
 /*                                                                          */

@@ -54,6 +54,52 @@ def test_exponential_varying(params):
     assert stats.kstest(-np.expm1(-lam * out), "uniform").pvalue > 1e-3
 
 
+def test_laplace_varying(params):
+    """Laplace(mu, b) (GetLaplace, Sec. 2.2) with per-draw parameters: the
+    PIT through the closed-form CDF is uniform."""
+    mu = params["mu"].astype(np.float64)
+    b = params["sigma"].astype(np.float64)
+    out, _ = oracle.step_laplace(6, _cur(N), mu, b)
+    assert stats.kstest(stats.laplace.cdf(out, loc=mu, scale=b), "uniform").pvalue > 1e-3
+
+
+def test_laplace_takes_two_exponential_calls():
+    """Two calls on the exponential pool, whole unit each: chain c's value is
+    mu + b (E[c] - E[64 + c]) for a full unit; the partial unit likewise."""
+    n = 100
+    cur = _cur(n)
+    out, _ = oracle.step_laplace(8, cur, np.zeros(n), np.ones(n))
+    assert list(cur[:, 2]) == [128, 72]
+    e0 = oracle.entries(8, 0, 2, 0, 128)
+    e1 = oracle.entries(8, 1, 2, 0, 72)
+    assert np.allclose(out[:64], e0[:64] - e0[64:], rtol=0, atol=1e-15)
+    assert np.allclose(out[64:], e1[:36] - e1[36:], rtol=0, atol=1e-15)
+    # symmetric about mu: as many draws on each side (binomial bounds)
+    big, _ = oracle.step_laplace(9, _cur(N), np.full(N, 3.0), np.full(N, 2.0))
+    k = int((big > 3.0).sum())
+    assert abs(k - N / 2) < 5 * math.sqrt(N / 4)
+
+
+def test_weibull_varying():
+    """Weibull(lambda, k) (GetWeibull, Sec. 2.2) with per-draw scale and
+    shape: the PIT through the closed-form CDF is uniform; the mean at a
+    fixed shape is lambda Gamma(1 + 1/k)."""
+    r = np.random.default_rng(11)
+    lam = np.exp(r.uniform(np.log(0.01), np.log(100.0), N))
+    k = np.exp(r.uniform(np.log(0.2), np.log(20.0), N))
+    out, _ = oracle.step_weibull(6, _cur(N), lam, k)
+    assert stats.kstest(stats.weibull_min.cdf(out, k, scale=lam), "uniform").pvalue > 1e-3
+    out, _ = oracle.step_weibull(7, _cur(N), np.full(N, 2.0), np.full(N, 1.5))
+    m, sd = 2.0 * special.gamma(1 + 1 / 1.5), 2.0 * math.sqrt(
+        special.gamma(1 + 2 / 1.5) - special.gamma(1 + 1 / 1.5) ** 2)
+    assert abs(out.mean() - m) < 5 * sd / math.sqrt(N)
+    # shape 1 is the exponential of the same entries
+    c1, c2 = _cur(N), _cur(N)
+    w, _ = oracle.step_weibull(4, c1, np.full(N, 3.0), np.ones(N))
+    e, _ = oracle.step_exp(4, c2, np.full(N, 1.0 / 3.0))
+    assert np.allclose(w, e, rtol=1e-14, atol=0)
+
+
 def test_calls_advance_cursors_in_slot_order():
     """Two calls over 100 chains: chain c of unit u takes entry (call * width
     + c - 64u) of its unit, for full units; the partial unit takes
