@@ -114,6 +114,15 @@ brng_status brng_step_normal(brng_ctx *ctx, const void *d_mu, const void *d_sigm
 brng_status brng_step_exp(brng_ctx *ctx, const void *d_lambda, void *d_out);
 brng_status brng_step_gamma(brng_ctx *ctx, const float *d_alpha, float *d_out);
 
+/* The paper's other irreducible samplers (Sec. 2.2: GetLaplace, GetWeibull),
+ * one draw per chain from the exponential pool, F32 only:
+ *   laplace: out = mu + b (E1 - E2)    (two calls: E1 for every chain of a
+ *                                       unit, then E2; b is the scale)
+ *   weibull: out = lambda E^(1/k)      (scale lambda, shape k > 0)
+ * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_UNSUPPORTED, BRNG_E_HIP. */
+brng_status brng_step_laplace(brng_ctx *ctx, const float *d_mu, const float *d_b, float *d_out);
+brng_status brng_step_weibull(brng_ctx *ctx, const float *d_lambda, const float *d_k, float *d_out);
+
 /* Dirichlet by normalised gammas (Sec. 1, footnote on Dirichlet): layout
  * ITEMS, item i has components [d_offsets[i], d_offsets[i+1]) of d_alpha and
  * d_out (F32).  Components are drawn in batches of 64, one gamma call per

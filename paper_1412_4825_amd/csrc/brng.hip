@@ -146,6 +146,42 @@ __global__ __launch_bounds__(512) void k_step_exp(Meta* meta, float* pool, uint3
     r.close(meta[unit]);
 }
 
+// Laplace (GetLaplace, Sec. 2.2): mu + b (E1 - E2), two calls on the
+// exponential pool.
+__global__ __launch_bounds__(512) void k_step_laplace(Meta* meta, float* pool, uint32_t W,
+                                                      uint32_t n, const float* mu, const float* b,
+                                                      float* out) {
+    const uint32_t unit = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (unit * 64 >= n) return;
+    const uint32_t c = unit * 64 + lane_id();
+    const bool act = c < n;
+    DirectReader<KIND_E> r;
+    r.open(meta[unit], pool + (size_t)unit * W, W);
+    const float e1 = r.take(act);
+    const float e2 = r.take(act);
+    if (act) {
+        const float s = b[c];
+        out[c] = mu[c] + (s * e1 - s * e2);
+    }
+    r.close(meta[unit]);
+}
+
+// Weibull (GetWeibull, Sec. 2.2): lambda E^(1/k) = lambda 2^(log2(E) / k),
+// one call on the exponential pool.
+__global__ __launch_bounds__(512) void k_step_weibull(Meta* meta, float* pool, uint32_t W,
+                                                      uint32_t n, const float* lam, const float* k,
+                                                      float* out) {
+    const uint32_t unit = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (unit * 64 >= n) return;
+    const uint32_t c = unit * 64 + lane_id();
+    const bool act = c < n;
+    DirectReader<KIND_E> r;
+    r.open(meta[unit], pool + (size_t)unit * W, W);
+    const float e = r.take(act);
+    if (act) out[c] = lam[c] * __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(e) / k[c]);
+    r.close(meta[unit]);
+}
+
 __global__ __launch_bounds__(512) void k_step_gamma(Meta* meta, Pools P, uint32_t n,
                                                     const float* alpha, float* out) {
     const uint32_t unit = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
@@ -532,6 +568,30 @@ brng_status brng_step_exp(brng_ctx* c, const void* lam, void* out) {
     hipLaunchKernelGGL(k_step_exp, unit_grid(c, c->n_units), dim3(64 * c->wpb), 0, c->stream,
                        c->meta, (float*)c->pool[BRNG_E], c->cfg.window[BRNG_E], c->cfg.n_chains,
                        (const float*)lam, (float*)out);
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
+brng_status brng_step_laplace(brng_ctx* c, const float* mu, const float* b, float* out) {
+    if (!c || !mu || !b || !out) return BRNG_E_ARG;
+    if (c->cfg.layout != BRNG_LAYOUT_CHAINS) return BRNG_E_ARG;
+    if (c->cfg.prec != BRNG_F32) return BRNG_E_UNSUPPORTED;
+    if (!c->cfg.window[BRNG_E]) return BRNG_E_KIND_DISABLED;
+    hipLaunchKernelGGL(k_step_laplace, unit_grid(c, c->n_units), dim3(64 * c->wpb), 0, c->stream,
+                       c->meta, (float*)c->pool[BRNG_E], c->cfg.window[BRNG_E], c->cfg.n_chains,
+                       mu, b, out);
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
+brng_status brng_step_weibull(brng_ctx* c, const float* lam, const float* k, float* out) {
+    if (!c || !lam || !k || !out) return BRNG_E_ARG;
+    if (c->cfg.layout != BRNG_LAYOUT_CHAINS) return BRNG_E_ARG;
+    if (c->cfg.prec != BRNG_F32) return BRNG_E_UNSUPPORTED;
+    if (!c->cfg.window[BRNG_E]) return BRNG_E_KIND_DISABLED;
+    hipLaunchKernelGGL(k_step_weibull, unit_grid(c, c->n_units), dim3(64 * c->wpb), 0, c->stream,
+                       c->meta, (float*)c->pool[BRNG_E], c->cfg.window[BRNG_E], c->cfg.n_chains,
+                       lam, k, out);
     HIPCHK(hipGetLastError());
     return BRNG_OK;
 }

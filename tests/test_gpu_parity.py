@@ -83,8 +83,9 @@ def test_fill_base_windows(dev, seed, kind):
 
 
 def test_steps_reducible_and_gamma(dev):
-    """Five calls of each one-at-a-time function with per-chain parameters;
-    small windows force refills inside the kernels."""
+    """Five calls of each one-at-a-time function (uniform, normal,
+    exponential, Laplace, Weibull) with per-chain parameters, then gamma;
+    small windows force refills inside the kernels; cursors bit-exact."""
     b = _b()
     n, seed = 1000, 99
     p = workloads.step_params(n, seed=5)
@@ -96,6 +97,8 @@ def test_steps_reducible_and_gamma(dev):
         ta, tb = _t(p["a"], dev), _t(p["b"], dev)
         tmu, tsg, tl = _t(p["mu"], dev), _t(p["sigma"], dev), _t(p["lam"], dev)
         tal = _t(p["alpha"], dev)
+        wk = np.exp(np.random.default_rng(3).uniform(np.log(0.2), np.log(20.0), n)).astype(np.float32)
+        tk = _t(wk, dev)
         units = np.arange(n) // 64
         flips = set()
         for it in range(5):
@@ -108,6 +111,13 @@ def test_steps_reducible_and_gamma(dev):
             b.brng_step_exp(ctx, tl, out)
             r, tol = oracle.step_exp(seed, cur, p["lam"])
             assert within(_np(out), r, tol).all()
+            b.brng_step_laplace(ctx, tmu, tsg, out)
+            r, tol = oracle.step_laplace(seed, cur, p["mu"], p["sigma"])
+            assert within(_np(out), r, tol).all()
+            b.brng_step_weibull(ctx, tl, tk, out)
+            r, tol = oracle.step_weibull(seed, cur, p["lam"], wk)
+            assert within(_np(out), r, tol).all()
+        assert np.array_equal(b.brng_get_cursors(ctx), cur)
         gcur = cur.copy()
         b.brng_step_gamma(ctx, tal, out)
         g, tol, margin, nN, nE = oracle.step_gamma(seed, gcur, p["alpha"])
