@@ -315,6 +315,49 @@ def setup_lda(torch, b, args):
                         "generator": "Philox4x32-10"})
 
 
+def per_distribution(torch, b, args, n=1 << 20, calls=20):
+    """The paper's results table on one MI355X, per distribution (Sec. 2.4):
+    the bulk fill of a pool (its Batch column) and one-at-a-time calls with a
+    different parameter per chain and per call (its BatchRNG column; each
+    call is one launch over n chains), in deviates/s."""
+    from paper_1412_4825_amd import workloads
+    dev = torch.device("cuda:0")
+    W = 4096
+    p = workloads.step_params(n, seed=args.seed)
+    t = {k: torch.from_numpy(v).to(dev) for k, v in p.items()}
+    shape = torch.from_numpy(np.exp(np.random.default_rng(1).uniform(
+        np.log(0.2), np.log(20.0), n)).astype(np.float32)).to(dev)
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    ctx = b.brng_create(args.seed, n, [W, W, W, 0], stream=torch.cuda.current_stream())
+    res = {}
+    try:
+        def timed(fn, count):
+            fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(calls):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return count * calls / (e0.elapsed_time(e1) / 1e3)
+
+        units = (n + 63) // 64
+        for name, kind in (("uniform", b.BRNG_U), ("normal", b.BRNG_N), ("exponential", b.BRNG_E)):
+            res[name] = {"batch_fill": timed(lambda: b.brng_fill_base(ctx, kind), units * W)}
+        res["uniform"]["one_at_a_time"] = timed(lambda: b.brng_step_uniform(ctx, t["a"], t["b"], out), n)
+        res["normal"]["one_at_a_time"] = timed(lambda: b.brng_step_normal(ctx, t["mu"], t["sigma"], out), n)
+        res["exponential"]["one_at_a_time"] = timed(lambda: b.brng_step_exp(ctx, t["lam"], out), n)
+        res["laplace"] = {"one_at_a_time": timed(lambda: b.brng_step_laplace(ctx, t["mu"], t["sigma"], out), n)}
+        res["weibull"] = {"one_at_a_time": timed(lambda: b.brng_step_weibull(ctx, t["lam"], shape, out), n)}
+        res["gamma"] = {"one_at_a_time": timed(lambda: b.brng_step_gamma(ctx, t["alpha"], out), n)}
+    finally:
+        b.brng_destroy(ctx)
+    return {"chains": n, "calls": calls, "window": W, "unit": "deviates/s",
+            "rates": {k: {c: float("%.4g" % v) for c, v in d.items()} for k, d in res.items()}}
+
+
 def autotune_launch(torch, b, args):
     """Pick the pool window and waves per workgroup for the gamma/LDA
     workloads by timing one step (bulk refills + the resumed chain launch)
@@ -460,6 +503,8 @@ def main():
                     help="skip the one-launch-per-step comparison (gamma)")
     ap.add_argument("--served-requests", type=int, default=2000)
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-dist", action="store_true",
+                    help="skip the per-distribution rates (fill and one-at-a-time calls)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="gamma/lda: use --window/--wpb as given instead of timing candidates")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -580,6 +625,8 @@ def main():
         b.brng_convert(b.BRNG_U, words, nw, conv, torch.cuda.current_stream())
         torch.cuda.synchronize()
         del words, conv
+    if not args.no_dist:
+        out["per_distribution"] = per_distribution(torch, b, args)
     if not args.no_served:
         # the metric's second half: served latency and throughput against
         # per-request plain launches on a mixed request stream
