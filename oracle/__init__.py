@@ -87,7 +87,8 @@ def _declare(L):
     L.or_triangle.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _dp, _dp, _u64p, _dp, _dp, _dp, _dp]
     L.or_normexp.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, _dp, _u64p, _dp, _dp, _dp, _dp]
     L.or_expchain.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, _dp, _u64p, _dp, _dp]
-    L.or_gamma_chain.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _i32p, _i32p, _dp, _u64p, _dp, _dp, _dp]
+    L.or_gamma_chain.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _i32p, _i32p, _dp, _u64p, _dp, _dp, _dp,
+                                 _i32p, _i32p]
     L.or_lda.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _i32p, _i32p, C.c_uint32, _i32p, _u64p, _dp, _dp, _i32p, _dp, _dp]
 
 
@@ -297,7 +298,9 @@ def sort_by_length(steps) -> np.ndarray:
 
 
 def gamma_chain(seed, alpha0, steps, perm=None, cursors=None, width=UNIT_WIDTH, unit0=0):
-    """alpha_{t+1} = 0.1 + g_t, g_t ~ Gamma(alpha_t, 1); traces are [t][slot]."""
+    """alpha_{t+1} = 0.1 + g_t, g_t ~ Gamma(alpha_t, 1); traces are [t][slot].
+    gr0/gr1 are the rounds (per unit, from this call's first) in which each
+    draw started and completed, -1 where a chain has no step t."""
     alpha = _d(alpha0).copy()
     steps = np.ascontiguousarray(steps, dtype=np.int32)
     n = alpha.size
@@ -308,9 +311,12 @@ def gamma_chain(seed, alpha0, steps, perm=None, cursors=None, width=UNIT_WIDTH, 
     cur = new_cursors(nu) if cursors is None else cursors
     smax = int(steps.max()) if n else 0
     gtr, gtol, gmar = (np.full((smax, n), np.nan) for _ in range(3))
+    gr0, gr1 = (np.full((smax, n), -1, dtype=np.int32) for _ in range(2))
     lib().or_gamma_chain(seed, unit0, n, width, _p(perm, _i32p), _p(steps, _i32p), _p(alpha, _dp),
-                         _p(cur, _u64p), _p(gtr, _dp), _p(gtol, _dp), _p(gmar, _dp))
-    return dict(alpha=alpha, gtrace=gtr, gtol=gtol, gmargin=gmar, perm=perm, cursors=cur)
+                         _p(cur, _u64p), _p(gtr, _dp), _p(gtol, _dp), _p(gmar, _dp),
+                         _p(gr0, _i32p), _p(gr1, _i32p))
+    return dict(alpha=alpha, gtrace=gtr, gtol=gtol, gmargin=gmar, gr0=gr0, gr1=gr1, perm=perm,
+                cursors=cur)
 
 
 def lda(seed, offsets, ntok, sweeps, counts0=None, cursors=None, unit0=0):

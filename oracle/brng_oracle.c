@@ -371,14 +371,19 @@ void or_step_weibull(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, 
 /*            error bound `abound` carried by alpha itself),                */
 /*   dg     : d g / d alpha (same base deviates),                           */
 /*   margin : the smallest |decision value| / its tolerance over the        */
-/*            draw's decisions; a value <= 1 means an fp32 implementation   */
-/*            may legitimately decide the other way,                        */
-/*   nN, nE : entries consumed.                                             */
+/*            draw's decisions (the sign of 1 + c x, the accept test and,  */
+/*            for a shape with an error bound, alpha < 1); a value <= 1    */
+/*            means an fp32 implementation may decide the other way,       */
+/*   nN, nE : entries consumed,                                             */
+/*   r0, r1 : the rounds (counted from 0 in this call) in which the draw    */
+/*            started and completed; a flip changes consumption from the  */
+/*            round it is made in, anywhere in [r0, r1].                    */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
     double g, tol, dg, margin;
     int nN, nE;
+    int r0, r1; /* rounds of the draw's first Gaussian and of its completion */
 } gdraw_t;
 
 /* q(y) = 3 ln(1+y) - 3y + 3y^2/2 - y^3; d q(y) is the accept statistic
@@ -407,26 +412,31 @@ static void or_gamma_rounds(stream_t *s, int nslots, gsrc_t *src)
     double kx[OR_MAXSLOT]; /* |d ln(g)/d ln(x)| of the accepted draw */
     uint8_t hold[OR_MAXSLOT], acc[OR_MAXSLOT];
     gdraw_t res[OR_MAXSLOT];
-    int any = 0;
+    int any = 0, rnd = 0;
     for (int k = 0; k < nslots; k++) {
         hold[k] = (uint8_t)src->next(src, k, &alpha[k], &ab[k]);
         any |= hold[k];
     }
     /* per-draw setup */
-#define SETUP(k)                                                                 \
+#define SETUP(k, r)                                                              \
     do {                                                                         \
         res[k].g = 0.0; res[k].tol = 0.0; res[k].dg = 0.0;                      \
         res[k].margin = INFINITY; res[k].nN = 0; res[k].nE = 0;                  \
+        res[k].r0 = (r); res[k].r1 = -1;                                         \
         kx[k] = 0.0;                                                             \
         if (shape_ok(alpha[k])) {                                                \
             double a_ = alpha[k] < 1.0 ? alpha[k] + 1.0 : alpha[k];              \
             d[k] = a_ - 1.0 / 3.0;                                               \
             c[k] = 1.0 / sqrt(9.0 * d[k]);                                       \
+            /* alpha < 1 (the boost) is a decision too when alpha carries   */  \
+            /* an error bound */                                                \
+            if (ab[k] > 0.0)                                                     \
+                res[k].margin = fabs(alpha[k] - 1.0) / ab[k];                    \
         }                                                                        \
     } while (0)
     for (int k = 0; k < nslots; k++)
         if (hold[k])
-            SETUP(k);
+            SETUP(k, 0);
     while (any) {
         /* a Gaussian for every slot holding a valid draw, ascending */
         for (int k = 0; k < nslots; k++) {
@@ -489,13 +499,15 @@ static void or_gamma_rounds(stream_t *s, int nslots, gsrc_t *src)
             if (hold[k] && (acc[k] || !shape_ok(alpha[k]))) {
                 if (!shape_ok(alpha[k]))
                     res[k].g = NAN;
+                res[k].r1 = rnd;
                 src->done(src, k, &res[k]);
                 hold[k] = (uint8_t)src->next(src, k, &alpha[k], &ab[k]);
                 if (hold[k])
-                    SETUP(k);
+                    SETUP(k, rnd + 1);
             }
             any |= hold[k];
         }
+        rnd++;
     }
 #undef SETUP
 }
@@ -864,12 +876,14 @@ void or_expchain(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, uint
  * draw is accepted it starts the chain's next step in the next round.
  * alpha (user order) in: alpha_0, out: the next shape.  Slots follow perm,
  * steps[c] per chain.  gtr/gtol/gmar are [t][slot] (left untouched where a
- * chain has no step t). */
+ * chain has no step t); gr0/gr1 (may be null) receive each draw's start and
+ * completion rounds, counted per unit from this call's first round. */
 typedef struct {
     int L[OR_MAXSLOT], t[OR_MAXSLOT];
     double a[OR_MAXSLOT], ab[OR_MAXSLOT];
     uint32_t n, lo;
     double *gtr, *gtol, *gmar;
+    int32_t *gr0, *gr1;
 } chains_t;
 
 static int chains_next(gsrc_t *g, int k, double *alpha, double *abound)
@@ -889,6 +903,8 @@ static void chains_done(gsrc_t *g, int k, const gdraw_t *r)
     if (c->gtr) c->gtr[o] = r->g;
     if (c->gtol) c->gtol[o] = r->tol;
     if (c->gmar) c->gmar[o] = r->margin;
+    if (c->gr0) c->gr0[o] = r->r0;
+    if (c->gr1) c->gr1[o] = r->r1;
     double an = 0.1 + r->g;
     /* the next shape carries g's bound plus the fp32 rounding of 0.1 + g
      * and of the constant 0.1 itself */
@@ -899,7 +915,7 @@ static void chains_done(gsrc_t *g, int k, const gdraw_t *r)
 
 void or_gamma_chain(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, const int32_t *perm,
                     const int32_t *steps, double *alpha, uint64_t *cursors,
-                    double *gtr, double *gtol, double *gmar)
+                    double *gtr, double *gtol, double *gmar, int32_t *gr0, int32_t *gr1)
 {
     if (width == 0 || width > OR_MAXSLOT)
         return;
@@ -915,6 +931,8 @@ void or_gamma_chain(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, c
         cs->gtr = gtr;
         cs->gtol = gtol;
         cs->gmar = gmar;
+        cs->gr0 = gr0;
+        cs->gr1 = gr1;
         for (int k = 0; k < ns; k++) {
             uint32_t ch = perm ? (uint32_t)perm[lo + k] : lo + k;
             cs->a[k] = alpha[ch];

@@ -70,3 +70,36 @@ def compare_units(gpu, ref, tol, margin, units_of_slot, step_axis=True, margin_l
         else:
             bad_total += int((~okc[t0:]).sum())
     return bad_total, flipped
+
+
+def compare_rounds(gpu, ref, tol, margin, r0, r1, units_of_slot, margin_limit=1.0):
+    """compare_units for [t][slot] traces whose slots draw in rounds (gamma
+    chains): a unit's steps do not line up in time across slots, so the
+    unit's first mismatch is the one that completed in the earliest round,
+    rb.  A flip is made in a round of the flipped draw's life [r0, r1], and
+    the flipped draw itself then mismatches, at r1 at the latest; so the
+    mismatch is explained only by a draw with margin <= limit and
+    r0 <= rb <= r1.  r0/r1 are the oracle's start and completion rounds per
+    draw (-1 where no draw)."""
+    gpu = np.atleast_2d(gpu)
+    ref = np.atleast_2d(ref)
+    ok = within(gpu, ref, np.atleast_2d(tol))
+    drawn = np.atleast_2d(r1) >= 0
+    r0 = np.atleast_2d(r0)
+    r1 = np.atleast_2d(r1)
+    margin = np.atleast_2d(margin)
+    bad_total = 0
+    flipped = set()
+    for u in np.unique(units_of_slot):
+        cols = np.where(units_of_slot == u)[0]
+        badc = drawn[:, cols] & ~ok[:, cols]
+        if not badc.any():
+            continue
+        rb = r1[:, cols][badc].min()
+        cand = (drawn[:, cols] & (margin[:, cols] <= margin_limit) & (r0[:, cols] <= rb)
+                & (rb <= r1[:, cols]))
+        if cand.any():
+            flipped.add(int(u))
+        else:
+            bad_total += int(badc.sum())
+    return bad_total, flipped

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_1412_4825_amd import workloads
-from tests.parity_util import compare_units, tol_of, within
+from tests.parity_util import compare_rounds, compare_units, tol_of, within
 
 pytestmark = pytest.mark.gpu
 
@@ -303,7 +303,7 @@ def test_gamma_chains(dev):
     r = oracle.gamma_chain(seed, w["alpha0"], w["steps"], perm=perm)
     assert np.array_equal(perm, oracle.sort_by_length(w["steps"]))
     units = np.arange(w["n_chains"]) // 64
-    bad, flips = compare_units(g, r["gtrace"], r["gtol"], r["gmargin"], units)
+    bad, flips = compare_rounds(g, r["gtrace"], r["gtol"], r["gmargin"], r["gr0"], r["gr1"], units)
     print("gamma flips", len(flips), "bad", bad, flush=True)
     assert bad == 0
     assert len(flips) <= 2

@@ -115,3 +115,50 @@ def test_lda_sweeps():
     pits = np.concatenate(pits)
     assert stats.kstest(pits, "uniform").pvalue > 1e-3
     assert np.array_equal(r["counts"], ct[-1])
+
+
+def test_gamma_chain_rounds():
+    """Per-slot rounds (reading of Sec. 2.2 for shared buffers): a slot's
+    first draw starts in round 0 and each next draw in the round after the
+    previous one completed."""
+    w = workloads.gamma_chain(n_chains=300, lmin=3, lmax=40, seed=12)
+    r = oracle.gamma_chain(5, w["alpha0"], w["steps"])
+    r0, r1 = r["gr0"], r["gr1"]
+    live = ~np.isnan(r["gtrace"])
+    assert np.array_equal(live, r1 >= 0) and np.array_equal(live, r0 >= 0)
+    assert np.all(r0[live] <= r1[live])
+    assert np.all(r0[0] == 0)
+    nxt = live[1:]
+    assert np.array_equal(r0[1:][nxt], r1[:-1][nxt] + 1)
+
+
+def test_gamma_chain_boost_branch_is_a_decision():
+    """A chain shape alpha_t = 0.1 + g_{t-1} carries an error bound, and
+    whether alpha_t < 1 (the boost for small shapes, Sec. 2.2 GetGamma)
+    selects a different draw: at a shape within its bound of 1 the draw's
+    margin must say that an fp32 run may take the other branch."""
+    seed = 3
+
+    def run(a0):
+        return oracle.gamma_chain(seed, np.array([a0]), np.array([2], dtype=np.int32))
+
+    def f(a0):
+        return 0.1 + run(a0)["gtrace"][0, 0] - 1.0
+
+    lo, hi = 0.5, 3.0
+    flo = f(lo)
+    assert np.sign(flo) != np.sign(f(hi))
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if np.sign(f(mid)) == np.sign(flo):
+            lo = mid
+        else:
+            hi = mid
+    a, b = run(lo), run(hi)
+    # both sides of the crossing: alpha_1 within its bound of 1
+    for r in (a, b):
+        assert abs(0.1 + r["gtrace"][0, 0] - 1.0) < r["gtol"][0, 0]
+        assert r["gmargin"][1, 0] <= 1.0
+    # and the branch matters: the two sides draw very different values
+    ga, gb = a["gtrace"][1, 0], b["gtrace"][1, 0]
+    assert abs(ga - gb) > 1e-3 * max(abs(ga), abs(gb))
