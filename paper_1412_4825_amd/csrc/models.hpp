@@ -482,6 +482,15 @@ constexpr int LDA_LDS_BYTES = LDA_RINGS_BYTES + AUX_BYTES;
 //   C_k = q_0 + ... + q_k; token i takes u_i from the U pool,
 //   j = (u_i 2^24 - 1) / 2, t = (j Q) >> 23, bin = first k with t < C_k.
 // LDS holds the bin ends, the counts and the component gammas (K <= 256).
+// Whether this lane's component of block b (components 64 b .. 64 b + 63)
+// exists.  K passes through an empty asm so the comparison is made where it
+// is used instead of being kept, one lane mask per block, across the sweep.
+__device__ __forceinline__ bool comp_in(int K, int b, uint32_t lane) {
+    int Kx = K;
+    asm volatile("" : "+s"(Kx));
+    return b * 64 + (int)lane < Kx;
+}
+
 // ---------------------------------------------------------------------------
 __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t doc,
                          unsigned char* lds) {
@@ -508,7 +517,7 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int k = b * 64 + (int)lane;
-        if (k < K) cnt[k] = counts[k];
+        if (comp_in(K, b, lane)) cnt[k] = counts[k];
     }
     for (int32_t sw = 0; sw < D.max_steps; ++sw) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -528,8 +537,9 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int k = b * 64 + (int)lane;
-            y[b] = (k < K) ? yv[k] : 0.0f;
-            if (k < K) part += y[b];
+            const bool in = b * 64 < K && comp_in(K, b, lane);
+            y[b] = in ? yv[k] : 0.0f;
+            if (in) part += y[b];
         }
         const float S = wave_sum(part);
         // theta, quantised weights and their prefix sums
@@ -539,10 +549,11 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
         for (int b = 0; b < 4; ++b) {
             const int k = b * 64 + (int)lane;
             if (b * 64 < K) {
-                th[b] = (k < K && S > 0.0f) ? y[b] / S : 0.0f;
-                const int32_t q = (k < K) ? (int32_t)rintf(th[b] * 16777216.0f) : 0;
+                const bool in = comp_in(K, b, lane);
+                th[b] = (in && S > 0.0f) ? y[b] / S : 0.0f;
+                const int32_t q = in ? (int32_t)rintf(th[b] * 16777216.0f) : 0;
                 const int32_t inc = wave_incl_scan(q) + carry;
-                if (k < K) Cs[k] = inc;
+                if (in) Cs[k] = inc;
                 carry = __shfl(inc, 63, 64);
             } else {
                 th[b] = 0.0f;
@@ -553,14 +564,14 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int k = b * 64 + (int)lane;
-                if (k < K) Cs[k] = k + 1;
+                if (b * 64 < K && comp_in(K, b, lane)) Cs[k] = k + 1;
             }
             Q = K;
         }
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int k = b * 64 + (int)lane;
-            if (k < K) cnt[k] = 0;
+            if (b * 64 < K && comp_in(K, b, lane)) cnt[k] = 0;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -588,7 +599,7 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int k = b * 64 + (int)lane;
-            if (k < K) {
+            if (b * 64 < K && comp_in(K, b, lane)) {
                 if (th_tr) th_tr[(size_t)sw * D.stride + off + k] = th[b];
                 if (ct_tr) ct_tr[(size_t)sw * D.stride + off + k] = cnt[k];
             }
@@ -597,7 +608,7 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int k = b * 64 + (int)lane;
-        if (k < K) counts[k] = cnt[k];
+        if (b * 64 < K && comp_in(K, b, lane)) counts[k] = cnt[k];
     }
     rn.close(*mp);
     re.close(*mp);

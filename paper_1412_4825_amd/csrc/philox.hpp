@@ -28,6 +28,10 @@ struct Key {
 // runs on the scalar unit.
 __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                           uint32_t k0, uint32_t k1) {
+    // The bumped keys are recomputed at each use (two scalar adds per round)
+    // instead of being hoisted out of the callers' loops, where twenty
+    // loop-invariant scalar registers would crowd out the samplers' state.
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
