@@ -473,6 +473,10 @@ using LdaRN = EpochReader<KIND_N, 1>;
 using LdaRE = EpochReader<KIND_E, 1>;
 using LdaRU = EpochReader<KIND_U, 1>;
 constexpr int LDA_RINGS_BYTES = LdaRN::LDS_BYTES + LdaRE::LDS_BYTES + LdaRU::LDS_BYTES;
+// Epoch points every two rounds keep the one-chunk rings covered.
+constexpr uint32_t LDA_EPOCH = 2;
+static_assert(LdaRN::CH >= 64 * LDA_EPOCH && LdaRE::CH >= 128 * LDA_EPOCH,
+              "LDA rings must cover an epoch");
 constexpr int LDA_LDS_BYTES = LDA_RINGS_BYTES + AUX_BYTES;
 
 // ---------------------------------------------------------------------------
@@ -500,6 +504,8 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
     const int32_t off = D.offsets[doc];
     const int K = D.offsets[doc + 1] - off;
     const int ntok = D.ntok[doc];
+    // largest power of two <= K (K >= 1)
+    const int kstep = K > 0 ? (int)(0x80000000u >> __builtin_clz((uint32_t)K)) : 0;
     LdaRN rn;
     LdaRE re;
     LdaRU ru;
@@ -512,8 +518,11 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
     int32_t* cnt = Cs + LDA_KMAX;                                      // 256 counts
     float* yv = reinterpret_cast<float*>(cnt + LDA_KMAX);              // 256 gammas
     int32_t* counts = reinterpret_cast<int32_t*>(D.state) + off;
-    float* th_tr = reinterpret_cast<float*>(D.trace);
-    int32_t* ct_tr = reinterpret_cast<int32_t*>(D.trace2);
+    const bool want_th = D.trace != nullptr, want_ct = D.trace2 != nullptr;
+    // this lane's trace entries (component lane + 64 b of the document) of
+    // the current sweep's rows; one row further per sweep
+    float* thp = want_th ? reinterpret_cast<float*>(D.trace) + off + lane : nullptr;
+    int32_t* ctp = want_ct ? reinterpret_cast<int32_t*>(D.trace2) + off + lane : nullptr;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int k = b * 64 + (int)lane;
@@ -528,7 +537,7 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
         src.alpha = nullptr;
         src.cnt = cnt;
         src.y = yv;
-        gamma_rounds<false>(rn, re, src, 4096u + 64u * (uint32_t)K);
+        gamma_rounds<true, LDA_EPOCH>(rn, re, src, 4096u + 64u * (uint32_t)K);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -554,7 +563,7 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
                 const int32_t q = in ? (int32_t)rintf(th[b] * 16777216.0f) : 0;
                 const int32_t inc = wave_incl_scan(q) + carry;
                 if (in) Cs[k] = inc;
-                carry = __shfl(inc, 63, 64);
+                carry = last_lane(inc);
             } else {
                 th[b] = 0.0f;
             }
@@ -579,19 +588,18 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
         for (int i0 = 0; i0 < ntok; i0 += 64) {
             const bool act = i0 + (int)lane < ntok;
             const float u = ru.take(act);
-            if (act) {
-                const uint32_t j = ((uint32_t)(u * 16777216.0f) - 1u) >> 1;
-                const uint32_t t = (uint32_t)(((uint64_t)j * (uint32_t)Q) >> 23);
-                int lo = 0, hi = K - 1;  // first k with t < Cs[k]
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if ((uint32_t)Cs[mid] > t)
-                        hi = mid;
-                    else
-                        lo = mid + 1;
-                }
-                atomicAdd(&cnt[lo], 1);
+            const uint32_t j = ((uint32_t)(u * 16777216.0f) - 1u) >> 1;
+            const uint32_t t = (uint32_t)(((uint64_t)j * (uint32_t)Q) >> 23);
+            // first k with t < C_k, i.e. the number of k with C_k <= t (the
+            // C_k do not decrease and C_{K-1} = Q > t): binary lifting over
+            // the power-of-two steps down from kstep, the same count of
+            // steps in every lane; a probe past the end reads C_{K-1}
+            int pos = 0;
+            for (int step = kstep; step > 0; step >>= 1) {
+                const int probe = min(pos + step, K) - 1;
+                pos += (uint32_t)Cs[probe] <= t ? step : 0;
             }
+            if (act) atomicAdd(&cnt[pos], 1);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -600,10 +608,12 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
         for (int b = 0; b < 4; ++b) {
             const int k = b * 64 + (int)lane;
             if (b * 64 < K && comp_in(K, b, lane)) {
-                if (th_tr) th_tr[(size_t)sw * D.stride + off + k] = th[b];
-                if (ct_tr) ct_tr[(size_t)sw * D.stride + off + k] = cnt[k];
+                if (want_th) thp[b * 64] = th[b];
+                if (want_ct) ctp[b * 64] = cnt[k];
             }
         }
+        thp += D.stride;
+        ctp += D.stride;
     }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {

@@ -26,12 +26,14 @@ struct Key {
 // and mixes in the key; the key advances by the Weyl increments between
 // rounds.  Key words are wave-uniform in every caller, so the key schedule
 // runs on the scalar unit.
+// KEYS_AT_USE: the bumped keys are recomputed at each use (two scalar adds
+// per round) instead of being hoisted out of the caller's loops, where twenty
+// loop-invariant scalar registers would crowd out a sampler's own state (the
+// gamma and Dirichlet rounds); callers with few live scalars keep them.
+template <bool KEYS_AT_USE = false>
 __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                           uint32_t k0, uint32_t k1) {
-    // The bumped keys are recomputed at each use (two scalar adds per round)
-    // instead of being hoisted out of the callers' loops, where twenty
-    // loop-invariant scalar registers would crowd out the samplers' state.
-    asm volatile("" : "+s"(k0), "+s"(k1));
+    if (KEYS_AT_USE) asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
@@ -49,8 +51,10 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     return make_uint4(c0, c1, c2, c3);
 }
 
+template <bool KEYS_AT_USE = false>
 __device__ __forceinline__ uint4 block_words(const Key& key, uint32_t kind, uint64_t block) {
-    return philox10((uint32_t)block, (uint32_t)(block >> 32), kind, key.c3, key.k0, key.k1);
+    return philox10<KEYS_AT_USE>((uint32_t)block, (uint32_t)(block >> 32), kind, key.c3, key.k0,
+                                 key.k1);
 }
 
 // U = (2 (w >> 9) + 1) 2^-24: the open midpoint grid, exact in fp32.
@@ -133,9 +137,9 @@ __device__ __forceinline__ uint4 convert_block(const uint4 w) {
 }
 
 // Pool block `block` of (key, KIND), converted.
-template <uint32_t KIND>
+template <uint32_t KIND, bool KEYS_AT_USE = false>
 __device__ __forceinline__ uint4 gen_block(const Key& key, uint64_t block) {
-    return convert_block<KIND>(block_words(key, KIND, block));
+    return convert_block<KIND>(block_words<KEYS_AT_USE>(key, KIND, block));
 }
 
 template <uint32_t KIND> struct KindTraits {

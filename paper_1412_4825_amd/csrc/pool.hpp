@@ -253,9 +253,10 @@ struct EpochReader {
     T* win;
     T* ring;  // LDS, R + 64 entries
     Key key;
-    uint64_t wbase, cur, staged;  // ring holds entries [.., staged)
+    uint64_t wbase, staged;  // ring holds entries [.., staged)
     uint32_t wlen, W;
-    int32_t avail;  // staged - cur
+    int32_t avail;  // staged - cursor (the cursor itself is staged - avail)
+    uint32_t pos;   // cursor mod R: the ring index of the next entry
     bool inflight;  // pf holds chunk `staged`
     u32x4 pf[CHV];
 
@@ -293,12 +294,12 @@ struct EpochReader {
             u32x4 tmp[CHV];
 #pragma unroll
             for (int j = 0; j < CHV; ++j) {
-                const uint4 v = gen_block<KIND>(key, b0 + (uint32_t)(j * 64) + lane);
+                const uint4 v = gen_block<KIND, true>(key, b0 + (uint32_t)(j * 64) + lane);
                 wd[j * 64 + lane] = v;
                 tmp[j] = u32x4{v.x, v.y, v.z, v.w};
             }
             for (uint32_t b = (uint32_t)(CHV * 64) + lane; b < nblk; b += 64)
-                wd[b] = gen_block<KIND>(key, b0 + b);
+                wd[b] = gen_block<KIND, true>(key, b0 + b);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             wbase = staged;
             wlen = W;
@@ -333,21 +334,30 @@ struct EpochReader {
         wbase = m.wbase[KIND];
         wlen = m.wlen[KIND];
         W = Wk;
-        cur = m.cur[KIND];
+        const uint64_t cur = m.cur[KIND];
         staged = cur & ~(uint64_t)(CH - 1);
         avail = -(int32_t)(cur - staged);
+        pos = (uint32_t)cur & (R - 1);
         prefetch();
         stage();
     }
-    // Make entries [cur, cur + n) readable (n <= 64).
+    // Make entries [cursor, cursor + n) readable (n <= 64).
     __device__ __forceinline__ void reserve(uint32_t n) {
         while ((int32_t)n > avail) stage();
     }
-    // Entry cur + r (r < 64, after reserve).
-    __device__ __forceinline__ T peek(uint32_t r) const { return ring[((uint32_t)cur & (R - 1)) + r]; }
+    // Entry cursor + r (r < 64, after reserve).
+    __device__ __forceinline__ T peek(uint32_t r) const { return ring[pos + r]; }
     __device__ __forceinline__ void advance(uint32_t n) {
-        cur += n;
+        pos = (pos + n) & (R - 1);
         avail -= (int32_t)n;
+    }
+    // Covered use: calls move only the ring position, and the count of
+    // entries left is recovered from it where it is needed (epoch points,
+    // close).  Valid while 1 <= avail <= R, which holds at every epoch point
+    // when an epoch never takes more than one chunk.
+    __device__ __forceinline__ void advance_pos(uint32_t n) { pos = (pos + n) & (R - 1); }
+    __device__ __forceinline__ void sync_avail() {
+        avail = (int32_t)((((uint32_t)staged - pos - 1u) & (R - 1)) + 1u);
     }
     // One call: every active lane gets the next entry, in lane order.
     __device__ __forceinline__ T take(bool active) {
@@ -360,7 +370,7 @@ struct EpochReader {
     }
     __device__ void close(Meta& m) const {
         if (lane_id() == 0) {
-            m.cur[KIND] = cur;
+            m.cur[KIND] = staged - (uint64_t)(int64_t)avail;
             m.wbase[KIND] = wbase;
             m.wlen[KIND] = wlen;
         }

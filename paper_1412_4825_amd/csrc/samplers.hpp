@@ -49,20 +49,6 @@ __device__ __forceinline__ bool gamma_shape_ok(float alpha) {
     return alpha > 0.0f && alpha < 0x1p64f;
 }
 
-// Per-lane constants of the draw a lane holds.
-struct GammaLane {
-    float alpha, a, d, c;
-    bool valid, boost;
-    __device__ __forceinline__ void setup(float al) {
-        alpha = al;
-        valid = gamma_shape_ok(al);
-        boost = valid && al < 1.0f;
-        a = valid ? (boost ? al + 1.0f : al) : 1.0f;
-        d = a - (1.0f / 3.0f);
-        c = __builtin_amdgcn_rsqf(9.0f * d);  // 1 / sqrt(9 d)
-    }
-};
-
 // ln(1 + y) for y > -1: the logarithm of the rounded sum u = 1 + y plus the
 // first-order correction for the rounding (y - (u - 1)) / u.
 __device__ __forceinline__ float log1p_fast(float y) {
@@ -71,22 +57,25 @@ __device__ __forceinline__ float log1p_fast(float y) {
     return fmaf(__builtin_amdgcn_logf(u), 0.693147180559945309f, corr);
 }
 
-// The accept statistic E + d q(y) in fp32 for a lane with 1 + c x = v0 > 0:
-// *acc is its sign, *unsure whether it lies within its fp32 error bound of
-// zero (term magnitudes times a few ulp, plus the effect of y's own
-// rounding), in which case the decision is taken again in fp64.
-__device__ __forceinline__ void mt_test(float d, float y, float v0, float e, bool* acc,
-                                        bool* unsure) {
+// The accept statistic E + d q(y) in fp32 for a lane with 1 + c x = v0 > 0,
+// and the size of its fp32 error bound (term magnitudes times a few ulp, plus
+// the effect of y's own rounding): a statistic within the bound of zero is
+// decided again in fp64.
+struct MtStat {
+    float stat, bound;
+};
+__device__ __forceinline__ MtStat mt_stat(float d, float y, float v0, float e) {
     const float l = log1p_fast(y);
     const float y2 = y * y;
     const float y3 = y2 * y;
     const float q = (3.0f * l - 3.0f * y) + (1.5f * y2 - y3);
-    const float stat = e + d * q;
     const float mag = e + d * (3.0f * fabsf(l) + 3.0f * fabsf(y) + 1.5f * y2 + fabsf(y3) +
                                3.0f * y2 * y2 * __builtin_amdgcn_rcpf(v0));
-    *acc = stat > 0.0f;
-    *unsure = !(fabsf(stat) > 2e-6f * mag);
+    return MtStat{e + d * q, 2e-6f * mag};
 }
+
+// Per-lane condition from a wave mask (the mask's own lane bit, no compare).
+__device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
 // Gamma draws in rounds over the 64 lanes of a wave.  Each lane holds at most
 // one draw.  Per round: a Gaussian for every lane holding a valid draw, an
@@ -98,91 +87,114 @@ __device__ __forceinline__ void mt_test(float d, float y, float v0, float e, boo
 // (the readers' epoch points).
 //
 // The loop carries only numbers (the shape of the draw each lane holds and
-// the source's counters); the per-lane conditions are derived from them at
-// the top of each round, which keeps lane-mask bookkeeping out of the loop.
+// the source's counters).  Each round's lane conditions are wave masks: the
+// ballot of one comparison is that comparison's own mask, masks combine on
+// the scalar unit, and a lane reads its bit back where it needs a condition.
 // Src provides:
 //   float first()                 shape of this lane's first draw (any
 //                                 value if it holds none)
-//   bool holding()                whether this lane holds a draw
-//   float complete(bool done, float g, float alpha)
-//                                 called by every lane; a lane whose draw is
-//                                 done hands over g; returns the shape of the
-//                                 lane's draw for the next round
+//   bool holding()                whether this lane holds a draw (a single
+//                                 comparison)
+//   float complete(uint64_t md, float g, float alpha)
+//                                 called by every lane with the mask of
+//                                 lanes whose draw is done; such a lane hands
+//                                 over g; returns the shape of the lane's
+//                                 draw for the next round
 //   void flush()                  epoch point (global stores go here)
 constexpr uint32_t EPOCH_ROUNDS = 4;
 
 // COVERED: the readers' rings hold an epoch's worst case (64 Gaussians and
 // 128 exponentials per round), so no call inside the rounds needs to stage.
-template <bool COVERED, class RN, class RE, class Src>
+// EPOCH (a power of two) is the number of rounds between epoch points.
+// Rounds run in whole epochs: the loop stops after the first multiple of
+// EPOCH rounds that is at least max_rounds, or when no lane holds a draw.
+template <bool COVERED, uint32_t EPOCH = EPOCH_ROUNDS, class RN, class RE, class Src>
 __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t max_rounds) {
+    // Covered readers move only their ring positions inside an epoch.
+    auto adv_n = [&](uint32_t n) {
+        if constexpr (COVERED) rn.advance_pos(n); else rn.advance(n);
+    };
+    auto adv_e = [&](uint32_t n) {
+        if constexpr (COVERED) re.advance_pos(n); else re.advance(n);
+    };
     float al = src.first();
     // Let every load issued so far land here, once: otherwise the first use
     // of a loaded value inside the loop makes the compiler wait for all
     // memory operations in flight at that point of every round.
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-    for (uint32_t round = 0; round < max_rounds; ++round) {
-        const bool hold = src.holding();
-        if (wave_ballot(hold) == 0) break;
-        if ((round & (EPOCH_ROUNDS - 1)) == 0) {
+    for (uint32_t round = 0;; ++round) {
+        const uint64_t mh = wave_ballot(src.holding());
+        if (mh == 0) break;
+        if ((round & (EPOCH - 1)) == 0) {
+            if (round >= max_rounds) break;
+            if constexpr (COVERED) {
+                rn.sync_avail();
+                re.sync_avail();
+            }
             epoch_point(rn, re);
             src.flush();
         }
-        GammaLane L;
-        L.setup(al);
-        const bool pend = hold && L.valid;
+        // shapes outside (0, 2^64) have no draw; below 1 the boost applies
+        const uint64_t mv = wave_ballot(al > 0.0f) & wave_ballot(al < 0x1p64f);
+        const uint64_t mboost = mv & wave_ballot(al < 1.0f);
+        const float a = lane_in(mv) ? (lane_in(mboost) ? al + 1.0f : al) : 1.0f;
+        const float d = a - (1.0f / 3.0f);
+        const float c = __builtin_amdgcn_rsqf(9.0f * d);  // 1 / sqrt(9 d)
+        const uint64_t mp = mh & mv;
         // The Gaussian call and the exponential call hand entries to the
         // same lanes whenever every pending lane has 1 + c x > 0, which is
         // nearly always: both are read with the same ranks at once, and the
         // exponential call is redone with its own ranks when it is not so.
-        const uint64_t mp = wave_ballot(pend);
         const uint32_t np = (uint32_t)__popcll(mp);
-        if (!COVERED) {
+        if constexpr (!COVERED) {
             rn.reserve(np);
             re.reserve(np);
         }
         const uint32_t rk = mask_rank(mp);
         const float xr = rn.peek(rk);
         float e = re.peek(rk);
-        rn.advance(np);
-        const float x = pend ? xr : 0.0f;
-        const float y = L.c * x;
+        adv_n(np);
+        const float x = lane_in(mp) ? xr : 0.0f;
+        const float y = c * x;
         const float v0 = 1.0f + y;
-        const bool need_e = pend && v0 > 0.0f;
-        const uint64_t me = wave_ballot(need_e);
+        const uint64_t me = mp & wave_ballot(v0 > 0.0f);
         if (me == mp) {
-            re.advance(np);
+            adv_e(np);
         } else {
             e = re.peek(mask_rank(me));
-            re.advance((uint32_t)__popcll(me));
+            adv_e((uint32_t)__popcll(me));
         }
         // One lane in twenty-odd needs the logarithm in a round, so the wave
         // nearly always does: every lane evaluates the test, and only lanes
         // whose fp32 statistic is within its error bound of zero (rare)
         // decide again in fp64.
-        bool acc, unsure;
-        mt_test(L.d, y, v0, e, &acc, &unsure);
-        acc = need_e && acc;
-        unsure = need_e && unsure;
-        if (wave_ballot(unsure) != 0) {
-            if (unsure) acc = mt_accept64(L.a, x, e);
+        const MtStat st = mt_stat(d, y, v0, e);
+        uint64_t macc = me & wave_ballot(st.stat > 0.0f);
+        const uint64_t muns = me & wave_ballot(!(fabsf(st.stat) > st.bound));
+        if (muns != 0) {
+            bool a64 = false;
+            if (lane_in(muns)) a64 = mt_accept64(a, x, e);
+            macc = (macc & ~muns) | (muns & wave_ballot(a64));
         }
-        float g = L.d * (v0 * v0 * v0);
-        const bool b = acc && L.boost;
+        float g = d * (v0 * v0 * v0);
         // boost: g exp(-E'/alpha) = 2^(log2 g - E' log2(e) / alpha), one
         // exponential whose result underflows only when the product does
-        const uint64_t mb = wave_ballot(b);
+        const uint64_t mb = macc & mboost;
         if (mb != 0) {
             const uint32_t nb = (uint32_t)__popcll(mb);
-            if (!COVERED) re.reserve(nb);
+            if constexpr (!COVERED) re.reserve(nb);
             const float e2 = re.peek(mask_rank(mb));
-            re.advance(nb);
+            adv_e(nb);
             const float gb = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(g) -
                                                     e2 * (1.44269504088896341f * __builtin_amdgcn_rcpf(al)));
-            g = b ? gb : g;
+            g = lane_in(mb) ? gb : g;
         }
-        const bool done = hold && (acc || !L.valid);
-        g = L.valid ? g : __builtin_nanf("");
-        al = src.complete(done, g, al);
+        g = lane_in(mv) ? g : __builtin_nanf("");
+        al = src.complete(mh & (macc | ~mv), g, al);
+    }
+    if constexpr (COVERED) {
+        rn.sync_avail();
+        re.sync_avail();
     }
     src.flush();
 }
@@ -194,7 +206,8 @@ struct OneEachSrc {
     float g;
     __device__ __forceinline__ float first() { return want ? alpha : 1.0f; }
     __device__ __forceinline__ bool holding() const { return want != 0; }
-    __device__ __forceinline__ float complete(bool done, float gv, float al) {
+    __device__ __forceinline__ float complete(uint64_t md, float gv, float al) {
+        const bool done = lane_in(md);
         g = done ? gv : g;
         want = done ? 0 : want;
         return al;
@@ -221,16 +234,15 @@ struct CompSrc {
         return comp < K ? shape(comp) : 1.0f;
     }
     __device__ __forceinline__ bool holding() const { return comp < K; }
-    __device__ __forceinline__ float complete(bool done, float gv, float al) {
+    __device__ __forceinline__ float complete(uint64_t md, float gv, float al) {
+        const bool done = lane_in(md);
         if (done) y[comp] = gv;
-        const uint64_t freed = wave_ballot(done);
-        const uint32_t r = mask_rank(freed);
         float a = al;
         if (done) {
-            comp = (int)(next + r);
+            comp = (int)(next + mask_rank(md));
             if (comp < K) a = shape(comp);
         }
-        next += (uint32_t)__popcll(freed);
+        next += (uint32_t)__popcll(md);
         return a;
     }
     __device__ __forceinline__ void flush() {}
@@ -247,55 +259,69 @@ struct ChainSrc {
     float* out;      // this lane's entry of the trace row of the next flushed step
     int64_t stride;  // trace elements between steps
     float* obuf;     // LDS, EPOCH_ROUNDS x 64 values; this lane's column
-    uint32_t nb;     // values buffered by this lane
+    int32_t t_ep;    // t at the last flush: values buffered = t - t_ep
     __device__ __forceinline__ float first() {
-        nb = 0;
+        t_ep = t;
         return alpha;
     }
     __device__ __forceinline__ bool holding() const { return t < L; }
-    // Branch-free: every lane writes its value to its next buffer slot, and
-    // only lanes whose draw completed move on (a slot written by a lane that
-    // did not is overwritten before it is flushed).
-    __device__ __forceinline__ float complete(bool done, float gv, float) {
-        if (trace) {
-            obuf[nb * 64] = gv;
-            nb += done ? 1u : 0u;
-        }
+    // Branch-free: every lane writes its value to its next buffer slot (also
+    // without a trace: the buffer is there either way), and only lanes whose
+    // draw completed move on (a slot written by a lane that did not is
+    // overwritten before it is flushed).
+    __device__ __forceinline__ float complete(uint64_t md, float gv, float) {
+        const bool done = lane_in(md);
+        obuf[(t - t_ep) * 64] = gv;
         alpha = done ? 0.1f + gv : alpha;
         t += done ? 1 : 0;
         return alpha;
     }
     __device__ __forceinline__ void flush() {
         if (trace) {
+            const int32_t nb = t - t_ep;
             static_for<0, (int)EPOCH_ROUNDS>([&](auto jc) {
-                constexpr uint32_t j = decltype(jc)::value;
+                constexpr int32_t j = decltype(jc)::value;
                 if (j < nb) {
                     *out = obuf[j * 64];
                     out += stride;
                 }
             });
         }
-        nb = 0;
+        t_ep = t;
     }
 };
 
-// Sum over the wave, identical in every lane (fixed butterfly order, then
-// lane 0's value broadcast).
+// Inclusive prefix sums over the 64 lanes with DPP lane moves (no LDS):
+// four row shifts give the sums within each row of 16 lanes, then the last
+// lane of row 0 (of row 2) is added to row 1 (row 3), and the last lane of
+// row 1 to rows 2 and 3.  Lanes without a source add zero.  The order of
+// additions is fixed, so float sums are reproducible.
+template <int CTRL, int ROWS, bool BOUND_ZERO, class T>
+__device__ __forceinline__ T dpp_move(T x) {
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int32_t, x), CTRL, ROWS, 0xF, BOUND_ZERO));
+}
+template <class T>
+__device__ __forceinline__ T dpp_incl_scan(T v) {
+    v += dpp_move<0x111, 0xF, true>(v);   // row_shr:1
+    v += dpp_move<0x112, 0xF, true>(v);   // row_shr:2
+    v += dpp_move<0x114, 0xF, true>(v);   // row_shr:4
+    v += dpp_move<0x118, 0xF, true>(v);   // row_shr:8
+    v += dpp_move<0x142, 0xA, false>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xC, false>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// Sum over the wave, identical in every lane (the scan's last lane).
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, v)));
+    const float t = dpp_incl_scan(v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, t), 63));
 }
 
 // Inclusive prefix sum over lanes (integers, exact).
-__device__ __forceinline__ int32_t wave_incl_scan(int32_t v) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t t = __shfl_up(v, o, 64);
-        if (lane >= (uint32_t)o) v += t;
-    }
-    return v;
-}
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t v) { return dpp_incl_scan(v); }
+
+// Value of lane 63 (wave-uniform).
+__device__ __forceinline__ int32_t last_lane(int32_t v) { return __builtin_amdgcn_readlane(v, 63); }
 
 }  // namespace brng
