@@ -504,8 +504,9 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
     const int32_t off = D.offsets[doc];
     const int K = D.offsets[doc + 1] - off;
     const int ntok = D.ntok[doc];
-    // largest power of two <= K (K >= 1)
-    const int kstep = K > 0 ? (int)(0x80000000u >> __builtin_clz((uint32_t)K)) : 0;
+    // first step of the bin search: the largest power of two <= K - 1 (the
+    // answer is at most K - 1, and the steps add up to at least that)
+    const int kstep = K > 1 ? (int)(0x80000000u >> __builtin_clz((uint32_t)(K - 1))) : 0;
     LdaRN rn;
     LdaRE re;
     LdaRU ru;
@@ -585,21 +586,31 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int i0 = 0; i0 < ntok; i0 += 64) {
-            const bool act = i0 + (int)lane < ntok;
-            const float u = ru.take(act);
-            const uint32_t j = ((uint32_t)(u * 16777216.0f) - 1u) >> 1;
-            const uint32_t t = (uint32_t)(((uint64_t)j * (uint32_t)Q) >> 23);
-            // first k with t < C_k, i.e. the number of k with C_k <= t (the
-            // C_k do not decrease and C_{K-1} = Q > t): binary lifting over
-            // the power-of-two steps down from kstep, the same count of
-            // steps in every lane; a probe past the end reads C_{K-1}
-            int pos = 0;
+        // Token u -> t = (j Q) >> 23 with j = (u 2^24 - 1) / 2, then the
+        // first k with t < C_k, i.e. the number of k with C_k <= t (the C_k
+        // do not decrease and C_{K-1} = Q > t): binary lifting over the
+        // power-of-two steps down from kstep, the same count of steps in
+        // every lane; a probe past the end reads C_{K-1}, which never
+        // passes.  Calls are taken two at a time (in call order) so that the
+        // two searches' LDS reads overlap.
+        for (int i0 = 0; i0 < ntok; i0 += 128) {
+            const bool act0 = i0 + (int)lane < ntok;
+            const bool act1 = i0 + 64 + (int)lane < ntok;
+            const float u0 = ru.take(act0);
+            const float u1 = ru.take(act1);
+            const uint32_t t0 =
+                (uint32_t)(((uint64_t)((((uint32_t)(u0 * 16777216.0f)) - 1u) >> 1) * (uint32_t)Q) >> 23);
+            const uint32_t t1 =
+                (uint32_t)(((uint64_t)((((uint32_t)(u1 * 16777216.0f)) - 1u) >> 1) * (uint32_t)Q) >> 23);
+            int p0 = 0, p1 = 0;
             for (int step = kstep; step > 0; step >>= 1) {
-                const int probe = min(pos + step, K) - 1;
-                pos += (uint32_t)Cs[probe] <= t ? step : 0;
+                const uint32_t c0 = (uint32_t)Cs[min(p0 + step, K) - 1];
+                const uint32_t c1 = (uint32_t)Cs[min(p1 + step, K) - 1];
+                p0 += c0 <= t0 ? step : 0;
+                p1 += c1 <= t1 ? step : 0;
             }
-            if (act) atomicAdd(&cnt[pos], 1);
+            if (act0) atomicAdd(&cnt[p0], 1);
+            if (act1) atomicAdd(&cnt[p1], 1);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
