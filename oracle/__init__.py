@@ -82,6 +82,7 @@ def _declare(L):
     L.or_step_weibull.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _dp,
                                   _dp, _dp]
     L.or_step_gamma.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _dp, _dp, _dp, _i32p, _i32p]
+    L.or_step_poisson.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _i32p, _dp]
     L.or_step_dirichlet.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _u64p, _i32p, _dp, _dp, _dp, _dp]
     L.or_multinomial.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _u64p, _i32p, _i32p, _dp, _i32p]
     L.or_triangle.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _dp, _dp, _u64p, _dp, _dp, _dp, _dp]
@@ -210,6 +211,19 @@ def step_gamma(seed, cursors, alpha, width=UNIT_WIDTH, unit0=0):
     lib().or_step_gamma(seed, unit0, n, width, _p(cursors, _u64p), _p(alpha, _dp), _p(out, _dp),
                         _p(t, _dp), _p(m, _dp), _p(nN, _i32p), _p(nE, _i32p))
     return out, t, m, nN, nE
+
+
+def step_poisson(seed, cursors, lam, width=UNIT_WIDTH, unit0=0):
+    """Poisson(lambda) per chain (double precision; U pool): inversion below
+    10, Hormann's transformed rejection (PTRS) above; -1 for lambda outside
+    [0, 2^30].  Returns (k as int32, decision margin)."""
+    lam = _d(lam)
+    n = lam.size
+    out = np.zeros(n, dtype=np.int32)
+    mar = np.zeros(n)
+    lib().or_step_poisson(seed, unit0, n, width, _p(cursors, _u64p), _p(lam, _dp), _p(out, _i32p),
+                          _p(mar, _dp))
+    return out, mar
 
 
 def step_dirichlet(seed, cursors, offsets, alpha, unit0=0):

@@ -635,6 +635,165 @@ static double dirichlet_item(stream_t *s, int K, const double *alpha,
     return mmin;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Poisson(lambda): a discrete getter (the expanded library of Sec. 3's     */
+/* future work).  Double precision on both sides; the U pool only.          */
+/*                                                                          */
+/*   lambda < 10: inversion with one uniform, k = min{k : u <= F(k)}, where */
+/*     F is accumulated from p_0 = exp(-lambda), p_k = p_{k-1} lambda / k.  */
+/*   lambda >= 10: transformed rejection with squeeze (Hormann 1993,        */
+/*     "PTRS"): an attempt takes two uniforms u, v; with U = u - 1/2,       */
+/*     us = 1/2 - |U|, k = floor((2a/us + b) U + lambda + 0.43); accept at  */
+/*     once if us >= 0.07 and v <= v_r; reject if k < 0 or (us < 0.013 and */
+/*     v > us); otherwise accept iff                                       */
+/*       ln v + ln(inv_alpha) - ln(a/us^2 + b)                               */
+/*         <= -lambda + k ln(lambda) - ln Gamma(k + 1),                      */
+/*     with b = 0.931 + 2.53 sqrt(lambda), a = -0.059 + 0.02483 b,           */
+/*     inv_alpha = 1.1239 + 1.1328/(b - 3.4), v_r = 0.9277 - 3.6224/(b - 2). */
+/*   lambda outside [0, 2^30] (or NaN): result -1, nothing consumed.        */
+/*                                                                          */
+/* Consumption order (the slots of a unit share the U pool, in rounds):     */
+/* in each round one uniform to every slot still pending (ascending), then  */
+/* one more to every pending slot with lambda >= 10 (ascending); a slot     */
+/* with lambda < 10 is pending only in round 0.                             */
+/*                                                                          */
+/* margin: the smallest |decision value| / its tolerance over the draw's    */
+/* decisions whose operands are not exact (u against F(k); the floor; v     */
+/* against v_r; the final test); <= 1 means a double-precision              */
+/* implementation with other elementary functions may decide otherwise.    */
+/* ------------------------------------------------------------------------ */
+
+#define OR_POIS_SMALL 10.0
+#define OR_POIS_MAX 0x1p30
+
+static int pois_valid(double lam) { return lam >= 0.0 && lam <= OR_POIS_MAX; }
+
+/* inversion with the uniform u; *margin receives the decisions' margin */
+static int32_t pois_invert(double lam, double u, double *margin)
+{
+    double p = exp(-lam), F = p, m = INFINITY;
+    int32_t k = 0;
+    for (;;) {
+        double t = 0x1p-46 * (double)(k + 1);
+        double mk = fabs(u - F) / t;
+        if (mk < m) m = mk;
+        if (u <= F || k >= 1000)
+            break;
+        k += 1;
+        p = p * lam / (double)k;
+        F = F + p;
+    }
+    *margin = m;
+    return k;
+}
+
+typedef struct {
+    double lam, slam, loglam, a, b, invalpha, vr;
+} ptrs_t;
+
+static void ptrs_setup(ptrs_t *P, double lam)
+{
+    P->lam = lam;
+    P->slam = sqrt(lam);
+    P->loglam = log(lam);
+    P->b = 0.931 + 2.53 * P->slam;
+    P->a = -0.059 + 0.02483 * P->b;
+    P->invalpha = 1.1239 + 1.1328 / (P->b - 3.4);
+    P->vr = 0.9277 - 3.6224 / (P->b - 2.0);
+}
+
+/* one attempt: 1 = accept with *k, 0 = reject; *margin is lowered */
+static int ptrs_attempt(const ptrs_t *P, double u, double v, int32_t *k, double *margin)
+{
+    double U = u - 0.5;
+    double us = 0.5 - fabs(U);
+    double slope = 2.0 * P->a / us + P->b;
+    double x = slope * U + P->lam + 0.43;
+    double fl = floor(x);
+    double d = fmin(x - fl, fl + 1.0 - x);
+    double tx = 0x1p-46 * (fabs(slope * U) + P->lam + 1.0);
+    if (d / tx < *margin) *margin = d / tx;
+    double kk = fl;
+    if (us >= 0.07) {
+        double mv = fabs(v - P->vr) / 0x1p-48;
+        if (mv < *margin) *margin = mv;
+        if (v <= P->vr) {
+            *k = (int32_t)kk;
+            return 1;
+        }
+    }
+    if (kk < 0.0 || (us < 0.013 && v > us))
+        return 0;
+    double q = P->a / (us * us) + P->b;
+    double lhs = log(v) + log(P->invalpha) - log(q);
+    double lg = lgamma(kk + 1.0);
+    double rhs = -P->lam + kk * P->loglam - lg;
+    double t = 0x1p-44 * (fabs(log(v)) + fabs(log(P->invalpha)) + fabs(log(q)) + P->lam +
+                          fabs(kk * P->loglam) + fabs(lg) + 1.0);
+    double mt = fabs(lhs - rhs) / t;
+    if (mt < *margin) *margin = mt;
+    if (lhs <= rhs) {
+        *k = (int32_t)kk;
+        return 1;
+    }
+    return 0;
+}
+
+void or_step_poisson(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, uint64_t *cursors,
+                     const double *lambda, int32_t *out, double *margin)
+{
+    if (width == 0 || width > OR_MAXSLOT)
+        return;
+    uint32_t nu = (n + width - 1) / width;
+    uint8_t pend[OR_MAXSLOT];
+    double u1[OR_MAXSLOT];
+    ptrs_t P[OR_MAXSLOT];
+    for (uint32_t un = 0; un < nu; un++) {
+        stream_t s = {seed, unit0 + un, cursors + 4 * (size_t)un};
+        uint32_t lo, hi;
+        unit_range(n, width, un, &lo, &hi);
+        int ns = (int)(hi - lo), any = 0;
+        for (int k = 0; k < ns; k++) {
+            double lam = lambda[lo + k];
+            pend[k] = (uint8_t)pois_valid(lam);
+            out[lo + k] = -1;
+            if (margin) margin[lo + k] = INFINITY;
+            if (pend[k] && lam >= OR_POIS_SMALL)
+                ptrs_setup(&P[k], lam);
+            any |= pend[k];
+        }
+        for (int round = 0; any && round < 1 << 20; round++) {
+            for (int k = 0; k < ns; k++)
+                if (pend[k])
+                    u1[k] = take(&s, OR_U);
+            for (int k = 0; k < ns; k++) {
+                if (!pend[k])
+                    continue;
+                double lam = lambda[lo + k];
+                double m = margin ? margin[lo + k] : INFINITY;
+                if (lam < OR_POIS_SMALL) {
+                    double mi;
+                    out[lo + k] = pois_invert(lam, u1[k], &mi);
+                    if (mi < m) m = mi;
+                    pend[k] = 0;
+                } else {
+                    double v = take(&s, OR_U);
+                    int32_t kk;
+                    if (ptrs_attempt(&P[k], u1[k], v, &kk, &m)) {
+                        out[lo + k] = kk;
+                        pend[k] = 0;
+                    }
+                }
+                if (margin) margin[lo + k] = m;
+            }
+            any = 0;
+            for (int k = 0; k < ns; k++)
+                any |= pend[k];
+        }
+    }
+}
+
+
 void or_step_dirichlet(uint64_t seed, uint32_t unit0, uint32_t n_items, uint64_t *cursors,
                        const int32_t *offsets, const double *alpha, double *out,
                        double *tol, double *margin)
