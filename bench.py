@@ -352,6 +352,12 @@ def per_distribution(torch, b, args, n=1 << 20, calls=20):
         res["laplace"] = {"one_at_a_time": timed(lambda: b.brng_step_laplace(ctx, t["mu"], t["sigma"], out), n)}
         res["weibull"] = {"one_at_a_time": timed(lambda: b.brng_step_weibull(ctx, t["lam"], shape, out), n)}
         res["gamma"] = {"one_at_a_time": timed(lambda: b.brng_step_gamma(ctx, t["alpha"], out), n)}
+        # Poisson rates log-uniform in [0.1, 1000]: both the inversion and
+        # the transformed-rejection path
+        rate = torch.from_numpy(np.exp(np.random.default_rng(2).uniform(
+            np.log(0.1), np.log(1000.0), n)).astype(np.float32)).to(dev)
+        kout = torch.empty(n, dtype=torch.int32, device=dev)
+        res["poisson"] = {"one_at_a_time": timed(lambda: b.brng_step_poisson(ctx, rate, kout), n)}
     finally:
         b.brng_destroy(ctx)
     return {"chains": n, "calls": calls, "window": W, "unit": "deviates/s",

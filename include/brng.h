@@ -123,6 +123,19 @@ brng_status brng_step_gamma(brng_ctx *ctx, const float *d_alpha, float *d_out);
 brng_status brng_step_laplace(brng_ctx *ctx, const float *d_mu, const float *d_b, float *d_out);
 brng_status brng_step_weibull(brng_ctx *ctx, const float *d_lambda, const float *d_k, float *d_out);
 
+/* Poisson, a discrete getter (the expanded library of Sec. 3's future work):
+ * one draw per chain from the uniform pool, computed in double precision;
+ * d_lambda holds n_chains rates (float), d_out n_chains int32 counts.
+ *   lambda < 10 : inversion, k = min{k : u <= F(k)}, one uniform;
+ *   lambda >= 10: Hormann's transformed rejection with squeeze (PTRS), two
+ *                 uniforms per attempt.
+ * A unit's lanes take uniforms in rounds: one to every pending lane (lane
+ * order), then one more to every pending lane with lambda >= 10.  lambda
+ * outside [0, 2^30] (or NaN) gives -1 and takes nothing.  Layout CHAINS,
+ * precision F32, U pool enabled.
+ * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_UNSUPPORTED, BRNG_E_HIP. */
+brng_status brng_step_poisson(brng_ctx *ctx, const float *d_lambda, int32_t *d_out);
+
 /* Dirichlet by normalised gammas (Sec. 1, footnote on Dirichlet): layout
  * ITEMS, item i has components [d_offsets[i], d_offsets[i+1]) of d_alpha and
  * d_out (F32).  Components are drawn in batches of 64, one gamma call per

@@ -28,7 +28,7 @@ WINDOW_MIN = 512
 
 EXPORTS = [
     "brng_create", "brng_destroy", "brng_fill_base", "brng_step_uniform", "brng_step_normal",
-    "brng_step_exp", "brng_step_gamma", "brng_step_laplace", "brng_step_weibull",
+    "brng_step_exp", "brng_step_gamma", "brng_step_laplace", "brng_step_weibull", "brng_step_poisson",
     "brng_step_dirichlet", "brng_run_gibbs",
     "brng_sort_by_length", "brng_get_cursors", "brng_set_cursors", "brng_get_window",
     "brng_get_info", "brng_set_launch", "brng_status_string", "brng_last_hip_error",
@@ -138,6 +138,7 @@ def _load():
     L.brng_step_gamma.argtypes = [vp, vp, vp]
     L.brng_step_laplace.argtypes = [vp, vp, vp, vp]
     L.brng_step_weibull.argtypes = [vp, vp, vp, vp]
+    L.brng_step_poisson.argtypes = [vp, vp, vp]
     L.brng_step_dirichlet.argtypes = [vp, vp, vp, vp]
     L.brng_run_gibbs.argtypes = [vp, C.POINTER(brng_gibbs_desc), C.c_uint32]
     L.brng_sort_by_length.argtypes = [C.c_uint32, vp, vp]
@@ -250,6 +251,10 @@ def brng_step_laplace(ctx, mu, b, out) -> None:
 
 def brng_step_weibull(ctx, lam, k, out) -> None:
     _check(_lib.brng_step_weibull(ctx, _ptr(lam), _ptr(k), _ptr(out)), "brng_step_weibull")
+
+
+def brng_step_poisson(ctx, lam, out) -> None:
+    _check(_lib.brng_step_poisson(ctx, _ptr(lam), _ptr(out)), "brng_step_poisson")
 
 
 def brng_step_dirichlet(ctx, offsets, alpha, out) -> None:

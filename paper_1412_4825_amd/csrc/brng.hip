@@ -182,6 +182,91 @@ __global__ __launch_bounds__(512) void k_step_weibull(Meta* meta, float* pool, u
     r.close(meta[unit]);
 }
 
+// Poisson (a discrete getter: the expanded library of Sec. 3's future
+// work), in double precision on the uniform pool.  lambda < 10: inversion
+// with one uniform, k = min{k : u <= F(k)} with F accumulated from
+// p_0 = exp(-lambda), p_k = p_{k-1} lambda / k.  lambda >= 10: Hormann's
+// transformed rejection with squeeze (PTRS, 1993), two uniforms per attempt.
+// Lanes take uniforms in rounds: one to every pending lane (lane order), then
+// one more to every pending lane with lambda >= 10; a lane with lambda < 10
+// is pending only in the first round.  lambda outside [0, 2^30] gives -1 and
+// takes nothing.
+struct Ptrs {
+    double lam, loglam, a, b, invalpha, vr;
+    __device__ __forceinline__ void setup(double l) {
+        lam = l;
+        loglam = log(l);
+        b = 0.931 + 2.53 * sqrt(l);
+        a = -0.059 + 0.02483 * b;
+        invalpha = 1.1239 + 1.1328 / (b - 3.4);
+        vr = 0.9277 - 3.6224 / (b - 2.0);
+    }
+    // one attempt with uniforms u, v: true and *k when accepted
+    __device__ __forceinline__ bool attempt(double u, double v, int32_t* k) const {
+        const double U = u - 0.5;
+        const double us = 0.5 - fabs(U);
+        const double kk = floor((2.0 * a / us + b) * U + lam + 0.43);
+        if (us >= 0.07 && v <= vr) {
+            *k = (int32_t)kk;
+            return true;
+        }
+        if (kk < 0.0 || (us < 0.013 && v > us)) return false;
+        const double lhs = log(v) + log(invalpha) - log(a / (us * us) + b);
+        if (lhs <= -lam + kk * loglam - lgamma(kk + 1.0)) {
+            *k = (int32_t)kk;
+            return true;
+        }
+        return false;
+    }
+};
+
+__device__ __forceinline__ int32_t poisson_invert(double lam, double u) {
+    double p = exp(-lam), F = p;
+    int32_t k = 0;
+    while (u > F && k < 1000) {
+        k += 1;
+        p = p * lam / (double)k;
+        F = F + p;
+    }
+    return k;
+}
+
+__global__ __launch_bounds__(512) void k_step_poisson(Meta* meta, float* pool, uint32_t W,
+                                                      uint32_t n, const float* lam_in,
+                                                      int32_t* out) {
+    const uint32_t unit = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (unit * 64 >= n) return;
+    const uint32_t c = unit * 64 + lane_id();
+    const bool act = c < n;
+    DirectReader<KIND_U> r;
+    r.open(meta[unit], pool + (size_t)unit * W, W);
+    const double lam = act ? (double)lam_in[c] : -1.0;
+    const bool valid = lam >= 0.0 && lam <= 0x1p30;  // false for NaN
+    const bool large = valid && lam >= 10.0;
+    Ptrs P;
+    if (large) P.setup(lam);
+    int32_t k = -1;
+    bool pend = valid;
+    for (uint32_t round = 0; round < (1u << 20); ++round) {
+        if (wave_ballot(pend) == 0) break;
+        const double u = (double)r.take(pend);
+        const bool need_v = pend && large;
+        const double v = (double)r.take(need_v);
+        if (pend && !large) {
+            k = poisson_invert(lam, u);
+            pend = false;
+        } else if (need_v) {
+            int32_t kk;
+            if (P.attempt(u, v, &kk)) {
+                k = kk;
+                pend = false;
+            }
+        }
+    }
+    if (act) out[c] = k;
+    r.close(meta[unit]);
+}
+
 __global__ __launch_bounds__(512) void k_step_gamma(Meta* meta, Pools P, uint32_t n,
                                                     const float* alpha, float* out) {
     const uint32_t unit = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
@@ -592,6 +677,18 @@ brng_status brng_step_weibull(brng_ctx* c, const float* lam, const float* k, flo
     hipLaunchKernelGGL(k_step_weibull, unit_grid(c, c->n_units), dim3(64 * c->wpb), 0, c->stream,
                        c->meta, (float*)c->pool[BRNG_E], c->cfg.window[BRNG_E], c->cfg.n_chains,
                        lam, k, out);
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
+brng_status brng_step_poisson(brng_ctx* c, const float* lam, int32_t* out) {
+    if (!c || !lam || !out) return BRNG_E_ARG;
+    if (c->cfg.layout != BRNG_LAYOUT_CHAINS) return BRNG_E_ARG;
+    if (c->cfg.prec != BRNG_F32) return BRNG_E_UNSUPPORTED;
+    if (!c->cfg.window[BRNG_U]) return BRNG_E_KIND_DISABLED;
+    hipLaunchKernelGGL(k_step_poisson, unit_grid(c, c->n_units), dim3(64 * c->wpb), 0, c->stream,
+                       c->meta, (float*)c->pool[BRNG_U], c->cfg.window[BRNG_U], c->cfg.n_chains,
+                       lam, out);
     HIPCHK(hipGetLastError());
     return BRNG_OK;
 }

@@ -152,6 +152,46 @@ def test_step_uniform_fp64(dev):
         b.brng_destroy(ctx)
 
 
+def test_step_poisson(dev):
+    """Poisson steps (inversion below 10, PTRS above) with per-chain rates
+    spanning 1e-3..1e5 and the edge values (0, the switch at 10, invalid
+    rates, 2^30); five calls through 512-entry windows; counts bit-exact,
+    cursors bit-exact, flips only where the oracle's margin allows."""
+    import torch
+    b = _b()
+    n, seed = 1000 + 17, 61
+    rng = np.random.default_rng(8)
+    lam = np.exp(rng.uniform(np.log(1e-3), np.log(1e5), n)).astype(np.float32)
+    lam[:9] = [0.0, 9.999, 10.0, -1.0, np.nan, np.inf, 2.0 ** 30, 2.0 ** 31, 1e-30]
+    _say("step_poisson", n, seed)
+    ctx = _ctx(seed, n, W_SMALL)
+    cur = oracle.new_cursors((n + 63) // 64)
+    out = torch.zeros(n, dtype=torch.int32, device=dev)
+    units = np.arange(n) // 64
+    flipped = set()
+    try:
+        tl = _t(lam, dev)
+        for it in range(5):
+            b.brng_step_poisson(ctx, tl, out)
+            k, margin = oracle.step_poisson(seed, cur, lam.astype(np.float64))
+            g = _np(out)
+            for u in np.unique(units[g != k]):
+                if u in flipped:
+                    continue
+                sl = units == u
+                assert margin[sl].min() <= 1.0, (it, u, g[sl], k[sl])
+                flipped.add(int(u))
+            ok = np.array([u not in flipped for u in units])
+            assert np.array_equal(g[ok], k[ok])
+        assert list(g[3:6]) == [-1, -1, -1] and g[7] == -1
+        got = b.brng_get_cursors(ctx)
+        keep = np.array([u not in flipped for u in range(got.shape[0])])
+        assert np.array_equal(got[keep], cur[keep])
+        assert len(flipped) <= 1
+    finally:
+        b.brng_destroy(ctx)
+
+
 def test_step_dirichlet_ragged(dev):
     b = _b()
     it = workloads.dirichlet_items(150, kmin=1, kmax=300, seed=3)
