@@ -422,7 +422,17 @@ def served_section(torch, args, n_req):
     deviates = sum(r.deviates for r in reqs)
     for r in reqs:
         r.reset()
-    service = serve.run_plain(torch, reqs, W)
+
+    def say(*a):
+        print("[served]", *a, file=sys.stderr, flush=True)
+
+    # plain launches in chunks of 100 requests (one context per chunk), with
+    # a progress line per chunk
+    service = []
+    for i in range(0, n_req, 100):
+        service.append(serve.run_plain(torch, reqs[i:i + 100], W))
+        say("plain", min(i + 100, n_req), "of", n_req)
+    service = np.concatenate(service)
     k = min(500, n_req)
     mu_p = k / service[:k].sum()
     rate = 0.7 * mu_p
@@ -430,6 +440,7 @@ def served_section(torch, args, n_req):
     lat_plain = serve.fifo_latency(arrivals, service)
     kw = dict(budget=args.served_budget_mb << 20, window=W, max_active=args.served_slots,
               tick_steps=args.served_tick_steps, tick_sweeps=args.served_tick_sweeps)
+    kw["on_done"] = lambda d: say("served", d, "of", n_req) if d % 100 == 0 else None
     for r in reqs:
         r.reset()
     _, makespan, st_sat = serve.run_served(torch, reqs, np.zeros(n_req), **kw)

@@ -82,10 +82,11 @@ def run_plain(torch, reqs, window, stream=None):
 
 
 def run_served(torch, reqs, arrivals_s, *, budget, window, max_active=64, tick_steps=256,
-               tick_sweeps=4, stream=None):
+               tick_sweeps=4, stream=None, on_done=None):
     """Serve `reqs`, request i arriving arrivals_s[i] seconds after the start
     (all at 0 for a saturated run).  Returns (latency_s per request, makespan
-    seconds from the first arrival to the last completion, server stats)."""
+    seconds from the first arrival to the last completion, server stats).
+    on_done(count), if given, is called after each completed request."""
     srv = b.brng_serve_open(budget, window, max_active=max_active, tick_steps=tick_steps,
                             tick_sweeps=tick_sweeps,
                             stream=stream or torch.cuda.current_stream())
@@ -110,6 +111,8 @@ def run_served(torch, reqs, arrivals_s, *, budget, window, max_active=64, tick_s
                 lat[k] = (d["t_done_ns"] - d["t_arrive_ns"]) / 1e9
                 t_last = max(t_last, d["t_done_ns"])
                 done += 1
+                if on_done is not None:
+                    on_done(done)
         stats = b.brng_serve_stats_get(srv)
     finally:
         b.brng_serve_close(srv)
