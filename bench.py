@@ -166,7 +166,9 @@ def setup_normexp(torch, b, args):
                 "sample": "whole workload (%d chains x %d steps, %.3g deviates) split by unit "
                           "over %d processes; %.1f s of CPU work" % (n, steps, dv, len(jobs), busy)}
 
-    return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_N, b.BRNG_E],
+    # `keep` holds the device arrays the descriptors point to for as long as
+    # the descriptors are used
+    return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_N, b.BRNG_E], keep=(st, ts, te),
                 entry_bytes={b.BRNG_N: 4, b.BRNG_E: 4}, windows={b.BRNG_N: W, b.BRNG_E: W},
                 deviates=2 * n * steps, out_bytes=2 * n * steps * 4, dtype="f32", cpu=cpu,
                 kernel="k_gibbs<NORMEXP>",
@@ -196,7 +198,7 @@ def setup_triangle(torch, b, args):
                 "sample": "whole workload (%d chains x %d iterations) split by unit over %d "
                           "processes; %.1f s of CPU work" % (n, iters, len(jobs), busy)}
 
-    return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_U64],
+    return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_U64], keep=(st, tx, ty),
                 entry_bytes={b.BRNG_U64: 8}, windows={b.BRNG_U64: W},
                 deviates=2 * n * iters, out_bytes=2 * n * iters * 8, dtype="f64", cpu=cpu,
                 kernel="k_gibbs<TRIANGLE>",
@@ -259,6 +261,7 @@ def setup_gamma(torch, b, args):
                         "on the stream between launches" % n}
 
     return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_N, b.BRNG_E],
+                keep=(st, tg, tsteps, tperm),
                 entry_bytes={b.BRNG_N: 4, b.BRNG_E: 4}, windows={b.BRNG_N: W, b.BRNG_E: W},
                 deviates=draws, out_bytes=draws * 4, dtype="f32", cpu=cpu, oaat=oaat,
                 kernel="k_gibbs<GAMMA_CHAIN>",
@@ -284,8 +287,11 @@ def setup_lda(torch, b, args):
     ct = torch.empty((sweeps, total), dtype=torch.int32, device=dev)
     toff = torch.from_numpy(wl["offsets"]).to(dev)
     tntok = torch.from_numpy(wl["ntok"]).to(dev)
+    # waves take documents by decreasing work (results do not depend on it)
+    from paper_1412_4825_amd import order
+    tperm = torch.from_numpy(order.doc_order(wl["offsets"], wl["ntok"])).to(dev)
     kw = dict(max_steps=sweeps, seed=args.seed, trace=th, trace2=ct, trace_stride=total,
-              offsets=toff, ntok=tntok)
+              offsets=toff, ntok=tntok, perm=tperm)
     fresh = b.gibbs_desc(b.BRNG_MODEL_LDA, nd, counts, **kw)
     resume = b.gibbs_desc(b.BRNG_MODEL_LDA, nd, counts, flags=b.BRNG_FLAG_RESUME, **kw)
     dv = sweeps * (total + int(wl["ntok"].sum()))
@@ -303,6 +309,7 @@ def setup_lda(torch, b, args):
                           "%.1f s of CPU work" % (sd, nd, sweeps, sdv, len(jobs), busy)}
 
     return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_U, b.BRNG_N, b.BRNG_E],
+                keep=(counts, th, ct, toff, tntok, tperm),
                 entry_bytes={b.BRNG_U: 4, b.BRNG_N: 4, b.BRNG_E: 4},
                 windows={b.BRNG_U: W, b.BRNG_N: W, b.BRNG_E: W},
                 deviates=dv, out_bytes=sweeps * total * 8, dtype="f32", cpu=cpu,

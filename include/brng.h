@@ -172,8 +172,11 @@ typedef struct {
     int32_t max_steps;     /* steps (sweeps for LDA) when d_steps is NULL */
     int32_t pad0;
     const int32_t *d_steps; /* per-chain steps (user order) or NULL */
-    const int32_t *d_perm;  /* slot -> chain, or NULL for identity; see
-                               brng_sort_by_length */
+    const int32_t *d_perm;  /* chains: slot -> chain, or NULL for identity
+                               (see brng_sort_by_length); LDA: wave order of
+                               the documents (wave i runs document
+                               d_perm[i]; a permutation of 0..n_docs-1), or
+                               NULL; results do not depend on it */
     void *d_state;          /* model state, user order, in/out:
                                TRIANGLE: double[2][n] (x then y)
                                NORMEXP : float[n] (s)

@@ -344,6 +344,16 @@ __host__ __device__ constexpr int model_lds_bytes(int model) {
                                  : RING_BYTES;
 }
 
+// LDA waves take documents in the order of D.perm when it is given (a
+// permutation of the documents, e.g. by decreasing work so that the longest
+// ones start first and the launch has no long tail); each document is its
+// own unit, so the order changes no result.  Returns false for an entry
+// outside the request.
+__device__ __forceinline__ bool lda_doc_of(const DescDev& D, uint32_t local, uint32_t* doc) {
+    *doc = D.perm ? (uint32_t)D.perm[local] : local;
+    return *doc < D.n_units;
+}
+
 // Documents the LDA kernel cannot serve are skipped: K outside [1, 256],
 // negative token counts, or traces too narrow for their components.
 __device__ __forceinline__ bool lda_doc_ok(const DescDev& D, uint32_t doc) {
@@ -358,9 +368,9 @@ template <int MODEL>
 __global__ __launch_bounds__(512) void k_gibbs(DescDev D, Meta* meta, Pools P) {
     extern __shared__ __align__(16) unsigned char lds_all[];
     const uint32_t w = wave_in_block();
-    const uint32_t local = blockIdx.x * (blockDim.x >> 6) + w;
+    uint32_t local = blockIdx.x * (blockDim.x >> 6) + w;
     if (local >= D.n_units) return;
-    if (MODEL == M_LDA && !lda_doc_ok(D, local)) return;
+    if (MODEL == M_LDA && !(lda_doc_of(D, local, &local) && lda_doc_ok(D, local))) return;
     run_unit<MODEL>(D, meta, P, local, lds_all + w * model_lds_bytes(MODEL));
 }
 
@@ -385,8 +395,8 @@ __global__ __launch_bounds__(512) void k_multi(const SlotTable T) {
     const DescDev D = T.s[lo].D;
     const Pools P = T.s[lo].P;
     Meta* meta = T.s[lo].meta;
-    const uint32_t local = g - first;
-    if (MODEL == M_LDA && !lda_doc_ok(D, local)) return;
+    uint32_t local = g - first;
+    if (MODEL == M_LDA && !(lda_doc_of(D, local, &local) && lda_doc_ok(D, local))) return;
     run_unit<MODEL>(D, meta, P, local, lds_all + w * model_lds_bytes(MODEL));
 }
 

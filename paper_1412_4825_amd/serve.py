@@ -48,7 +48,10 @@ class Request:
             self.deviates = (int(off[-1]) + int(ntok.sum())) * s
         kw = {}
         if self.model == b.BRNG_MODEL_LDA:
-            kw = dict(offsets=self.offsets, ntok=self.ntok)
+            # documents by decreasing work (no effect on results)
+            from . import order
+            self.perm = torch.from_numpy(order.doc_order(q["offsets"], q["ntok"])).to(dev)
+            kw = dict(offsets=self.offsets, ntok=self.ntok, perm=self.perm)
         self.desc = b.gibbs_desc(self.model, n, self.state, max_steps=s, seed=q["seed"], **kw)
         self.units = n if self.model == b.BRNG_MODEL_LDA else (n + 63) // 64
 

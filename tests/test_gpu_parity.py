@@ -389,6 +389,40 @@ def test_lda(dev):
         b.brng_destroy(ctx)
 
 
+def test_lda_document_order_invariance(dev):
+    """Waves taking documents in another order (the work order the bench
+    uses, and a random one) give the same counts, traces and cursors bit for
+    bit: each document is its own unit."""
+    import torch
+    from paper_1412_4825_amd import order
+    b = _b()
+    w = workloads.lda(n_docs=300, sweeps=6, seed=12)
+    seed = 77
+    nd, total, sw = w["n_docs"], int(w["offsets"][-1]), w["sweeps"]
+    perms = [None, order.doc_order(w["offsets"], w["ntok"]),
+             np.random.default_rng(4).permutation(nd).astype(np.int32)]
+    _say("lda order", nd, sw, seed)
+    res = []
+    for perm in perms:
+        ctx = _ctx(seed, nd, W_SMALL, layout=1)
+        counts = torch.zeros(total, dtype=torch.int32, device=dev)
+        th = torch.zeros((sw, total), dtype=torch.float32, device=dev)
+        ct = torch.zeros((sw, total), dtype=torch.int32, device=dev)
+        tp = None if perm is None else _t(perm, dev)
+        try:
+            b.brng_set_launch(ctx, 2)
+            b.brng_run_gibbs(ctx, b.gibbs_desc(b.BRNG_MODEL_LDA, nd, counts, max_steps=sw,
+                                               seed=seed, trace=th, trace2=ct, trace_stride=total,
+                                               offsets=_t(w["offsets"], dev),
+                                               ntok=_t(w["ntok"], dev), perm=tp))
+            res.append((_np(counts), _np(th), _np(ct), b.brng_get_cursors(ctx)))
+        finally:
+            b.brng_destroy(ctx)
+    for r in res[1:]:
+        for x, y in zip(r, res[0]):
+            assert np.array_equal(x, y)
+
+
 def test_window_length_invariance(dev):
     """Window length is a speed knob only (Sec. 2.4): bitwise equal results."""
     w = workloads.gamma_chain(n_chains=1024 + 5, lmin=10, lmax=80, seed=9)
