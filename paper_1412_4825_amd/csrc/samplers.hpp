@@ -122,18 +122,8 @@ __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t 
     // of a loaded value inside the loop makes the compiler wait for all
     // memory operations in flight at that point of every round.
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-    for (uint32_t round = 0;; ++round) {
-        const uint64_t mh = wave_ballot(src.holding());
-        if (mh == 0) break;
-        if ((round & (EPOCH - 1)) == 0) {
-            if (round >= max_rounds) break;
-            if constexpr (COVERED) {
-                rn.sync_avail();
-                re.sync_avail();
-            }
-            epoch_point(rn, re);
-            src.flush();
-        }
+    // One round for the lanes of mask mh (those holding a draw).
+    auto one_round = [&](const uint64_t mh) {
         // shapes outside (0, 2^64) have no draw; below 1 the boost applies
         const uint64_t mv = wave_ballot(al > 0.0f) & wave_ballot(al < 0x1p64f);
         const uint64_t mboost = mv & wave_ballot(al < 1.0f);
@@ -191,6 +181,30 @@ __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t 
         }
         g = lane_in(mv) ? g : __builtin_nanf("");
         al = src.complete(mh & (macc | ~mv), g, al);
+    };
+    // Epochs of EPOCH rounds, the rounds of an epoch unrolled.
+    bool live = true;
+    for (uint32_t round = 0; live; round += EPOCH) {
+        uint64_t mh = wave_ballot(src.holding());
+        if (mh == 0 || round >= max_rounds) break;
+        if constexpr (COVERED) {
+            rn.sync_avail();
+            re.sync_avail();
+        }
+        epoch_point(rn, re);
+        src.flush();
+        static_for<0, (int)EPOCH>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if (!live) return;
+            if (i > 0) {
+                mh = wave_ballot(src.holding());
+                if (mh == 0) {
+                    live = false;
+                    return;
+                }
+            }
+            one_round(mh);
+        });
     }
     if constexpr (COVERED) {
         rn.sync_avail();
