@@ -83,6 +83,8 @@ def _declare(L):
                                   _dp, _dp]
     L.or_step_gamma.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _dp, _dp, _dp, _i32p, _i32p]
     L.or_step_poisson.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _i32p, _dp]
+    L.or_step_binomial.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _i32p, _dp, _i32p,
+                                   _dp]
     L.or_step_dirichlet.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _u64p, _i32p, _dp, _dp, _dp, _dp]
     L.or_multinomial.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _u64p, _i32p, _i32p, _dp, _i32p]
     L.or_triangle.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _dp, _dp, _u64p, _dp, _dp, _dp, _dp]
@@ -223,6 +225,21 @@ def step_poisson(seed, cursors, lam, width=UNIT_WIDTH, unit0=0):
     mar = np.zeros(n)
     lib().or_step_poisson(seed, unit0, n, width, _p(cursors, _u64p), _p(lam, _dp), _p(out, _i32p),
                           _p(mar, _dp))
+    return out, mar
+
+
+def step_binomial(seed, cursors, n, p, width=UNIT_WIDTH, unit0=0):
+    """Binomial(n, p) per chain (double precision; U pool): with p' =
+    min(p, 1 - p), inversion when n p' < 10, Hormann's BTRD otherwise,
+    mirrored for p > 1/2; -1 for n < 0 or p outside [0, 1].  Returns (k as
+    int32, decision margin)."""
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    p = _d(p)
+    m = n.size
+    out = np.zeros(m, dtype=np.int32)
+    mar = np.zeros(m)
+    lib().or_step_binomial(seed, unit0, m, width, _p(cursors, _u64p), _p(n, _i32p), _p(p, _dp),
+                           _p(out, _i32p), _p(mar, _dp))
     return out, mar
 
 

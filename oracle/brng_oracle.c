@@ -794,6 +794,211 @@ void or_step_poisson(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, 
 }
 
 
+/* ------------------------------------------------------------------------ */
+/* Binomial(n, p): the second discrete getter (Sec. 3's future work).       */
+/* Double precision; the U pool only.  With p' = min(p, 1 - p) the draw is  */
+/* made for p' and mirrored (n - k) when p > 1/2.                           */
+/*                                                                          */
+/*   n p' < 10: inversion with one uniform, k = min{k : u <= F(k)}, F       */
+/*     accumulated from P_0 = exp(n ln(1 - p')),                            */
+/*     P_k = P_{k-1} (n - k + 1) / k * (p'/(1 - p')), k <= n.               */
+/*   n p' >= 10: transformed rejection with decomposition (Hormann 1993,    */
+/*     "BTRD").  Setup: m = floor((n + 1) p'), spq = sqrt(n p' q'),         */
+/*     b = 1.15 + 2.53 spq, a = -0.0873 + 0.0248 b + 0.01 p',               */
+/*     c = n p' + 0.5, alpha = (2.83 + 5.1/b) spq, v_r = 0.92 - 4.2/b,      */
+/*     u_r v_r = 0.86 v_r.  An attempt takes a first uniform v:             */
+/*       v <= u_r v_r: U = v/v_r - 0.43, k = floor((2a/(1/2 - |U|) + b) U   */
+/*         + c), accepted at once (if 0 <= k <= n);                         */
+/*       otherwise a second uniform w: if v >= v_r, U = w - 1/2 and V = v;  */
+/*         else U = v/v_r - 0.93, U = sign(U)/2 - U, V = w v_r;             */
+/*         us = 1/2 - |U|, k = floor((2a/us + b) U + c), rejected unless    */
+/*         0 <= k <= n, and accepted iff                                    */
+/*           ln(V alpha / (a/us^2 + b)) <= ln P(k) - ln P(m)                */
+/*         (the method's exact test, evaluated with ln Gamma).              */
+/*   n < 0, p outside [0, 1] or NaN: result -1, nothing consumed.           */
+/*                                                                          */
+/* Consumption order, in rounds over a unit's slots: one uniform to every   */
+/* pending slot (ascending), then one more to every pending slot on the     */
+/* rejection path whose first uniform was above u_r v_r (ascending); an     */
+/* inversion slot is pending only in round 0.                               */
+/* margin: as for Poisson, over the decisions with inexact operands.        */
+/* ------------------------------------------------------------------------ */
+
+static int32_t binom_invert(int32_t n, double pp, double u, double *margin)
+{
+    double q = 1.0 - pp, s = pp / q;
+    double P = exp((double)n * log1p(-pp)), F = P, mm = INFINITY;
+    int32_t k = 0;
+    for (;;) {
+        double mk = fabs(u - F) / (0x1p-46 * (double)(k + 1));
+        if (mk < mm) mm = mk;
+        if (u <= F || k >= n)
+            break;
+        k += 1;
+        P = P * (double)(n - k + 1) / (double)k * s;
+        F = F + P;
+    }
+    *margin = mm;
+    return k;
+}
+
+typedef struct {
+    double n, p, lp_m, logp, logq, lgn1, a, b, c, alpha, vr, urvr;
+    int32_t ni, m;
+} btrd_t;
+
+static double binom_lp(const btrd_t *B, double k)
+{
+    return B->lgn1 - lgamma(k + 1.0) - lgamma(B->n - k + 1.0) + k * B->logp + (B->n - k) * B->logq;
+}
+
+static void btrd_setup(btrd_t *B, int32_t n, double pp)
+{
+    B->ni = n;
+    B->n = (double)n;
+    B->p = pp;
+    double q = 1.0 - pp;
+    B->m = (int32_t)floor((B->n + 1.0) * pp);
+    double spq = sqrt(B->n * pp * q);
+    B->b = 1.15 + 2.53 * spq;
+    B->a = -0.0873 + 0.0248 * B->b + 0.01 * pp;
+    B->c = B->n * pp + 0.5;
+    B->alpha = (2.83 + 5.1 / B->b) * spq;
+    B->vr = 0.92 - 4.2 / B->b;
+    B->urvr = 0.86 * B->vr;
+    B->logp = log(pp);
+    B->logq = log1p(-pp);
+    B->lgn1 = lgamma(B->n + 1.0);
+    B->lp_m = binom_lp(B, (double)B->m);
+}
+
+static void lower(double *m, double v) { if (v < *m) *m = v; }
+
+/* distance of x to the nearest integer, over its rounding scale */
+static double floor_margin(double x, double scale)
+{
+    double fl = floor(x);
+    return fmin(x - fl, fl + 1.0 - x) / (0x1p-46 * (scale + 1.0));
+}
+
+/* first part of an attempt: 1 = accepted at once with *k, 0 = needs w */
+static int btrd_first(const btrd_t *B, double v, int32_t *k, double *margin)
+{
+    lower(margin, fabs(v - B->urvr) / 0x1p-48);
+    if (v <= B->urvr) {
+        double U = v / B->vr - 0.43;
+        double t = (2.0 * B->a / (0.5 - fabs(U)) + B->b) * U;
+        double x = t + B->c;
+        lower(margin, floor_margin(x, fabs(t) + B->c));
+        double kk = floor(x);
+        if (kk >= 0.0 && kk <= B->n) {
+            *k = (int32_t)kk;
+            return 1;
+        }
+        return -1; /* outside [0, n]: the attempt is rejected */
+    }
+    return 0;
+}
+
+/* second part: 1 = accept with *k, 0 = reject */
+static int btrd_second(const btrd_t *B, double v, double w, int32_t *k, double *margin)
+{
+    double U, V;
+    lower(margin, fabs(v - B->vr) / 0x1p-48);
+    if (v >= B->vr) {
+        U = w - 0.5;
+        V = v;
+    } else {
+        U = v / B->vr - 0.93;
+        U = (U >= 0.0 ? 0.5 : -0.5) - U;
+        V = w * B->vr;
+    }
+    double us = 0.5 - fabs(U);
+    double t = (2.0 * B->a / us + B->b) * U;
+    double x = t + B->c;
+    if (!(x >= 0.0 && x < B->n + 1.0)) /* k < 0 or k > n (also x NaN/inf) */
+        return 0;
+    lower(margin, floor_margin(x, fabs(t) + B->c));
+    double kk = floor(x);
+    double lhs = log(V * B->alpha / (B->a / (us * us) + B->b));
+    double lpk = binom_lp(B, kk);
+    double rhs = lpk - B->lp_m;
+    double tol = 0x1p-44 * (fabs(lhs) + fabs(lpk) + fabs(B->lp_m) + B->lgn1 + 1.0);
+    lower(margin, fabs(lhs - rhs) / tol);
+    if (lhs <= rhs) {
+        *k = (int32_t)kk;
+        return 1;
+    }
+    return 0;
+}
+
+void or_step_binomial(uint64_t seed, uint32_t unit0, uint32_t n_ch, uint32_t width,
+                      uint64_t *cursors, const int32_t *nn, const double *pr, int32_t *out,
+                      double *margin)
+{
+    if (width == 0 || width > OR_MAXSLOT)
+        return;
+    uint32_t nu = (n_ch + width - 1) / width;
+    uint8_t pend[OR_MAXSLOT], flip[OR_MAXSLOT], inv[OR_MAXSLOT];
+    double v1[OR_MAXSLOT], pp[OR_MAXSLOT];
+    btrd_t B[OR_MAXSLOT];
+    for (uint32_t un = 0; un < nu; un++) {
+        stream_t s = {seed, unit0 + un, cursors + 4 * (size_t)un};
+        uint32_t lo, hi;
+        unit_range(n_ch, width, un, &lo, &hi);
+        int ns = (int)(hi - lo), any = 0;
+        for (int k = 0; k < ns; k++) {
+            int32_t n = nn[lo + k];
+            double p = pr[lo + k];
+            out[lo + k] = -1;
+            if (margin) margin[lo + k] = INFINITY;
+            pend[k] = (uint8_t)(n >= 0 && p >= 0.0 && p <= 1.0);
+            if (!pend[k])
+                continue;
+            flip[k] = (uint8_t)(p > 0.5);
+            pp[k] = flip[k] ? 1.0 - p : p;
+            inv[k] = (uint8_t)((double)n * pp[k] < 10.0);
+            if (!inv[k])
+                btrd_setup(&B[k], n, pp[k]);
+            any = 1;
+        }
+        for (int round = 0; any && round < 1 << 20; round++) {
+            for (int k = 0; k < ns; k++)
+                if (pend[k])
+                    v1[k] = take(&s, OR_U);
+            for (int k = 0; k < ns; k++) {
+                if (!pend[k])
+                    continue;
+                double mg = margin ? margin[lo + k] : INFINITY;
+                int32_t kk = 0, done = 0;
+                if (inv[k]) {
+                    double mi;
+                    kk = binom_invert(nn[lo + k], pp[k], v1[k], &mi);
+                    lower(&mg, mi);
+                    done = 1;
+                } else {
+                    int r = btrd_first(&B[k], v1[k], &kk, &mg);
+                    if (r == 1) {
+                        done = 1;
+                    } else if (r == 0) {
+                        double w = take(&s, OR_U);
+                        done = btrd_second(&B[k], v1[k], w, &kk, &mg);
+                    }
+                }
+                if (done) {
+                    out[lo + k] = flip[k] ? nn[lo + k] - kk : kk;
+                    pend[k] = 0;
+                }
+                if (margin) margin[lo + k] = mg;
+            }
+            any = 0;
+            for (int k = 0; k < ns; k++)
+                any |= pend[k];
+        }
+    }
+}
+
+
 void or_step_dirichlet(uint64_t seed, uint32_t unit0, uint32_t n_items, uint64_t *cursors,
                        const int32_t *offsets, const double *alpha, double *out,
                        double *tol, double *margin)
