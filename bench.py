@@ -365,6 +365,11 @@ def per_distribution(torch, b, args, n=1 << 20, calls=20):
             np.log(0.1), np.log(1000.0), n)).astype(np.float32)).to(dev)
         kout = torch.empty(n, dtype=torch.int32, device=dev)
         res["poisson"] = {"one_at_a_time": timed(lambda: b.brng_step_poisson(ctx, rate, kout), n)}
+        # binomial: n log-uniform in [1, 10^4], p uniform: both paths
+        g2 = np.random.default_rng(3)
+        trials = torch.from_numpy(np.floor(np.exp(g2.uniform(0, np.log(1e4), n))).astype(np.int32)).to(dev)
+        prob = torch.from_numpy(g2.uniform(size=n).astype(np.float32)).to(dev)
+        res["binomial"] = {"one_at_a_time": timed(lambda: b.brng_step_binomial(ctx, trials, prob, kout), n)}
     finally:
         b.brng_destroy(ctx)
     return {"chains": n, "calls": calls, "window": W, "unit": "deviates/s",

@@ -136,6 +136,22 @@ brng_status brng_step_weibull(brng_ctx *ctx, const float *d_lambda, const float 
  * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_UNSUPPORTED, BRNG_E_HIP. */
 brng_status brng_step_poisson(brng_ctx *ctx, const float *d_lambda, int32_t *d_out);
 
+/* Binomial(n, p), the second discrete getter: one draw per chain from the
+ * uniform pool, computed in double precision; d_n holds n_chains trial
+ * counts (int32), d_p n_chains probabilities (float), d_out n_chains int32
+ * results.  With p' = min(p, 1 - p) the draw is made for p' and mirrored
+ * (n - k) when p > 1/2:
+ *   n p' < 10 : inversion, k = min{k : u <= F(k)}, one uniform;
+ *   n p' >= 10: Hormann's transformed rejection with decomposition (BTRD):
+ *               an attempt takes one uniform, or two when the first is
+ *               above u_r v_r.
+ * A unit's lanes take uniforms in rounds: one to every pending lane (lane
+ * order), then one more to every pending lane that needs a second.  n < 0
+ * or p outside [0, 1] (or NaN) gives -1 and takes nothing.  Layout CHAINS,
+ * precision F32, U pool enabled.
+ * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_UNSUPPORTED, BRNG_E_HIP. */
+brng_status brng_step_binomial(brng_ctx *ctx, const int32_t *d_n, const float *d_p, int32_t *d_out);
+
 /* Dirichlet by normalised gammas (Sec. 1, footnote on Dirichlet): layout
  * ITEMS, item i has components [d_offsets[i], d_offsets[i+1]) of d_alpha and
  * d_out (F32).  Components are drawn in batches of 64, one gamma call per

@@ -267,6 +267,129 @@ __global__ __launch_bounds__(512) void k_step_poisson(Meta* meta, float* pool, u
     r.close(meta[unit]);
 }
 
+// Binomial (the second discrete getter), double precision on the uniform
+// pool.  With p' = min(p, 1 - p) the draw is made for p' and mirrored
+// (n - k) when p > 1/2.  n p' < 10: inversion with one uniform,
+// k = min{k : u <= F(k)}, F accumulated from P_0 = exp(n ln(1 - p')),
+// P_k = P_{k-1} (n - k + 1) / k * p'/(1 - p').  Otherwise Hormann's
+// transformed rejection with decomposition (BTRD, 1993): an attempt's first
+// uniform v accepts at once below u_r v_r; above, a second uniform is taken
+// and the candidate k is accepted by the exact test ln(V alpha/(a/us^2 + b))
+// <= ln P(k) - ln P(m), evaluated with ln Gamma.  Lanes take uniforms in
+// rounds: one to every pending lane (lane order), then one more to every
+// pending rejection-path lane whose first uniform was above u_r v_r; an
+// inversion lane is pending only in the first round.  n < 0 or p outside
+// [0, 1] gives -1 and takes nothing.
+struct Btrd {
+    double n, m, a, b, c, alpha, vr, urvr, logp, logq, lgn1, lpm;
+    __device__ __forceinline__ double lp(double k) const {
+        return lgn1 - lgamma(k + 1.0) - lgamma(n - k + 1.0) + k * logp + (n - k) * logq;
+    }
+    __device__ __forceinline__ void setup(int32_t ni, double p) {
+        const double q = 1.0 - p;
+        n = (double)ni;
+        m = floor((n + 1.0) * p);
+        const double spq = sqrt(n * p * q);
+        b = 1.15 + 2.53 * spq;
+        a = -0.0873 + 0.0248 * b + 0.01 * p;
+        c = n * p + 0.5;
+        alpha = (2.83 + 5.1 / b) * spq;
+        vr = 0.92 - 4.2 / b;
+        urvr = 0.86 * vr;
+        logp = log(p);
+        logq = log1p(-p);
+        lgn1 = lgamma(n + 1.0);
+        lpm = lp(m);
+    }
+    // first uniform: 1 accepted with *k, -1 rejected, 0 a second is needed
+    __device__ __forceinline__ int first(double v, int32_t* k) const {
+        if (v > urvr) return 0;
+        const double U = v / vr - 0.43;
+        const double kk = floor((2.0 * a / (0.5 - fabs(U)) + b) * U + c);
+        if (kk >= 0.0 && kk <= n) {
+            *k = (int32_t)kk;
+            return 1;
+        }
+        return -1;
+    }
+    __device__ __forceinline__ bool second(double v, double w, int32_t* k) const {
+        double U, V;
+        if (v >= vr) {
+            U = w - 0.5;
+            V = v;
+        } else {
+            U = v / vr - 0.93;
+            U = (U >= 0.0 ? 0.5 : -0.5) - U;
+            V = w * vr;
+        }
+        const double us = 0.5 - fabs(U);
+        const double x = (2.0 * a / us + b) * U + c;
+        if (!(x >= 0.0 && x < n + 1.0)) return false;
+        const double kk = floor(x);
+        if (log(V * alpha / (a / (us * us) + b)) <= lp(kk) - lpm) {
+            *k = (int32_t)kk;
+            return true;
+        }
+        return false;
+    }
+};
+
+__device__ __forceinline__ int32_t binomial_invert(int32_t n, double p, double u) {
+    const double s = p / (1.0 - p);
+    double P = exp((double)n * log1p(-p)), F = P;
+    int32_t k = 0;
+    while (u > F && k < n) {
+        k += 1;
+        P = P * (double)(n - k + 1) / (double)k * s;
+        F = F + P;
+    }
+    return k;
+}
+
+__global__ __launch_bounds__(512) void k_step_binomial(Meta* meta, float* pool, uint32_t W,
+                                                       uint32_t n_ch, const int32_t* n_in,
+                                                       const float* p_in, int32_t* out) {
+    const uint32_t unit = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (unit * 64 >= n_ch) return;
+    const uint32_t c = unit * 64 + lane_id();
+    const bool act = c < n_ch;
+    DirectReader<KIND_U> r;
+    r.open(meta[unit], pool + (size_t)unit * W, W);
+    const int32_t n = act ? n_in[c] : -1;
+    const double p = act ? (double)p_in[c] : 0.0;
+    const bool valid = n >= 0 && p >= 0.0 && p <= 1.0;  // false for NaN
+    const bool flip = p > 0.5;
+    const double pp = flip ? 1.0 - p : p;
+    const bool inv = valid && (double)n * pp < 10.0;
+    Btrd B;
+    if (valid && !inv) B.setup(n, pp);
+    int32_t k = -1;
+    bool pend = valid;
+    for (uint32_t round = 0; round < (1u << 20); ++round) {
+        if (wave_ballot(pend) == 0) break;
+        const double v = (double)r.take(pend);
+        int32_t kk = 0;
+        int st = 0;  // 1 done, -1 attempt rejected, 0 needs a second uniform
+        if (pend) {
+            if (inv) {
+                kk = binomial_invert(n, pp, v);
+                st = 1;
+            } else {
+                st = B.first(v, &kk);
+            }
+        }
+        const bool need_w = pend && st == 0;
+        const double w = (double)r.take(need_w);
+        if (need_w) st = B.second(v, w, &kk) ? 1 : -1;
+        if (pend && st == 1) {
+            k = flip ? n - kk : kk;
+            pend = false;
+        }
+    }
+    if (act) out[c] = k;
+    r.close(meta[unit]);
+}
+
 __global__ __launch_bounds__(512) void k_step_gamma(Meta* meta, Pools P, uint32_t n,
                                                     const float* alpha, float* out) {
     const uint32_t unit = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
@@ -699,6 +822,18 @@ brng_status brng_step_poisson(brng_ctx* c, const float* lam, int32_t* out) {
     hipLaunchKernelGGL(k_step_poisson, unit_grid(c, c->n_units), dim3(64 * c->wpb), 0, c->stream,
                        c->meta, (float*)c->pool[BRNG_U], c->cfg.window[BRNG_U], c->cfg.n_chains,
                        lam, out);
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
+brng_status brng_step_binomial(brng_ctx* c, const int32_t* n, const float* p, int32_t* out) {
+    if (!c || !n || !p || !out) return BRNG_E_ARG;
+    if (c->cfg.layout != BRNG_LAYOUT_CHAINS) return BRNG_E_ARG;
+    if (c->cfg.prec != BRNG_F32) return BRNG_E_UNSUPPORTED;
+    if (!c->cfg.window[BRNG_U]) return BRNG_E_KIND_DISABLED;
+    hipLaunchKernelGGL(k_step_binomial, unit_grid(c, c->n_units), dim3(64 * c->wpb), 0, c->stream,
+                       c->meta, (float*)c->pool[BRNG_U], c->cfg.window[BRNG_U], c->cfg.n_chains,
+                       n, p, out);
     HIPCHK(hipGetLastError());
     return BRNG_OK;
 }

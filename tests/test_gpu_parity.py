@@ -192,6 +192,48 @@ def test_step_poisson(dev):
         b.brng_destroy(ctx)
 
 
+def test_step_binomial(dev):
+    """Binomial steps (inversion when n min(p, 1-p) < 10, BTRD otherwise,
+    mirrored above 1/2) with per-chain n up to 1e6 and p in [0, 1] plus the
+    edge values; five calls through 512-entry windows; counts and cursors
+    bit-exact, flips only where the oracle's margin allows."""
+    import torch
+    b = _b()
+    m, seed = 1000 + 17, 62
+    rng = np.random.default_rng(9)
+    n = np.floor(np.exp(rng.uniform(0, np.log(1e6), m))).astype(np.int32)
+    p = rng.uniform(size=m).astype(np.float32)
+    n[:10] = [0, 10, 10, 40, -1, 10, 10, 10, 2 ** 30, 3]
+    p[:10] = [0.3, 0.0, 1.0, 0.5, 0.5, -0.1, np.nan, 1.5, 0.5, 0.9999]
+    _say("step_binomial", m, seed)
+    ctx = _ctx(seed, m, W_SMALL)
+    cur = oracle.new_cursors((m + 63) // 64)
+    out = torch.zeros(m, dtype=torch.int32, device=dev)
+    units = np.arange(m) // 64
+    flipped = set()
+    try:
+        tn, tp = _t(n, dev), _t(p, dev)
+        for it in range(5):
+            b.brng_step_binomial(ctx, tn, tp, out)
+            k, margin = oracle.step_binomial(seed, cur, n, p.astype(np.float64))
+            g = _np(out)
+            for u in np.unique(units[g != k]):
+                if u in flipped:
+                    continue
+                sl = units == u
+                assert margin[sl].min() <= 1.0, (it, u, g[sl], k[sl])
+                flipped.add(int(u))
+            ok = np.array([u not in flipped for u in units])
+            assert np.array_equal(g[ok], k[ok])
+        assert list(g[:3]) == [0, 0, 10] and list(g[4:8]) == [-1, -1, -1, -1]
+        got = b.brng_get_cursors(ctx)
+        keep = np.array([u not in flipped for u in range(got.shape[0])])
+        assert np.array_equal(got[keep], cur[keep])
+        assert len(flipped) <= 1
+    finally:
+        b.brng_destroy(ctx)
+
+
 def test_step_dirichlet_ragged(dev):
     b = _b()
     it = workloads.dirichlet_items(150, kmin=1, kmax=300, seed=3)
