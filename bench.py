@@ -322,6 +322,28 @@ def setup_lda(torch, b, args):
                         "generator": "Philox4x32-10"})
 
 
+def copy_bandwidth(torch, b, nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth for context: the library's streaming
+    conversion kernel (brng_convert, uniform kind: one 16-byte load and one
+    16-byte store per thread) over `nbytes` of words, read + write bytes over
+    event time."""
+    n = nbytes // 4
+    src = torch.randint(0, 2 ** 31 - 1, (n,), dtype=torch.int32, device="cuda")
+    dst = torch.empty(n, dtype=torch.float32, device="cuda")
+    b.brng_convert(b.BRNG_U, src, n, dst, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.brng_convert(b.BRNG_U, src, n, dst, stream=torch.cuda.current_stream())
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    return gbs
+
+
 def per_distribution(torch, b, args, n=1 << 20, calls=20):
     """The paper's results table on one MI355X, per distribution (Sec. 2.4):
     the bulk fill of a pool (its Batch column) and one-at-a-time calls with a
@@ -617,6 +639,10 @@ def main():
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(Wk["kernel"]),
             "kernel": Wk["kernel"],
             "kernel_ms": round(chain_ms, 4), "alg_bytes_per_launch": chain_b}
+    # context: what a plain copy reaches on this GPU
+    cgbs = copy_bandwidth(torch, b)
+    roof["copy_gbs"] = round(cgbs, 1)
+    roof["frac_of_copy"] = round(gbs / cgbs, 4)
     out = {
         "metric": "varying-param deviates/s + % HBM roofline",
         "value": value,
