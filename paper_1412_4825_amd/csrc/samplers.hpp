@@ -43,12 +43,6 @@ __device__ __noinline__ bool mt_accept64(float a, float x, float e) {
     return (double)e + d * mt_q64(y) > 0.0;
 }
 
-// Shapes outside (0, 2^64) would never be accepted (or are meaningless);
-// such draws complete at once with NaN and consume nothing.
-__device__ __forceinline__ bool gamma_shape_ok(float alpha) {
-    return alpha > 0.0f && alpha < 0x1p64f;
-}
-
 // ln(1 + y) for y > -1: the logarithm of the rounded sum u = 1 + y plus the
 // first-order correction for the rounding (y - (u - 1)) / u.
 __device__ __forceinline__ float log1p_fast(float y) {
@@ -124,7 +118,8 @@ __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t 
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     // One round for the lanes of mask mh (those holding a draw).
     auto one_round = [&](const uint64_t mh) {
-        // shapes outside (0, 2^64) have no draw; below 1 the boost applies
+        // shapes outside (0, 2^64) have no draw (it completes at once with NaN
+        // and consumes nothing); below 1 the boost applies
         const uint64_t mv = wave_ballot(al > 0.0f) & wave_ballot(al < 0x1p64f);
         const uint64_t mboost = mv & wave_ballot(al < 1.0f);
         const float a = lane_in(mv) ? (lane_in(mboost) ? al + 1.0f : al) : 1.0f;
