@@ -421,7 +421,7 @@ __device__ void unit_expchain(const DescDev& D, Meta* mp, const Pools& P, uint32
 // ---------------------------------------------------------------------------
 using GammaRN = EpochReader<KIND_N, 1>;
 using GammaRE = EpochReader<KIND_E, 2>;
-constexpr int GAMMA_OBUF_BYTES = (int)EPOCH_ROUNDS * 64 * 4;
+constexpr int GAMMA_OBUF_BYTES = TRACE_ROWS * 64 * 4;
 constexpr int GAMMA_LDS_BYTES = GammaRN::LDS_BYTES + GammaRE::LDS_BYTES + GAMMA_OBUF_BYTES;
 // An epoch's worst case fits the rings (a round takes at most one Gaussian
 // and two exponentials per lane), so the rounds run without staging checks.
@@ -452,9 +452,9 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
     src.L = L;
     src.alpha = in ? st[chain] : 1.0f;
     src.trace = D.trace != nullptr;
-    src.out = src.trace ? reinterpret_cast<float*>(D.trace) + (int64_t)t0 * D.stride + slot : nullptr;
+    src.col = src.trace ? reinterpret_cast<float*>(D.trace) + slot : nullptr;
     src.stride = D.stride;
-    src.obuf = reinterpret_cast<float*>(lds + GammaRN::LDS_BYTES + GammaRE::LDS_BYTES) + lane;
+    src.ring = reinterpret_cast<float*>(lds + GammaRN::LDS_BYTES + GammaRE::LDS_BYTES) + lane;
     const uint32_t smax = (uint32_t)min(D.max_steps, 1 << 24);
     gamma_rounds<true>(rn, re, src, D.max_rounds > 0 ? (uint32_t)D.max_rounds : 4096u + 64u * smax);
     if (in) st[chain] = src.alpha;

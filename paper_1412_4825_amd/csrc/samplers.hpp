@@ -94,7 +94,8 @@ __device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_in
 //                                 lanes whose draw is done; such a lane hands
 //                                 over g; returns the shape of the lane's
 //                                 draw for the next round
-//   void flush()                  epoch point (global stores go here)
+//   void flush(bool final)        epoch point (global stores go here);
+//                                 final at the end of the rounds
 constexpr uint32_t EPOCH_ROUNDS = 4;
 
 // COVERED: the readers' rings hold an epoch's worst case (64 Gaussians and
@@ -205,7 +206,7 @@ __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t 
         rn.sync_avail();
         re.sync_avail();
     }
-    src.flush();
+    src.flush(true);
 }
 
 // One draw per lane (the one-at-a-time call).
@@ -221,7 +222,7 @@ struct OneEachSrc {
         want = done ? 0 : want;
         return al;
     }
-    __device__ __forceinline__ void flush() {}
+    __device__ __forceinline__ void flush(bool = false) {}
 };
 
 // Components of one Dirichlet item: lanes start with components 0..63 and a
@@ -254,49 +255,87 @@ struct CompSrc {
         next += (uint32_t)__popcll(md);
         return a;
     }
-    __device__ __forceinline__ void flush() {}
+    __device__ __forceinline__ void flush(bool = false) {}
 };
 
+// Wave minimum / maximum of an int32 (every lane gets the result), by DPP
+// lane moves: lanes without a source keep the identity.
+template <bool MAX>
+__device__ __forceinline__ int32_t wave_minmax(int32_t v) {
+    constexpr int32_t ID = MAX ? INT32_MIN : INT32_MAX;
+    auto op = [](int32_t a, int32_t b) { return MAX ? max(a, b) : min(a, b); };
+    v = op(v, __builtin_amdgcn_update_dpp(ID, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+    v = op(v, __builtin_amdgcn_update_dpp(ID, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+    v = op(v, __builtin_amdgcn_update_dpp(ID, v, 0x114, 0xF, 0xF, false));  // row_shr:4
+    v = op(v, __builtin_amdgcn_update_dpp(ID, v, 0x118, 0xF, 0xF, false));  // row_shr:8
+    v = op(v, __builtin_amdgcn_update_dpp(ID, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = op(v, __builtin_amdgcn_update_dpp(ID, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 // One chain per lane: g_t ~ Gamma(alpha_t, 1), alpha_{t+1} = 0.1 + g_t; the
-// lane starts its next step as soon as a draw is accepted.  Trace values wait
-// in LDS (at most EPOCH_ROUNDS per lane, one per round) and go out at the
-// epoch points.
+// lane starts its next step as soon as a draw is accepted.
+//
+// Trace rows are staged in LDS (a ring of TRACE_ROWS rows of 64 values) and
+// stored whole: a lane that completes step t writes row t of the ring, and at
+// an epoch point every row below the smallest step a lane still holds is
+// complete and goes out as one 256-byte row store (lanes whose chain has no
+// such step, or that wrote the row in an earlier launch, are masked off).
+// Lanes at different steps (rejections) then no longer scatter 4-byte stores
+// over many rows.  When the lanes spread further apart than the ring holds,
+// the lowest rows are stored partially (the lanes that have written them) and
+// a lane that later completes such a row stores its value directly.
+constexpr int32_t TRACE_ROWS = 16;
 struct ChainSrc {
     int32_t t, L;
+    int32_t t0;      // the lane's first step in this launch
     float alpha;
     bool trace;      // wave-uniform: write the trace
-    float* out;      // this lane's entry of the trace row of the next flushed step
+    float* col;      // this lane's trace column (row 0), or null
     int64_t stride;  // trace elements between steps
-    float* obuf;     // LDS, EPOCH_ROUNDS x 64 values; this lane's column
-    int32_t t_ep;    // t at the last flush: values buffered = t - t_ep
+    float* ring;     // LDS, TRACE_ROWS x 64 values; this lane's column
+    int32_t f;       // wave-uniform: rows below f have been stored
     __device__ __forceinline__ float first() {
-        t_ep = t;
+        t0 = t;
+        f = wave_minmax<false>(t < L ? t : INT32_MAX);
         return alpha;
     }
     __device__ __forceinline__ bool holding() const { return t < L; }
-    // Branch-free: every lane writes its value to its next buffer slot (also
-    // without a trace: the buffer is there either way), and only lanes whose
-    // draw completed move on (a slot written by a lane that did not is
-    // overwritten before it is flushed).
+    // Every lane writes its value to the ring slot of its current step (also
+    // without a trace: the ring is there either way); only lanes whose draw
+    // completed move on, so a slot written by a lane that did not is
+    // rewritten before its row is stored.  A lane behind the stored rows
+    // stores a completed value itself.
     __device__ __forceinline__ float complete(uint64_t md, float gv, float) {
         const bool done = lane_in(md);
-        obuf[(t - t_ep) * 64] = gv;
+        const bool behind = t < f;
+        if (wave_ballot(behind) == 0) {
+            ring[(t & (TRACE_ROWS - 1)) * 64] = gv;
+        } else {
+            if (!behind) ring[(t & (TRACE_ROWS - 1)) * 64] = gv;
+            if (behind && done && trace) col[(int64_t)t * stride] = gv;
+        }
         alpha = done ? 0.1f + gv : alpha;
         t += done ? 1 : 0;
         return alpha;
     }
-    __device__ __forceinline__ void flush() {
+    // Row r: the lanes that wrote it in this launch store their value.
+    __device__ __forceinline__ void store_row(int32_t r) {
+        if (t0 <= r && r < t) col[(int64_t)r * stride] = ring[(r & (TRACE_ROWS - 1)) * 64];
+    }
+    // Epoch point (final: the end of the launch, when every written row goes
+    // out).  Keeps room in the ring for the next EPOCH_ROUNDS steps.
+    __device__ __forceinline__ void flush(bool final = false) {
+        const int32_t lo = wave_minmax<false>(t < L ? t : INT32_MAX);
+        const int32_t hi = wave_minmax<true>(t);
         if (trace) {
-            const int32_t nb = t - t_ep;
-            static_for<0, (int)EPOCH_ROUNDS>([&](auto jc) {
-                constexpr int32_t j = decltype(jc)::value;
-                if (j < nb) {
-                    *out = obuf[j * 64];
-                    out += stride;
-                }
-            });
+            const int32_t end = final ? hi : min(lo, hi);
+            for (int32_t r = f; r < end; ++r) store_row(r);
+            f = max(f, end);
+            for (; f < hi + (int32_t)EPOCH_ROUNDS - TRACE_ROWS; ++f) store_row(f);
+        } else {
+            f = max(f, max(min(lo, hi), hi + (int32_t)EPOCH_ROUNDS - TRACE_ROWS));
         }
-        t_ep = t;
     }
 };
 
