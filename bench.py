@@ -435,7 +435,7 @@ def autotune_launch(torch, b, args):
         return trial, cache
 
     trial, cache = trial_factory()
-    best = autotune.pick(trial, windows=(2048, 4096, 16384), wpbs=(2, 4, 8), reps=2)
+    best = autotune.pick(trial, windows=(512, 1024, 2048, 4096), wpbs=(2, 4, 8), reps=2)
     for Wk in cache.values():
         b.brng_destroy(Wk["ctx"])
     torch.cuda.synchronize()

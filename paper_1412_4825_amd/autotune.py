@@ -14,7 +14,7 @@ import os
 from typing import Callable, Iterable
 
 WPB_CANDIDATES = (1, 2, 4, 8)
-WINDOW_CANDIDATES = (1024, 4096, 16384)
+WINDOW_CANDIDATES = (512, 1024, 2048, 4096)
 
 
 def pick(trial: Callable[[int, int], float], windows: Iterable[int] = WINDOW_CANDIDATES,

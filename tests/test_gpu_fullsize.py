@@ -4,8 +4,9 @@ launch after the bulk refills, as bench.py times it.
 
 - normal/exponential chains: 65,536 chains x 1,000 steps, window 4,096;
 - gamma chains: 262,144 chains of lengths U{50..1000}, slots sorted by
-  length, window 2,048 (the autotuner's usual choice);
-- LDA: 16,384 documents x 100 sweeps, window 4,096, two waves per block.
+  length, window 512, eight waves per block (the autotuner's usual choice);
+- LDA: 16,384 documents x 100 sweeps, window 512, eight waves per block,
+  documents in the work order the bench uses.
 
 Every test prints its case before the GPU calls."""
 import numpy as np
@@ -94,7 +95,7 @@ def test_gamma_full_size(dev):
     import torch
     b = _b()
     w = workloads.gamma_chain(n_chains=262144, seed=SEED)
-    n, W = w["n_chains"], 2048
+    n, W = w["n_chains"], 512
     perm = b.brng_sort_by_length(w["steps"])
     smax = int(w["steps"].max())
     _say("gamma full size", n, smax, W)
@@ -104,7 +105,7 @@ def test_gamma_full_size(dev):
     units = [0, 1, 1024, 2047, 3000, 4095]
     cols = [64 * u + c for u in units for c in range(64)]
     try:
-        b.brng_set_launch(ctx, 4)
+        b.brng_set_launch(ctx, 8)
         kw = dict(max_steps=smax, seed=SEED, trace=tg, trace_stride=n,
                   steps=_t(w["steps"], dev), perm=_t(perm, dev))
         b.brng_run_gibbs(ctx, b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, n, st, **kw))
@@ -153,7 +154,7 @@ def test_lda_full_size(dev):
     import torch
     b = _b()
     w = workloads.lda(n_docs=16384, sweeps=100, seed=SEED)
-    nd, sweeps, W = w["n_docs"], w["sweeps"], 4096
+    nd, sweeps, W = w["n_docs"], w["sweeps"], 512
     off, ntok = w["offsets"], w["ntok"]
     total = int(off[-1])
     _say("lda full size", nd, sweeps, W)
@@ -169,9 +170,11 @@ def test_lda_full_size(dev):
         docs += [int(idx[0]), int(idx[len(idx) // 2])]
     cols = [c for d in docs for c in range(off[d], off[d + 1])]
     try:
-        b.brng_set_launch(ctx, 2)
+        b.brng_set_launch(ctx, 8)
+        from paper_1412_4825_amd import order
+        tperm = _t(order.doc_order(off, ntok), dev)
         kw = dict(max_steps=sweeps, seed=SEED, trace=th, trace2=ct, trace_stride=total,
-                  offsets=_t(off, dev), ntok=_t(ntok, dev))
+                  offsets=_t(off, dev), ntok=_t(ntok, dev), perm=tperm)
         b.brng_run_gibbs(ctx, b.gibbs_desc(b.BRNG_MODEL_LDA, nd, counts, **kw))
         runs = [(_cols(th, cols), _cols(ct, cols))]
         for k in (b.BRNG_U, b.BRNG_N, b.BRNG_E):
