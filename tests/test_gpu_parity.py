@@ -433,8 +433,9 @@ def test_lda(dev):
 
 def test_lda_document_order_invariance(dev):
     """Waves taking documents in another order (the work order the bench
-    uses, and a random one) give the same counts, traces and cursors bit for
-    bit: each document is its own unit."""
+    uses, and a random one), with other windows and workgroup sizes, give the
+    same counts, traces and cursors bit for bit: each document is its own
+    unit."""
     import torch
     from paper_1412_4825_amd import order
     b = _b()
@@ -443,16 +444,19 @@ def test_lda_document_order_invariance(dev):
     nd, total, sw = w["n_docs"], int(w["offsets"][-1]), w["sweeps"]
     perms = [None, order.doc_order(w["offsets"], w["ntok"]),
              np.random.default_rng(4).permutation(nd).astype(np.int32)]
+    # (document order, window, waves per workgroup); the bench's tuned shape
+    # is the second
+    cases = [(perms[0], 4096, 2), (perms[1], 512, 8), (perms[2], 1024, 4)]
     _say("lda order", nd, sw, seed)
     res = []
-    for perm in perms:
-        ctx = _ctx(seed, nd, W_SMALL, layout=1)
+    for perm, win, wpb in cases:
+        ctx = _ctx(seed, nd, [win] * 3 + [0], layout=1)
         counts = torch.zeros(total, dtype=torch.int32, device=dev)
         th = torch.zeros((sw, total), dtype=torch.float32, device=dev)
         ct = torch.zeros((sw, total), dtype=torch.int32, device=dev)
         tp = None if perm is None else _t(perm, dev)
         try:
-            b.brng_set_launch(ctx, 2)
+            b.brng_set_launch(ctx, wpb)
             b.brng_run_gibbs(ctx, b.gibbs_desc(b.BRNG_MODEL_LDA, nd, counts, max_steps=sw,
                                                seed=seed, trace=th, trace2=ct, trace_stride=total,
                                                offsets=_t(w["offsets"], dev),
