@@ -85,6 +85,8 @@ def _declare(L):
     L.or_step_poisson.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _dp, _i32p, _dp]
     L.or_step_binomial.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _i32p, _dp, _i32p,
                                    _dp]
+    L.or_step_multinomial.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _i32p, _i32p,
+                                      _dp, _i32p, _dp]
     L.or_step_dirichlet.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _u64p, _i32p, _dp, _dp, _dp, _dp]
     L.or_multinomial.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _u64p, _i32p, _i32p, _dp, _i32p]
     L.or_triangle.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _dp, _dp, _u64p, _dp, _dp, _dp, _dp]
@@ -240,6 +242,21 @@ def step_binomial(seed, cursors, n, p, width=UNIT_WIDTH, unit0=0):
     mar = np.zeros(m)
     lib().or_step_binomial(seed, unit0, m, width, _p(cursors, _u64p), _p(n, _i32p), _p(p, _dp),
                            _p(out, _i32p), _p(mar, _dp))
+    return out, mar
+
+
+def step_multinomial(seed, cursors, offsets, n, weights, width=UNIT_WIDTH, unit0=0):
+    """Multinomial(n_i, weights of item i) per item (items are the chains of
+    64-item units; components by offsets) by conditional binomials on the U
+    pool.  Returns (int32 counts per component, margin per item)."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.int32)
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    w = _d(weights)
+    ni = n.size
+    out = np.zeros(int(offsets[-1]), dtype=np.int32)
+    mar = np.zeros(ni)
+    lib().or_step_multinomial(seed, unit0, ni, width, _p(cursors, _u64p), _p(offsets, _i32p),
+                              _p(n, _i32p), _p(w, _dp), _p(out, _i32p), _p(mar, _dp))
     return out, mar
 
 

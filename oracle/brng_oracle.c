@@ -932,6 +932,68 @@ static int btrd_second(const btrd_t *B, double v, double w, int32_t *k, double *
     return 0;
 }
 
+/* One binomial call over a unit's slots: every slot k with act[k] draws
+ * Binomial(n[k], p[k]) (as above; -1 for invalid parameters); other slots
+ * are left alone.  margin[k] is lowered by the draw's decisions. */
+static void binom_call(stream_t *s, int ns, const int32_t *nn, const double *pr,
+                       const uint8_t *act, int32_t *out, double *margin)
+{
+    uint8_t pend[OR_MAXSLOT], flip[OR_MAXSLOT], inv[OR_MAXSLOT];
+    double v1[OR_MAXSLOT], pp[OR_MAXSLOT];
+    btrd_t B[OR_MAXSLOT];
+    int any = 0;
+    for (int k = 0; k < ns; k++) {
+        pend[k] = 0;
+        if (!act[k])
+            continue;
+        int32_t n = nn[k];
+        double p = pr[k];
+        out[k] = -1;
+        pend[k] = (uint8_t)(n >= 0 && p >= 0.0 && p <= 1.0);
+        if (!pend[k])
+            continue;
+        flip[k] = (uint8_t)(p > 0.5);
+        pp[k] = flip[k] ? 1.0 - p : p;
+        inv[k] = (uint8_t)((double)n * pp[k] < 10.0);
+        if (!inv[k])
+            btrd_setup(&B[k], n, pp[k]);
+        any = 1;
+    }
+    for (int round = 0; any && round < 1 << 20; round++) {
+        for (int k = 0; k < ns; k++)
+            if (pend[k])
+                v1[k] = take(s, OR_U);
+        for (int k = 0; k < ns; k++) {
+            if (!pend[k])
+                continue;
+            double mg = margin ? margin[k] : INFINITY;
+            int32_t kk = 0, done = 0;
+            if (inv[k]) {
+                double mi;
+                kk = binom_invert(nn[k], pp[k], v1[k], &mi);
+                lower(&mg, mi);
+                done = 1;
+            } else {
+                int r = btrd_first(&B[k], v1[k], &kk, &mg);
+                if (r == 1) {
+                    done = 1;
+                } else if (r == 0) {
+                    double w = take(s, OR_U);
+                    done = btrd_second(&B[k], v1[k], w, &kk, &mg);
+                }
+            }
+            if (done) {
+                out[k] = flip[k] ? nn[k] - kk : kk;
+                pend[k] = 0;
+            }
+            if (margin) margin[k] = mg;
+        }
+        any = 0;
+        for (int k = 0; k < ns; k++)
+            any |= pend[k];
+    }
+}
+
 void or_step_binomial(uint64_t seed, uint32_t unit0, uint32_t n_ch, uint32_t width,
                       uint64_t *cursors, const int32_t *nn, const double *pr, int32_t *out,
                       double *margin)
@@ -939,61 +1001,96 @@ void or_step_binomial(uint64_t seed, uint32_t unit0, uint32_t n_ch, uint32_t wid
     if (width == 0 || width > OR_MAXSLOT)
         return;
     uint32_t nu = (n_ch + width - 1) / width;
-    uint8_t pend[OR_MAXSLOT], flip[OR_MAXSLOT], inv[OR_MAXSLOT];
-    double v1[OR_MAXSLOT], pp[OR_MAXSLOT];
-    btrd_t B[OR_MAXSLOT];
+    uint8_t act[OR_MAXSLOT];
+    memset(act, 1, sizeof(act));
     for (uint32_t un = 0; un < nu; un++) {
         stream_t s = {seed, unit0 + un, cursors + 4 * (size_t)un};
         uint32_t lo, hi;
         unit_range(n_ch, width, un, &lo, &hi);
-        int ns = (int)(hi - lo), any = 0;
-        for (int k = 0; k < ns; k++) {
-            int32_t n = nn[lo + k];
-            double p = pr[lo + k];
-            out[lo + k] = -1;
-            if (margin) margin[lo + k] = INFINITY;
-            pend[k] = (uint8_t)(n >= 0 && p >= 0.0 && p <= 1.0);
-            if (!pend[k])
-                continue;
-            flip[k] = (uint8_t)(p > 0.5);
-            pp[k] = flip[k] ? 1.0 - p : p;
-            inv[k] = (uint8_t)((double)n * pp[k] < 10.0);
-            if (!inv[k])
-                btrd_setup(&B[k], n, pp[k]);
-            any = 1;
-        }
-        for (int round = 0; any && round < 1 << 20; round++) {
-            for (int k = 0; k < ns; k++)
-                if (pend[k])
-                    v1[k] = take(&s, OR_U);
-            for (int k = 0; k < ns; k++) {
-                if (!pend[k])
-                    continue;
-                double mg = margin ? margin[lo + k] : INFINITY;
-                int32_t kk = 0, done = 0;
-                if (inv[k]) {
-                    double mi;
-                    kk = binom_invert(nn[lo + k], pp[k], v1[k], &mi);
-                    lower(&mg, mi);
-                    done = 1;
-                } else {
-                    int r = btrd_first(&B[k], v1[k], &kk, &mg);
-                    if (r == 1) {
-                        done = 1;
-                    } else if (r == 0) {
-                        double w = take(&s, OR_U);
-                        done = btrd_second(&B[k], v1[k], w, &kk, &mg);
-                    }
-                }
-                if (done) {
-                    out[lo + k] = flip[k] ? nn[lo + k] - kk : kk;
-                    pend[k] = 0;
-                }
-                if (margin) margin[lo + k] = mg;
+        if (margin)
+            for (uint32_t c = lo; c < hi; c++) margin[c] = INFINITY;
+        binom_call(&s, (int)(hi - lo), nn + lo, pr + lo, act, out + lo, margin ? margin + lo : NULL);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multinomial(n, p_0..p_{K-1}) by conditional binomials (the discrete       */
+/* library of Sec. 3's future work): x_k ~ Binomial(n - x_0 - ... - x_{k-1},  */
+/* p_k / S_k) for k < K - 1, x_{K-1} the rest, where S_k is the weight left:  */
+/* S_0 = p_0 + ... + p_{K-1} summed in index order and S_{k+1} = S_k - p_k, */
+/* in double precision; S_k <= 0 gives probability 0, a quotient above 1 is */
+/* taken as 1.  Items are the */
+/* chains of a unit (one item per slot, components by offsets).  Component  */
+/* k of every item that draws one (k < K_i - 1) is one binomial call over    */
+/* the unit, k = 0, 1, ...  An item with n < 0, K < 1 or a weight that is   */
+/* negative or not finite gives -1 in all its components and draws nothing. */
+/* ------------------------------------------------------------------------ */
+void or_step_multinomial(uint64_t seed, uint32_t unit0, uint32_t n_items, uint32_t width,
+                         uint64_t *cursors, const int32_t *offsets, const int32_t *nn,
+                         const double *pw, int32_t *out, double *margin)
+{
+    if (width == 0 || width > OR_MAXSLOT)
+        return;
+    uint32_t nu = (n_items + width - 1) / width;
+    for (uint32_t un = 0; un < nu; un++) {
+        stream_t s = {seed, unit0 + un, cursors + 4 * (size_t)un};
+        uint32_t lo, hi;
+        unit_range(n_items, width, un, &lo, &hi);
+        int ns = (int)(hi - lo), kmax = 0;
+        uint8_t ok[OR_MAXSLOT], act[OR_MAXSLOT];
+        int32_t rem[OR_MAXSLOT], x[OR_MAXSLOT];
+        double pk[OR_MAXSLOT], mg[OR_MAXSLOT];
+        for (int j = 0; j < ns; j++) {
+            uint32_t i = lo + (uint32_t)j;
+            int32_t K = offsets[i + 1] - offsets[i];
+            int good = nn[i] >= 0 && K >= 1;
+            for (int32_t c = 0; good && c < K; c++) {
+                double w = pw[offsets[i] + c];
+                good = w >= 0.0 && w < INFINITY;
             }
-            any = 0;
-            for (int k = 0; k < ns; k++)
-                any |= pend[k];
+            ok[j] = (uint8_t)good;
+            rem[j] = nn[i];
+            mg[j] = INFINITY;
+            for (int32_t c = 0; c < K; c++)
+                out[offsets[i] + c] = -1;
+            if (good && K > kmax)
+                kmax = K;
+        }
+        double S[OR_MAXSLOT];
+        for (int j = 0; j < ns; j++) {
+            uint32_t i = lo + (uint32_t)j;
+            int32_t K = offsets[i + 1] - offsets[i];
+            S[j] = 0.0;
+            for (int32_t c = 0; ok[j] && c < K; c++)
+                S[j] += pw[offsets[i] + c];
+        }
+        for (int32_t k = 0; k + 1 < kmax; k++) {
+            for (int j = 0; j < ns; j++) {
+                uint32_t i = lo + (uint32_t)j;
+                int32_t K = offsets[i + 1] - offsets[i];
+                act[j] = (uint8_t)(ok[j] && k + 1 < K);
+                if (!act[j])
+                    continue;
+                double w = pw[offsets[i] + k];
+                double q = S[j] > 0.0 ? w / S[j] : 0.0;
+                pk[j] = q > 1.0 ? 1.0 : q;
+                S[j] -= w;
+            }
+            binom_call(&s, ns, rem, pk, act, x, mg);
+            for (int j = 0; j < ns; j++) {
+                if (!act[j])
+                    continue;
+                uint32_t i = lo + (uint32_t)j;
+                out[offsets[i] + k] = x[j];
+                rem[j] -= x[j];
+            }
+        }
+        for (int j = 0; j < ns; j++) {
+            uint32_t i = lo + (uint32_t)j;
+            int32_t K = offsets[i + 1] - offsets[i];
+            if (ok[j])
+                out[offsets[i] + K - 1] = rem[j];
+            if (margin) margin[i] = mg[j];
         }
     }
 }
