@@ -392,6 +392,13 @@ def per_distribution(torch, b, args, n=1 << 20, calls=20):
         trials = torch.from_numpy(np.floor(np.exp(g2.uniform(0, np.log(1e4), n))).astype(np.int32)).to(dev)
         prob = torch.from_numpy(g2.uniform(size=n).astype(np.float32)).to(dev)
         res["binomial"] = {"one_at_a_time": timed(lambda: b.brng_step_binomial(ctx, trials, prob, kout), n)}
+        # multinomial by conditional binomials: 8 components per item, the
+        # same trial counts; deviates = items x components
+        moff = torch.arange(0, 8 * n + 1, 8, dtype=torch.int32, device=dev)
+        mw = torch.from_numpy(g2.exponential(size=8 * n).astype(np.float32)).to(dev)
+        mout = torch.empty(8 * n, dtype=torch.int32, device=dev)
+        res["multinomial_k8"] = {"one_at_a_time": timed(
+            lambda: b.brng_step_multinomial(ctx, moff, trials, mw, mout), 8 * n)}
     finally:
         b.brng_destroy(ctx)
     return {"chains": n, "calls": calls, "window": W, "unit": "deviates/s",

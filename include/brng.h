@@ -152,6 +152,23 @@ brng_status brng_step_poisson(brng_ctx *ctx, const float *d_lambda, int32_t *d_o
  * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_UNSUPPORTED, BRNG_E_HIP. */
 brng_status brng_step_binomial(brng_ctx *ctx, const int32_t *d_n, const float *d_p, int32_t *d_out);
 
+/* Multinomial(n, p) by conditional binomials (the discrete library of Sec.
+ * 3's future work): one item per chain (n_chains items, layout CHAINS,
+ * precision F32, U pool), item i with components [d_offsets[i],
+ * d_offsets[i+1]) of d_w (float weights, need not add to 1) and d_out (int32
+ * counts), d_n[i] trials.  x_k ~ Binomial(n - x_0 - ... - x_{k-1}, p_k / S_k)
+ * for k < K - 1, x_{K-1} the rest; S_0 = p_0 + ... + p_{K-1} (index order,
+ * double precision), S_{k+1} = S_k - p_k; S_k <= 0 gives probability 0, a
+ * quotient above 1 is taken as 1.  Component k of every item that draws one
+ * is one binomial call over the unit (as brng_step_binomial), k = 0, 1, ...
+ * An item with n < 0, no components or a weight that is negative or not
+ * finite gets -1 in every component and draws nothing.  d_offsets holds
+ * n_chains + 1 nondecreasing entries from 0; d_w and d_out hold
+ * d_offsets[n_chains] entries.
+ * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_UNSUPPORTED, BRNG_E_HIP. */
+brng_status brng_step_multinomial(brng_ctx *ctx, const int32_t *d_offsets, const int32_t *d_n,
+                                  const float *d_w, int32_t *d_out);
+
 /* Dirichlet by normalised gammas (Sec. 1, footnote on Dirichlet): layout
  * ITEMS, item i has components [d_offsets[i], d_offsets[i+1]) of d_alpha and
  * d_out (F32).  Components are drawn in batches of 64, one gamma call per

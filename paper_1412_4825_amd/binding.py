@@ -29,7 +29,7 @@ WINDOW_MIN = 512
 EXPORTS = [
     "brng_create", "brng_destroy", "brng_fill_base", "brng_step_uniform", "brng_step_normal",
     "brng_step_exp", "brng_step_gamma", "brng_step_laplace", "brng_step_weibull", "brng_step_poisson",
-    "brng_step_binomial",
+    "brng_step_binomial", "brng_step_multinomial",
     "brng_step_dirichlet", "brng_run_gibbs",
     "brng_sort_by_length", "brng_get_cursors", "brng_set_cursors", "brng_get_window",
     "brng_get_info", "brng_set_launch", "brng_status_string", "brng_last_hip_error",
@@ -141,6 +141,7 @@ def _load():
     L.brng_step_weibull.argtypes = [vp, vp, vp, vp]
     L.brng_step_poisson.argtypes = [vp, vp, vp]
     L.brng_step_binomial.argtypes = [vp, vp, vp, vp]
+    L.brng_step_multinomial.argtypes = [vp, vp, vp, vp, vp]
     L.brng_step_dirichlet.argtypes = [vp, vp, vp, vp]
     L.brng_run_gibbs.argtypes = [vp, C.POINTER(brng_gibbs_desc), C.c_uint32]
     L.brng_sort_by_length.argtypes = [C.c_uint32, vp, vp]
@@ -261,6 +262,11 @@ def brng_step_poisson(ctx, lam, out) -> None:
 
 def brng_step_binomial(ctx, n, p, out) -> None:
     _check(_lib.brng_step_binomial(ctx, _ptr(n), _ptr(p), _ptr(out)), "brng_step_binomial")
+
+
+def brng_step_multinomial(ctx, offsets, n, w, out) -> None:
+    _check(_lib.brng_step_multinomial(ctx, _ptr(offsets), _ptr(n), _ptr(w), _ptr(out)),
+           "brng_step_multinomial")
 
 
 def brng_step_dirichlet(ctx, offsets, alpha, out) -> None:

@@ -346,18 +346,12 @@ __device__ __forceinline__ int32_t binomial_invert(int32_t n, double p, double u
     return k;
 }
 
-__global__ __launch_bounds__(512) void k_step_binomial(Meta* meta, float* pool, uint32_t W,
-                                                       uint32_t n_ch, const int32_t* n_in,
-                                                       const float* p_in, int32_t* out) {
-    const uint32_t unit = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
-    if (unit * 64 >= n_ch) return;
-    const uint32_t c = unit * 64 + lane_id();
-    const bool act = c < n_ch;
-    DirectReader<KIND_U> r;
-    r.open(meta[unit], pool + (size_t)unit * W, W);
-    const int32_t n = act ? n_in[c] : -1;
-    const double p = act ? (double)p_in[c] : 0.0;
-    const bool valid = n >= 0 && p >= 0.0 && p <= 1.0;  // false for NaN
+// One binomial call over a wave: every lane with `act` draws
+// Binomial(n, p) (-1 for n < 0 or p outside [0, 1]); the lanes take their
+// uniforms in the rounds described above.  Called by every lane of the wave.
+__device__ __forceinline__ int32_t binomial_call(DirectReader<KIND_U>& r, int32_t n, double p,
+                                                 bool act) {
+    const bool valid = act && n >= 0 && p >= 0.0 && p <= 1.0;  // false for NaN
     const bool flip = p > 0.5;
     const double pp = flip ? 1.0 - p : p;
     const bool inv = valid && (double)n * pp < 10.0;
@@ -386,7 +380,74 @@ __global__ __launch_bounds__(512) void k_step_binomial(Meta* meta, float* pool, 
             pend = false;
         }
     }
+    return k;
+}
+
+__global__ __launch_bounds__(512) void k_step_binomial(Meta* meta, float* pool, uint32_t W,
+                                                       uint32_t n_ch, const int32_t* n_in,
+                                                       const float* p_in, int32_t* out) {
+    const uint32_t unit = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (unit * 64 >= n_ch) return;
+    const uint32_t c = unit * 64 + lane_id();
+    const bool act = c < n_ch;
+    DirectReader<KIND_U> r;
+    r.open(meta[unit], pool + (size_t)unit * W, W);
+    const int32_t k = binomial_call(r, act ? n_in[c] : -1, act ? (double)p_in[c] : 0.0, act);
     if (act) out[c] = k;
+    r.close(meta[unit]);
+}
+
+// Multinomial by conditional binomials (the discrete library of Sec. 3's
+// future work), one item per lane: x_k ~ Binomial(n - x_0 - ... - x_{k-1},
+// p_k / S_k) for k < K - 1 and x_{K-1} the rest, where S_0 = p_0 + ... +
+// p_{K-1} (index order, double precision) and S_{k+1} = S_k - p_k; S_k <= 0
+// gives probability 0 and a quotient above 1 is taken as 1.  Component k of
+// every item that draws one is one binomial call over the wave.  An item
+// with n < 0, K < 1 or a weight that is negative or not finite gets -1 in
+// every component and draws nothing.
+__global__ __launch_bounds__(512) void k_step_multinomial(Meta* meta, float* pool, uint32_t W,
+                                                          uint32_t n_items, const int32_t* offsets,
+                                                          const int32_t* n_in, const float* w_in,
+                                                          int32_t* out) {
+    const uint32_t unit = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (unit * 64 >= n_items) return;
+    const uint32_t c = unit * 64 + lane_id();
+    const bool act = c < n_items;
+    DirectReader<KIND_U> r;
+    r.open(meta[unit], pool + (size_t)unit * W, W);
+    int32_t off = 0, K = 0, rem = -1;
+    if (act) {
+        off = offsets[c];
+        K = offsets[c + 1] - off;
+        rem = n_in[c];
+    }
+    bool ok = act && rem >= 0 && K >= 1;
+    double S = 0.0;
+    for (int32_t j = 0; ok && j < K; ++j) {
+        const double wj = (double)w_in[off + j];
+        ok = wj >= 0.0 && wj < INFINITY;
+        S += wj;
+    }
+    const int32_t kmax = wave_minmax<true>(ok ? K : 0);
+    for (int32_t k = 0; k + 1 < kmax; ++k) {
+        const bool draw = ok && k + 1 < K;
+        double q = 0.0;
+        if (draw) {
+            const double wk = (double)w_in[off + k];
+            q = S > 0.0 ? wk / S : 0.0;
+            q = q > 1.0 ? 1.0 : q;
+            S -= wk;
+        }
+        const int32_t x = binomial_call(r, rem, q, draw);
+        if (draw) {
+            out[off + k] = x;
+            rem -= x;
+        }
+    }
+    if (ok)
+        out[off + K - 1] = rem;
+    else if (act)
+        for (int32_t j = 0; j < K; ++j) out[off + j] = -1;
     r.close(meta[unit]);
 }
 
@@ -834,6 +895,19 @@ brng_status brng_step_binomial(brng_ctx* c, const int32_t* n, const float* p, in
     hipLaunchKernelGGL(k_step_binomial, unit_grid(c, c->n_units), dim3(64 * c->wpb), 0, c->stream,
                        c->meta, (float*)c->pool[BRNG_U], c->cfg.window[BRNG_U], c->cfg.n_chains,
                        n, p, out);
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
+
+brng_status brng_step_multinomial(brng_ctx* c, const int32_t* offsets, const int32_t* n,
+                                  const float* w, int32_t* out) {
+    if (!c || !offsets || !n || !w || !out) return BRNG_E_ARG;
+    if (c->cfg.layout != BRNG_LAYOUT_CHAINS) return BRNG_E_ARG;
+    if (c->cfg.prec != BRNG_F32) return BRNG_E_UNSUPPORTED;
+    if (!c->cfg.window[BRNG_U]) return BRNG_E_KIND_DISABLED;
+    hipLaunchKernelGGL(k_step_multinomial, unit_grid(c, c->n_units), dim3(64 * c->wpb), 0,
+                       c->stream, c->meta, (float*)c->pool[BRNG_U], c->cfg.window[BRNG_U],
+                       c->cfg.n_chains, offsets, n, w, out);
     HIPCHK(hipGetLastError());
     return BRNG_OK;
 }

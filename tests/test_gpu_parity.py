@@ -234,6 +234,56 @@ def test_step_binomial(dev):
         b.brng_destroy(ctx)
 
 
+def test_step_multinomial(dev):
+    """Conditional-binomial multinomial steps: 1,017 items with 1..40
+    components (and one of 300), n up to 1e5, weights with zeros, and invalid
+    items; five calls through 512-entry windows; counts and cursors
+    bit-exact, flips only where the oracle's margin allows."""
+    import torch
+    b = _b()
+    ni, seed = 1000 + 17, 63
+    rng = np.random.default_rng(10)
+    K = rng.integers(1, 41, ni)
+    K[5] = 300
+    n = np.floor(np.exp(rng.uniform(0, np.log(1e5), ni))).astype(np.int32)
+    off = np.concatenate([[0], np.cumsum(K)]).astype(np.int32)
+    w = rng.exponential(size=int(off[-1])).astype(np.float32)
+    w[rng.uniform(size=w.size) < 0.1] = 0.0
+    n[7] = -1
+    w[off[9]] = -1.0
+    w[off[11]] = np.nan
+    _say("step_multinomial", ni, seed)
+    ctx = _ctx(seed, ni, W_SMALL)
+    cur = oracle.new_cursors((ni + 63) // 64)
+    out = torch.zeros(int(off[-1]), dtype=torch.int32, device=dev)
+    unit_of_comp = np.repeat(np.arange(ni) // 64, K)
+    units = np.arange(ni) // 64
+    flipped = set()
+    try:
+        toff, tn, tw = _t(off, dev), _t(n, dev), _t(w, dev)
+        for it in range(5):
+            b.brng_step_multinomial(ctx, toff, tn, tw, out)
+            x, margin = oracle.step_multinomial(seed, cur, off, n, w.astype(np.float64))
+            g = _np(out)
+            for u in np.unique(unit_of_comp[g != x]):
+                if u in flipped:
+                    continue
+                assert margin[units == u].min() <= 1.0, (it, u)
+                flipped.add(int(u))
+            ok = np.array([u not in flipped for u in unit_of_comp])
+            assert np.array_equal(g[ok], x[ok])
+        sums = np.add.reduceat(g, off[:-1])
+        good = np.array([i not in (7, 9, 11) for i in range(ni)])
+        assert np.array_equal(sums[good], n[good])
+        assert np.all(g[off[7]:off[8]] == -1)
+        got = b.brng_get_cursors(ctx)
+        keep = np.array([u not in flipped for u in range(got.shape[0])])
+        assert np.array_equal(got[keep], cur[keep])
+        assert len(flipped) <= 1
+    finally:
+        b.brng_destroy(ctx)
+
+
 def test_step_dirichlet_ragged(dev):
     b = _b()
     it = workloads.dirichlet_items(150, kmin=1, kmax=300, seed=3)
