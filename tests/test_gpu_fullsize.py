@@ -4,9 +4,10 @@ launch after the bulk refills, as bench.py times it.
 
 - normal/exponential chains: 65,536 chains x 1,000 steps, window 4,096;
 - gamma chains: 262,144 chains of lengths U{50..1000}, slots sorted by
-  length, window 512, eight waves per block (the autotuner's usual choice);
-- LDA: 16,384 documents x 100 sweeps, window 512, eight waves per block,
-  documents in the work order the bench uses.
+  length, window 512, eight waves per block requested (the autotuner's usual
+  choice; the launch fits four in its LDS);
+- LDA: 16,384 documents x 100 sweeps, window 512, eight waves per block
+  requested, documents in the work order the bench uses.
 
 Every test prints its case before the GPU calls."""
 import numpy as np
