@@ -504,9 +504,10 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
     const int32_t off = D.offsets[doc];
     const int K = D.offsets[doc + 1] - off;
     const int ntok = D.ntok[doc];
-    // first step of the bin search: the largest power of two <= K - 1 (the
-    // answer is at most K - 1, and the steps add up to at least that)
-    const int kstep = K > 1 ? (int)(0x80000000u >> __builtin_clz((uint32_t)(K - 1))) : 0;
+    // first step of the bin search, kstep = 2^kexp: the largest power of
+    // two <= K - 1 (the answer is at most K - 1, and the steps add up to at
+    // least that); kexp = -1 for K = 1, which needs no step
+    const int kexp = K > 1 ? 31 - (int)__builtin_clz((uint32_t)(K - 1)) : -1;
     LdaRN rn;
     LdaRE re;
     LdaRU ru;
@@ -524,10 +525,14 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
     // the current sweep's rows; one row further per sweep
     float* thp = want_th ? reinterpret_cast<float*>(D.trace) + off + lane : nullptr;
     int32_t* ctp = want_ct ? reinterpret_cast<int32_t*>(D.trace2) + off + lane : nullptr;
+    // bin ends past the last component hold a value above every token's
+    // t (t < Q <= 2^24 + K), so a probe there never passes and the search
+    // needs no clamp
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int k = b * 64 + (int)lane;
         if (comp_in(K, b, lane)) cnt[k] = counts[k];
+        else Cs[k] = 0x7fffffff;
     }
     for (int32_t sw = 0; sw < D.max_steps; ++sw) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -589,10 +594,12 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
         // Token u -> t = (j Q) >> 23 with j = (u 2^24 - 1) / 2, then the
         // first k with t < C_k, i.e. the number of k with C_k <= t (the C_k
         // do not decrease and C_{K-1} = Q > t): binary lifting over the
-        // power-of-two steps down from kstep, the same count of steps in
-        // every lane; a probe past the end reads C_{K-1}, which never
-        // passes.  Calls are taken two at a time (in call order) so that the
-        // two searches' LDS reads overlap.
+        // power-of-two steps 2^e, e = kexp .. 0, the same count of steps in
+        // every lane.  The steps are unrolled from the largest possible one
+        // (2^7; K <= 256) and those above kstep skipped as a wave, so each
+        // probe is an LDS read at a fixed offset from the position reached
+        // (at most 2 kstep - 2 <= 254).  Calls are taken two at a time (in
+        // call order) so that the two searches' LDS reads overlap.
         for (int i0 = 0; i0 < ntok; i0 += 128) {
             const bool act0 = i0 + (int)lane < ntok;
             const bool act1 = i0 + 64 + (int)lane < ntok;
@@ -602,15 +609,20 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
                 (uint32_t)(((uint64_t)((((uint32_t)(u0 * 16777216.0f)) - 1u) >> 1) * (uint32_t)Q) >> 23);
             const uint32_t t1 =
                 (uint32_t)(((uint64_t)((((uint32_t)(u1 * 16777216.0f)) - 1u) >> 1) * (uint32_t)Q) >> 23);
-            int p0 = 0, p1 = 0;
-            for (int step = kstep; step > 0; step >>= 1) {
-                const uint32_t c0 = (uint32_t)Cs[min(p0 + step, K) - 1];
-                const uint32_t c1 = (uint32_t)Cs[min(p1 + step, K) - 1];
-                p0 += c0 <= t0 ? step : 0;
-                p1 += c1 <= t1 ? step : 0;
-            }
-            if (act0) atomicAdd(&cnt[p0], 1);
-            if (act1) atomicAdd(&cnt[p1], 1);
+            int32_t* p0 = Cs;  // bin end of the position reached
+            int32_t* p1 = Cs;
+            static_for<0, 8>([&](auto jc) {
+                constexpr int e = 7 - decltype(jc)::value;
+                if (e <= kexp) {
+                    const uint32_t c0 = (uint32_t)p0[(1 << e) - 1];
+                    const uint32_t c1 = (uint32_t)p1[(1 << e) - 1];
+                    p0 += c0 <= t0 ? (1 << e) : 0;
+                    p1 += c1 <= t1 ? (1 << e) : 0;
+                }
+            });
+            // the counts sit LDA_KMAX entries past the bin ends
+            if (act0) atomicAdd(p0 + LDA_KMAX, 1);
+            if (act1) atomicAdd(p1 + LDA_KMAX, 1);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
