@@ -458,24 +458,63 @@ def test_lda(dev):
         _gibbs(ctx, b.BRNG_MODEL_LDA, nd, counts, w["sweeps"], seed, dev, th, ct, total,
                offsets=_t(w["offsets"], dev), ntok=_t(w["ntok"], dev))
         r = oracle.lda(seed, w["offsets"], w["ntok"], w["sweeps"])
-        gth, gct = _np(th), _np(ct)
-        off = w["offsets"]
-        diverged = 0
-        for d in range(nd):
-            a, z = off[d], off[d + 1]
-            for s in range(w["sweeps"]):
-                okt = within(gth[s, a:z], r["theta"][s, a:z], r["theta_tol"][s, a:z]).all()
-                okc = np.array_equal(gct[s, a:z], r["ctrace"][s, a:z])
-                if okt and okc:
-                    continue
-                # only a decision within tolerance may change the course
-                if not okt:
-                    assert r["gmargin"][s, d] <= 1.0, (d, s)
-                else:
-                    assert r["mmargin"][s, d] <= 0.0, (d, s)
-                diverged += 1
-                break
+        diverged = _lda_diverged(_np(th), _np(ct), r, w["offsets"], w["sweeps"])
         print("lda diverged docs", diverged, flush=True)
+        assert diverged <= 2
+    finally:
+        b.brng_destroy(ctx)
+
+
+def _lda_diverged(gth, gct, r, off, sweeps):
+    """Documents whose theta or counts left the oracle's, each at a decision
+    within tolerance (asserted); the others match in every sweep."""
+    diverged = 0
+    for d in range(len(off) - 1):
+        a, z = off[d], off[d + 1]
+        for s in range(sweeps):
+            okt = within(gth[s, a:z], r["theta"][s, a:z], r["theta_tol"][s, a:z]).all()
+            okc = np.array_equal(gct[s, a:z], r["ctrace"][s, a:z])
+            if okt and okc:
+                continue
+            # only a decision within tolerance may change the course
+            if not okt:
+                assert r["gmargin"][s, d] <= 1.0, (d, s)
+            else:
+                assert r["mmargin"][s, d] <= 0.0, (d, s)
+            diverged += 1
+            break
+    return diverged
+
+
+def test_lda_ragged_components_and_tokens(dev):
+    """Component counts across the bin search's step boundaries (1, 2, 3,
+    powers of two and their neighbours up to 256) and token counts at the
+    edges of the two-calls-at-a-time token loop (0, 1, 63..65, 127..129,
+    255..257), against the oracle."""
+    import torch
+    b = _b()
+    Ks = [1, 2, 3, 4, 5, 7, 8, 9, 15, 17, 31, 33, 63, 64, 65, 100, 127, 128, 129, 200, 255, 256]
+    toks = [0, 1, 63, 64, 65, 127, 128, 129, 255, 256, 257, 200]
+    K = np.array([Ks[i % len(Ks)] for i in range(2 * len(Ks))], dtype=np.int32)
+    ntok = np.array([toks[i % len(toks)] for i in range(len(K))], dtype=np.int32)
+    off = np.zeros(len(K) + 1, dtype=np.int32)
+    off[1:] = np.cumsum(K)
+    nd, total, sweeps, seed = len(K), int(off[-1]), 5, 909
+    _say("lda ragged K", nd, sweeps, seed)
+    ctx = _ctx(seed, nd, W_SMALL, layout=1)
+    counts = torch.zeros(total, dtype=torch.int32, device=dev)
+    th = torch.zeros((sweeps, total), dtype=torch.float32, device=dev)
+    ct = torch.zeros((sweeps, total), dtype=torch.int32, device=dev)
+    try:
+        _gibbs(ctx, b.BRNG_MODEL_LDA, nd, counts, sweeps, seed, dev, th, ct, total,
+               offsets=_t(off, dev), ntok=_t(ntok, dev))
+        gct = _np(ct)
+        r = oracle.lda(seed, off, ntok, sweeps)
+        diverged = _lda_diverged(_np(th), gct, r, off, sweeps)
+        # every sweep's counts add up to the document's tokens
+        for d in range(nd):
+            assert (gct[:, off[d]:off[d + 1]].sum(axis=1) == ntok[d]).all(), d
+        print("lda ragged diverged docs", diverged, flush=True)
         assert diverged <= 2
     finally:
         b.brng_destroy(ctx)
