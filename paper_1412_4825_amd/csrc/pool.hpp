@@ -51,12 +51,6 @@ __device__ __forceinline__ uint32_t mask_rank(uint64_t m) {
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
-__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
 // Wave-cooperative generation of `nblocks` blocks starting at block `b0`
 // into `dst` (16 bytes per block, 64 lanes write 1 KiB per instruction).
 template <uint32_t KIND>
