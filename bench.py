@@ -16,7 +16,9 @@ alpha_{t+1} = 0.1 + g_t), lda (16,384 documents, Dirichlet + multinomial,
 100 sweeps), served (the mixed request stream alone).
 
 Prints one JSON line: deviates/s, the roofline of the dominant kernel
-(algorithmic bytes over its event-timed duration against 8 TB/s), the CPU
+(algorithmic bytes over its duration against 8 TB/s; the duration from HIP
+events that the launch itself records at the kernel's start and end, with
+the span of the call on the stream beside it), the CPU
 oracle timed on the host over the workload or a stated sample of it, and
 (unless --no-served) the served form against per-request plain launches on
 a mixed request stream: throughput with every request queued, and p50/p99
@@ -601,16 +603,27 @@ def main():
     b.brng_set_launch(ctx, args.wpb)
     ev = Events(torch)
 
-    def step():
+    def step(kpair=None):
         for k in Wk["kinds"]:
             b.brng_fill_base(ctx, k)
-        e = ev.span("chains")
+        # the chain kernel's own start and end (events the launch records),
+        # and the span of the call on the stream (which adds the dispatch gap)
+        if kpair is not None:
+            b.brng_time_next_launch(ctx, *kpair)
+            ev.pairs.setdefault("chains", []).append(kpair)
+        e = ev.span("chains_span")
         b.brng_run_gibbs(ctx, Wk["resume"])
         e.record()
 
     b.brng_run_gibbs(ctx, Wk["fresh"])  # fresh start: streams at 0
     for _ in range(max(0, args.warmup - 1)):
         step()
+    # kernel event pairs, created (recorded once) before the timed region
+    kpairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    for kp in kpairs:
+        for e in kp:
+            e.record()
     torch.cuda.synchronize()
     ev.pairs.clear()
     cur0 = b.brng_get_cursors(ctx)
@@ -619,8 +632,8 @@ def main():
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     start.record()
-    for _ in range(args.steps):
-        step()
+    for i in range(args.steps):
+        step(kpairs[i])
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -641,11 +654,13 @@ def main():
     step_b = pool_b + Wk["out_bytes"]
     chain_b = step_b - fill_b
     chain_ms = float(np.mean(ev.ms("chains")))
+    span_ms = float(np.mean(ev.ms("chains_span")))
     gbs = chain_b / (chain_ms / 1e3) / 1e9
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(Wk["kernel"]),
             "kernel": Wk["kernel"],
-            "kernel_ms": round(chain_ms, 4), "alg_bytes_per_launch": chain_b}
+            "kernel_ms": round(chain_ms, 4), "call_span_ms": round(span_ms, 4),
+            "alg_bytes_per_launch": chain_b}
     # context: what a plain copy reaches on this GPU
     cgbs = copy_bandwidth(torch, b)
     roof["copy_gbs"] = round(cgbs, 1)

@@ -278,6 +278,18 @@ brng_status brng_get_info(const brng_ctx *ctx, uint32_t *n_units, uint32_t *wind
  * Errors: BRNG_E_ARG. */
 brng_status brng_set_launch(brng_ctx *ctx, int32_t waves_per_block, int32_t reserved);
 
+/* Measurement support (no passage of the paper; for timing the chain
+ * kernel alone, as the paper times its generators).  start_event and
+ * stop_event are hipEvent_t handles the caller created with timing enabled
+ * and owns.  The next brng_run_gibbs call in the plain form (one request)
+ * launches its chain kernel so that start_event is recorded when the kernel
+ * starts and stop_event when it ends: their elapsed time is the kernel's own
+ * duration, without the dispatch gap that events recorded on the stream
+ * around the call include.  The pair is used once and then forgotten; a
+ * batched call leaves it pending.  Both NULL clears a pending pair.
+ * Errors: BRNG_E_ARG (NULL ctx, or exactly one event NULL). */
+brng_status brng_time_next_launch(brng_ctx *ctx, void *start_event, void *stop_event);
+
 /* ---------------------------------------------------------------------- */
 /* Served form: a request loop with continuous batching.  Requests (one    */
 /* brng_gibbs_desc each) arrive at any time; the server admits them while  */

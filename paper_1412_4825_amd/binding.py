@@ -32,7 +32,8 @@ EXPORTS = [
     "brng_step_binomial", "brng_step_multinomial",
     "brng_step_dirichlet", "brng_run_gibbs",
     "brng_sort_by_length", "brng_get_cursors", "brng_set_cursors", "brng_get_window",
-    "brng_get_info", "brng_set_launch", "brng_status_string", "brng_last_hip_error",
+    "brng_get_info", "brng_set_launch", "brng_time_next_launch", "brng_status_string",
+    "brng_last_hip_error",
     "brng_convert", "brng_serve_open", "brng_serve_now", "brng_serve_submit",
     "brng_serve_progress", "brng_serve_poll", "brng_serve_stats_get", "brng_serve_close",
 ]
@@ -151,6 +152,7 @@ def _load():
                                   C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)]
     L.brng_get_info.argtypes = [vp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
     L.brng_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
+    L.brng_time_next_launch.argtypes = [vp, vp, vp]
     L.brng_convert.argtypes = [C.c_int32, vp, C.c_uint64, vp, vp]
     L.brng_serve_open.argtypes = [C.POINTER(brng_serve_config), C.POINTER(vp)]
     L.brng_serve_now.argtypes = []
@@ -345,6 +347,21 @@ def brng_get_window(ctx: int, kind: int, unit: int):
 
 def brng_set_launch(ctx: int, waves_per_block: int) -> None:
     _check(_lib.brng_set_launch(ctx, waves_per_block, 0), "brng_set_launch")
+
+
+def brng_time_next_launch(ctx: int, start=None, stop=None) -> None:
+    """Record two timing events (torch.cuda.Event with enable_timing, or raw
+    hipEvent_t handles) at the start and end of the next plain chain launch;
+    no events clears a pending pair."""
+    def handle(e):
+        if e is None:
+            return None
+        if not hasattr(e, "cuda_event"):
+            return int(e)
+        if not e.cuda_event:  # torch creates the HIP event at its first record
+            e.record()
+        return e.cuda_event
+    _check(_lib.brng_time_next_launch(ctx, handle(start), handle(stop)), "brng_time_next_launch")
 
 
 def brng_convert(kind: int, words, n_words: int, out, stream=None) -> None:

@@ -8,6 +8,7 @@
 //                    of Sec. 1 with the reducible transforms of Sec. 2.1)
 //   k_gibbs<M>       all steps of every chain of one request
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cstdio>
@@ -596,6 +597,8 @@ struct brng_ctx {
     Meta* meta;
     int wpb;
     int n_cu;
+    // events for the next plain chain launch (brng_time_next_launch)
+    hipEvent_t t_start = nullptr, t_stop = nullptr;
 };
 
 static thread_local int32_t g_last_hip = 0;
@@ -977,23 +980,26 @@ static brng_status launch_plain(brng_ctx* c, const DescDev& D) {
     const dim3 grid((D.n_units + wpb - 1) / wpb), block(64 * wpb);
     const size_t lds = (size_t)wpb * model_lds_bytes(D.model);
     const Pools P = make_pools(c);
+    // with a pending event pair the launch records them at the kernel's own
+    // start and end (then forgets them)
+    hipEvent_t ts = c->t_start, te = c->t_stop;
+    c->t_start = c->t_stop = nullptr;
+#define BRNG_LAUNCH_GIBBS(MODEL)                                                               \
+    do {                                                                                      \
+        if (ts)                                                                               \
+            hipExtLaunchKernelGGL(k_gibbs<MODEL>, grid, block, (uint32_t)lds, c->stream, ts,  \
+                                  te, 0u, D, c->meta, P);                                     \
+        else                                                                                  \
+            hipLaunchKernelGGL(k_gibbs<MODEL>, grid, block, lds, c->stream, D, c->meta, P);   \
+    } while (0)
     switch (D.model) {
-        case M_TRIANGLE:
-            hipLaunchKernelGGL(k_gibbs<M_TRIANGLE>, grid, block, lds, c->stream, D, c->meta, P);
-            break;
-        case M_NORMEXP:
-            hipLaunchKernelGGL(k_gibbs<M_NORMEXP>, grid, block, lds, c->stream, D, c->meta, P);
-            break;
-        case M_GAMMA:
-            hipLaunchKernelGGL(k_gibbs<M_GAMMA>, grid, block, lds, c->stream, D, c->meta, P);
-            break;
-        case M_LDA:
-            hipLaunchKernelGGL(k_gibbs<M_LDA>, grid, block, lds, c->stream, D, c->meta, P);
-            break;
-        default:
-            hipLaunchKernelGGL(k_gibbs<M_EXPCHAIN>, grid, block, lds, c->stream, D, c->meta, P);
-            break;
+        case M_TRIANGLE: BRNG_LAUNCH_GIBBS(M_TRIANGLE); break;
+        case M_NORMEXP: BRNG_LAUNCH_GIBBS(M_NORMEXP); break;
+        case M_GAMMA: BRNG_LAUNCH_GIBBS(M_GAMMA); break;
+        case M_LDA: BRNG_LAUNCH_GIBBS(M_LDA); break;
+        default: BRNG_LAUNCH_GIBBS(M_EXPCHAIN); break;
     }
+#undef BRNG_LAUNCH_GIBBS
     HIPCHK(hipGetLastError());
     return BRNG_OK;
 }
@@ -1141,6 +1147,13 @@ brng_status brng_get_info(const brng_ctx* c, uint32_t* n_units, uint32_t* window
 brng_status brng_set_launch(brng_ctx* c, int32_t wpb, int32_t reserved) {
     if (!c || !(wpb == 1 || wpb == 2 || wpb == 4 || wpb == 8) || reserved != 0) return BRNG_E_ARG;
     c->wpb = wpb;
+    return BRNG_OK;
+}
+
+brng_status brng_time_next_launch(brng_ctx* c, void* start_event, void* stop_event) {
+    if (!c || (start_event == nullptr) != (stop_event == nullptr)) return BRNG_E_ARG;
+    c->t_start = static_cast<hipEvent_t>(start_event);
+    c->t_stop = static_cast<hipEvent_t>(stop_event);
     return BRNG_OK;
 }
 

@@ -419,8 +419,8 @@ __device__ void unit_expchain(const DescDev& D, Meta* mp, const Pools& P, uint32
 // Each lane runs its chain through the gamma rounds and starts its next step
 // as soon as a draw is accepted.
 // ---------------------------------------------------------------------------
-using GammaRN = EpochReader<KIND_N, 1>;
-using GammaRE = EpochReader<KIND_E, 2>;
+using GammaRN = EpochReader<KIND_N, 1, true>;
+using GammaRE = EpochReader<KIND_E, 2, true>;
 constexpr int GAMMA_OBUF_BYTES = TRACE_ROWS * 64 * 4;
 constexpr int GAMMA_LDS_BYTES = GammaRN::LDS_BYTES + GammaRE::LDS_BYTES + GAMMA_OBUF_BYTES;
 // An epoch's worst case fits the rings (a round takes at most one Gaussian

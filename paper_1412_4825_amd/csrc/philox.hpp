@@ -51,6 +51,35 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     return make_uint4(c0, c1, c2, c3);
 }
 
+// Two counters under one key schedule (the key words advance once for both):
+// what a lane computes when it regenerates two blocks of one window.
+template <bool KEYS_AT_USE = false>
+__device__ __forceinline__ void philox10x2(uint32_t (&a)[4], uint32_t (&b)[4], uint32_t k0,
+                                           uint32_t k1) {
+    if (KEYS_AT_USE) asm volatile("" : "+s"(k0), "+s"(k1));
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa0 = (uint64_t)a[0] * 0xD2511F53u;
+        const uint64_t pa1 = (uint64_t)a[2] * 0xCD9E8D57u;
+        const uint64_t pb0 = (uint64_t)b[0] * 0xD2511F53u;
+        const uint64_t pb1 = (uint64_t)b[2] * 0xCD9E8D57u;
+        const uint32_t na0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa1 >> 32), a[1], k0, 0x96);
+        const uint32_t na2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa0 >> 32), a[3], k1, 0x96);
+        const uint32_t nb0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb1 >> 32), b[1], k0, 0x96);
+        const uint32_t nb2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb0 >> 32), b[3], k1, 0x96);
+        a[1] = (uint32_t)pa1;
+        a[3] = (uint32_t)pa0;
+        a[0] = na0;
+        a[2] = na2;
+        b[1] = (uint32_t)pb1;
+        b[3] = (uint32_t)pb0;
+        b[0] = nb0;
+        b[2] = nb2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
 template <bool KEYS_AT_USE = false>
 __device__ __forceinline__ uint4 block_words(const Key& key, uint32_t kind, uint64_t block) {
     return philox10<KEYS_AT_USE>((uint32_t)block, (uint32_t)(block >> 32), kind, key.c3, key.k0,
@@ -140,6 +169,17 @@ __device__ __forceinline__ uint4 convert_block(const uint4 w) {
 template <uint32_t KIND, bool KEYS_AT_USE = false>
 __device__ __forceinline__ uint4 gen_block(const Key& key, uint64_t block) {
     return convert_block<KIND>(block_words<KEYS_AT_USE>(key, KIND, block));
+}
+
+// Pool blocks `ba` and `bb` of (key, KIND), converted, with one key schedule.
+template <uint32_t KIND, bool KEYS_AT_USE = false>
+__device__ __forceinline__ void gen_block2(const Key& key, uint64_t ba, uint64_t bb, uint4& va,
+                                           uint4& vb) {
+    uint32_t a[4] = {(uint32_t)ba, (uint32_t)(ba >> 32), KIND, key.c3};
+    uint32_t b[4] = {(uint32_t)bb, (uint32_t)(bb >> 32), KIND, key.c3};
+    philox10x2<KEYS_AT_USE>(a, b, key.k0, key.k1);
+    va = convert_block<KIND>(make_uint4(a[0], a[1], a[2], a[3]));
+    vb = convert_block<KIND>(make_uint4(b[0], b[1], b[2], b[3]));
 }
 
 template <uint32_t KIND> struct KindTraits {

@@ -235,8 +235,12 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // If a call needs more than the ring holds, it stages at once (correct,
 // only slower); sized so that an epoch's worst case fits, that never happens.
 // ---------------------------------------------------------------------------
-template <uint32_t KIND, int CHV>
+// PAIRED: a regenerating lane computes its blocks two at a time under one key
+// schedule (fewer scalar instructions, more code and registers; it pays off
+// for a kernel with two readers, not with three).
+template <uint32_t KIND, int CHV, bool PAIRED = false>
 struct EpochReader {
+    static_assert(CHV == 1 || CHV == 2, "a chunk is one or two blocks per lane");
     using T = typename KindTraits<KIND>::T;
     static constexpr int EPB = KindTraits<KIND>::EPB;
     static constexpr uint32_t CH = 64u * EPB * CHV;
@@ -283,17 +287,37 @@ struct EpochReader {
             // keeps the compiler from moving memory operations across.
             const uint32_t lane = lane_id();
             const uint64_t b0 = staged / EPB;
-            const uint32_t nblk = W / EPB;
             uint4* wd = reinterpret_cast<uint4*>(win);
             u32x4 tmp[CHV];
+            if constexpr (PAIRED) {
+                // blocks two at a time; a window has a whole number of
+                // 64-block groups, at least two
+                const uint32_t ng = W / EPB / 64;
+                uint4 va, vb;
+                gen_block2<KIND, true>(key, b0 + lane, b0 + 64 + lane, va, vb);
+                wd[lane] = va;
+                wd[64 + lane] = vb;
+                tmp[0] = u32x4{va.x, va.y, va.z, va.w};
+                if constexpr (CHV == 2) tmp[1] = u32x4{vb.x, vb.y, vb.z, vb.w};
+                uint32_t g = 2;
+                for (; g + 1 < ng; g += 2) {
+                    gen_block2<KIND, true>(key, b0 + g * 64 + lane, b0 + (g + 1) * 64 + lane, va,
+                                           vb);
+                    wd[g * 64 + lane] = va;
+                    wd[(g + 1) * 64 + lane] = vb;
+                }
+                if (g < ng) wd[g * 64 + lane] = gen_block<KIND, true>(key, b0 + g * 64 + lane);
+            } else {
+                const uint32_t nblk = W / EPB;
 #pragma unroll
-            for (int j = 0; j < CHV; ++j) {
-                const uint4 v = gen_block<KIND, true>(key, b0 + (uint32_t)(j * 64) + lane);
-                wd[j * 64 + lane] = v;
-                tmp[j] = u32x4{v.x, v.y, v.z, v.w};
+                for (int j = 0; j < CHV; ++j) {
+                    const uint4 v = gen_block<KIND, true>(key, b0 + (uint32_t)(j * 64) + lane);
+                    wd[j * 64 + lane] = v;
+                    tmp[j] = u32x4{v.x, v.y, v.z, v.w};
+                }
+                for (uint32_t b = (uint32_t)(CHV * 64) + lane; b < nblk; b += 64)
+                    wd[b] = gen_block<KIND, true>(key, b0 + b);
             }
-            for (uint32_t b = (uint32_t)(CHV * 64) + lane; b < nblk; b += 64)
-                wd[b] = gen_block<KIND, true>(key, b0 + b);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             wbase = staged;
             wlen = W;

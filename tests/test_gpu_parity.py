@@ -706,3 +706,52 @@ def test_conversions_exhaustive_grid(dev):
         assert not bad.any(), (np.flatnonzero(bad)[:5], got[bad][:5], ref[bad][:5])
     pair = np.random.default_rng(3).integers(0, 2**32, size=1 << 22, dtype=np.uint64).astype(np.uint32)
     assert np.array_equal(_convert_gpu(dev, 3, pair), oracle.convert(3, pair))
+
+
+def test_time_next_launch_brackets_the_chain_kernel(dev):
+    """Events handed to brng_time_next_launch are recorded at the chain
+    kernel's start and end: their interval is positive and lies inside the
+    span of the call on the stream; the pair is used once (a second launch
+    leaves the events as they were), and the results equal an untimed run."""
+    import torch
+    b = _b()
+    w = workloads.gamma_chain(n_chains=4096, lmin=50, lmax=300, seed=3)
+    n, smax, seed = w["n_chains"], int(w["steps"].max()), 31
+    _say("timed chain launch", n, smax)
+    outs = []
+    for timed in (False, True):
+        ctx = _ctx(seed, n, W_SMALL)
+        st = _t(w["alpha0"], dev)
+        tg = torch.zeros((smax, n), dtype=torch.float32, device=dev)
+        try:
+            kw = dict(max_steps=smax, seed=seed, trace=tg, trace_stride=n,
+                      steps=_t(w["steps"], dev))
+            if timed:
+                k0 = torch.cuda.Event(enable_timing=True)
+                k1 = torch.cuda.Event(enable_timing=True)
+                s0 = torch.cuda.Event(enable_timing=True)
+                s1 = torch.cuda.Event(enable_timing=True)
+                b.brng_time_next_launch(ctx, k0, k1)
+                s0.record()
+            b.brng_run_gibbs(ctx, b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, n, st, **kw))
+            if timed:
+                s1.record()
+                torch.cuda.synchronize()
+                kms, sms = k0.elapsed_time(k1), s0.elapsed_time(s1)
+                print("kernel ms", kms, "span ms", sms, flush=True)
+                assert 0.0 < kms <= sms * 1.001 + 1e-3
+                outs.append((_np(tg), _np(st)))
+                # used once: a second (resumed) launch does not move them
+                b.brng_run_gibbs(ctx, b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, n, st,
+                                                   flags=b.BRNG_FLAG_RESUME, **kw))
+                torch.cuda.synchronize()
+                assert k0.elapsed_time(k1) == kms
+                # a lone event is refused
+                with pytest.raises(b.BrngError):
+                    b.brng_time_next_launch(ctx, k0, None)
+            else:
+                outs.append((_np(tg), _np(st)))
+        finally:
+            b.brng_destroy(ctx)
+    assert np.array_equal(outs[0][0], outs[1][0], equal_nan=True)
+    assert np.array_equal(outs[0][1], outs[1][1])
