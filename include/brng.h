@@ -136,7 +136,8 @@ brng_status brng_step_weibull(brng_ctx *ctx, const float *d_lambda, const float 
  * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_UNSUPPORTED, BRNG_E_HIP. */
 brng_status brng_step_poisson(brng_ctx *ctx, const float *d_lambda, int32_t *d_out);
 
-/* Binomial(n, p), the second discrete getter: one draw per chain from the
+/* Binomial(n, p), the second discrete getter (the discrete library of Sec.
+ * 3's future work): one draw per chain from the
  * uniform pool, computed in double precision; d_n holds n_chains trial
  * counts (int32), d_p n_chains probabilities (float), d_out n_chains int32
  * results.  With p' = min(p, 1 - p) the draw is made for p' and mirrored
@@ -228,7 +229,9 @@ typedef struct {
     const int32_t *d_ntok;    /* LDA: tokens per document */
 } brng_gibbs_desc;
 
-/* Run chains to completion on the context's stream.  Each request is one
+/* Run chains to completion on the context's stream: the one-at-a-time loop
+ * of Sec. 1 (Eq. 1 / Fig. 1, the Dirichlet redraws of its footnote) for
+ * many chains at once.  Each request is one
  * launch of its model's kernel (one wave per unit, every step of every chain
  * inside that launch); several requests run back to back on the stream.
  * Each request's units [unit_base, unit_base + n_units) must lie inside the
@@ -239,28 +242,33 @@ typedef struct {
  * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_HIP. */
 brng_status brng_run_gibbs(brng_ctx *ctx, const brng_gibbs_desc *h_descs, uint32_t n_desc);
 
-/* Slot order for uneven chain lengths: perm[p] = chain in slot p, chains
+/* A scheduling aid with no counterpart in the paper.  Slot order for uneven
+ * chain lengths: perm[p] = chain in slot p, chains
  * stably sorted by descending steps (so a unit's lanes finish together).
  * Host arrays of n entries.  Errors: BRNG_E_ARG. */
 brng_status brng_sort_by_length(uint32_t n, const int32_t *h_steps, int32_t *h_perm);
 
-/* Copy the cursors to the host as uint64[n_units][4] (waits for the
+/* The buffer counters of Sec. 2.2, one per unit and kind.  Copy the cursors
+ * to the host as uint64[n_units][4] (waits for the
  * stream).  Errors: BRNG_E_ARG, BRNG_E_HIP. */
 brng_status brng_get_cursors(brng_ctx *ctx, uint64_t *h_out);
 
-/* Restore cursors (checkpoint/resume): uint64[n_units][4]; invalidates the
+/* Restore the buffer counters of Sec. 2.2 (checkpoint/resume, a library
+ * addition): uint64[n_units][4]; invalidates the
  * windows, which the next call regenerates from the cursors.  Units keep
  * their stream keys.  Errors: BRNG_E_ARG, BRNG_E_HIP. */
 brng_status brng_set_cursors(brng_ctx *ctx, const uint64_t *h_in);
 
-/* Copy unit `unit`'s current window of `kind` to the host: *h_base gets the
+/* The buffer contents of Sec. 2.2.  Copy unit `unit`'s current window of
+ * `kind` to the host: *h_base gets the
  * pool index of its first entry, *h_len its valid length (0 if empty), and
  * h_out up to cap entries (float, or double for U64).  Waits for the
  * stream.  Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_HIP. */
 brng_status brng_get_window(brng_ctx *ctx, int32_t kind, uint32_t unit, void *h_out,
                             uint32_t cap, uint64_t *h_base, uint32_t *h_len);
 
-/* The conversion half of the core engine on caller-supplied words: n_words
+/* The conversion half of the core engine (the reducible base distributions
+ * of Sec. 2.1) on caller-supplied words: n_words
  * 32-bit words (a multiple of 4, 16-byte aligned device arrays) become
  * n_words entries of kind U, N or E (floats; N pairs words 2i, 2i+1) or
  * n_words/2 entries of U64 (doubles), exactly as pool entries are made from
@@ -270,10 +278,14 @@ brng_status brng_get_window(brng_ctx *ctx, int32_t kind, uint32_t unit, void *h_
 brng_status brng_convert(int32_t kind, const uint32_t *d_words, uint64_t n_words, void *d_out,
                          void *stream);
 
-/* Context facts: number of units, window lengths. */
+/* Context facts (a library aid, no passage of the paper): number of units
+ * and the four window lengths (window4 holds 4 entries).  Host pointers;
+ * either may be NULL.
+ * Errors: BRNG_E_ARG. */
 brng_status brng_get_info(const brng_ctx *ctx, uint32_t *n_units, uint32_t *window4);
 
-/* Launch shape of the chain and step kernels (a tuning knob; results do not
+/* Launch shape of the chain and step kernels (a tuning knob with no
+ * counterpart in the paper; results do not
  * depend on it): waves per workgroup, 1, 2, 4 or 8; `reserved` must be 0.
  * Errors: BRNG_E_ARG. */
 brng_status brng_set_launch(brng_ctx *ctx, int32_t waves_per_block, int32_t reserved);
@@ -369,12 +381,14 @@ brng_status brng_serve_progress(brng_server *srv, int32_t wait);
  * count.  Errors: BRNG_E_ARG. */
 brng_status brng_serve_poll(brng_server *srv, brng_serve_done *h_out, uint32_t cap, uint32_t *n);
 
+/* Copy the server's counters to *h_out (host).  Errors: BRNG_E_ARG. */
 brng_status brng_serve_stats_get(const brng_server *srv, brng_serve_stats *h_out);
 
 /* Finish every queued request, then free the server.  NULL is a no-op. */
 brng_status brng_serve_close(brng_server *srv);
 
-/* Human-readable status. Never NULL. */
+/* Integer status codes, in the style of the vector-library calls shown in
+ * Sec. 1.  Human-readable status; never NULL. */
 const char *brng_status_string(brng_status s);
 /* hipError_t of the last BRNG_E_HIP in this thread (0 if none). */
 int32_t brng_last_hip_error(void);
