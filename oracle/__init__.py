@@ -384,3 +384,93 @@ def lda(seed, offsets, ntok, sweeps, counts0=None, cursors=None, unit0=0):
                  _p(gmar, _dp), _p(mmar, _dp))
     return dict(counts=counts, theta=thtr, theta_tol=thtol, ctrace=cntr, gmargin=gmar,
                 mmargin=mmar, cursors=cur)
+
+
+# --------------------------------------------------------------------------
+# Full LDA: topic-word and document-topic Dirichlets with per-token topics
+# (the motivating application of Sec. 1 and its footnote, run as the
+# uncollapsed Gibbs sampler of the LDA model: phi_k | z ~ Dir(beta + n_k.),
+# theta_d | z ~ Dir(alpha + n_d.), z_di | theta, phi ~ Cat(theta_dk phi_k,w)).
+# Units: topic k is unit k, document d is unit K + d.
+# --------------------------------------------------------------------------
+
+def lda_full_counts(K, V, doc_offsets, words, z):
+    """n_dk [D][K] and n_kw [K][V] of an assignment (plain counting; tokens
+    with z < 0 or a word outside [0, V) are not counted)."""
+    doc_offsets = np.asarray(doc_offsets, dtype=np.int64)
+    words = np.asarray(words, dtype=np.int64)
+    z = np.asarray(z, dtype=np.int64)
+    D = doc_offsets.size - 1
+    ndk = np.zeros((D, K), dtype=np.int32)
+    nkw = np.zeros((K, V), dtype=np.int32)
+    for d in range(D):
+        for i in range(doc_offsets[d], doc_offsets[d + 1]):
+            k, w = z[i], words[i]
+            if 0 <= k < K and 0 <= w < V:
+                ndk[d, k] += 1
+                nkw[k, w] += 1
+    return ndk, nkw
+
+
+def lda_full_token_topic(theta_d, phi, w, u):
+    """One token's topic from the fp32 theta row of its document, the fp32
+    topic-word matrix, its word id and its uniform u (a pool entry).  The
+    weights p_k = theta_k phi_k,w are formed in fp32 and quantised against
+    their maximum, q_k = rint(2^24 p_k / max p), so that the decision is an
+    integer one and both sides take it in the same precision; with
+    C_k = q_0 + ... + q_k, j = (u 2^24 - 1) / 2 and t = (j C_{K-1}) >> 23, the
+    topic is the first k with t < C_k (the multinomial rule of the chain
+    model, over per-token weights).  A word outside [0, V) gives -1."""
+    K, V = phi.shape
+    if not (0 <= w < V):
+        return -1
+    p = np.asarray(theta_d, dtype=np.float32) * np.asarray(phi[:, w], dtype=np.float32)
+    m = p.max()
+    if m > 0:
+        q = np.rint((p / m).astype(np.float32) * np.float32(16777216.0)).astype(np.int64)
+    else:
+        q = np.ones(K, dtype=np.int64)
+    c = np.cumsum(q)
+    j = (int(round(float(u) * 16777216.0)) - 1) >> 1
+    t = (j * int(c[-1])) >> 23
+    return int(np.searchsorted(c, t, side="right"))
+
+
+def lda_full_sweep(seed, cursors, K, V, alpha, beta, doc_offsets, words, z_in,
+                   theta32=None, phi32=None):
+    """One sweep from assignment z_in.  Topic k draws phi_k ~ Dir(beta + n_k.)
+    from its pools, document d draws theta_d ~ Dir(alpha + n_d.) from its
+    pools, then takes one uniform per token in token order and draws the
+    token's topic by lda_full_token_topic.  The shapes beta + n and alpha + n
+    are formed in fp32, as the sampler receives them.  The token step uses
+    theta32 / phi32 when given (the device's fp32 values, for replay), else
+    this sweep's own values rounded to fp32.  cursors ([K + D][4], uint64)
+    advance in place.  Returns the fp64 phi and theta with their tolerances
+    and decision margins, the new assignment and its counts."""
+    doc_offsets = np.ascontiguousarray(doc_offsets, dtype=np.int32)
+    words = np.asarray(words, dtype=np.int64)
+    D = doc_offsets.size - 1
+    ndk, nkw = lda_full_counts(K, V, doc_offsets, words, z_in)
+    a_phi = (np.float32(beta) + nkw.astype(np.float32)).astype(np.float32).ravel()
+    a_th = (np.float32(alpha) + ndk.astype(np.float32)).astype(np.float32).ravel()
+    off_phi = (np.arange(K + 1, dtype=np.int32) * V).astype(np.int32)
+    off_th = (np.arange(D + 1, dtype=np.int32) * K).astype(np.int32)
+    ct = cursors[:K]
+    cd = cursors[K:]
+    phi, phi_t, phi_m = step_dirichlet(seed, ct, off_phi, a_phi, unit0=0)
+    th, th_t, th_m = step_dirichlet(seed, cd, off_th, a_th, unit0=K)
+    phi_f = (phi.astype(np.float32) if phi32 is None else np.asarray(phi32, np.float32)).reshape(K, V)
+    th_f = (th.astype(np.float32) if theta32 is None else np.asarray(theta32, np.float32)).reshape(D, K)
+    z = np.full(words.size, -1, dtype=np.int32)
+    for d in range(D):
+        a, b = int(doc_offsets[d]), int(doc_offsets[d + 1])
+        if b == a:
+            continue
+        u = entries(seed, K + d, KIND_U, int(cd[d, KIND_U]), b - a)
+        cd[d, KIND_U] += np.uint64(b - a)
+        for i in range(a, b):
+            z[i] = lda_full_token_topic(th_f[d], phi_f, int(words[i]), u[i - a])
+    ndk2, nkw2 = lda_full_counts(K, V, doc_offsets, words, z)
+    return dict(phi=phi.reshape(K, V), phi_tol=phi_t.reshape(K, V), phi_margin=phi_m,
+                theta=th.reshape(D, K), theta_tol=th_t.reshape(D, K), theta_margin=th_m,
+                z=z, ndk=ndk2, nkw=nkw2, cursors=cursors)
