@@ -178,6 +178,46 @@ brng_status brng_step_multinomial(brng_ctx *ctx, const int32_t *d_offsets, const
 brng_status brng_step_dirichlet(brng_ctx *ctx, const int32_t *d_offsets,
                                 const float *d_alpha, float *d_out);
 
+/* Full LDA on a corpus (the model whose Dirichlet redraws motivate the
+ * method, Sec. 1 and its footnote), by the uncollapsed Gibbs sampler.  Per
+ * sweep: phi_k ~ Dir(beta + n_k.) over the vocabulary for every topic,
+ * theta_d ~ Dir(alpha + n_d.) for every document, then every token's topic
+ * z ~ Cat(theta_d,k phi_k,w), one uniform per token in token order.  The
+ * token draw quantises its fp32 weights p_k = theta_k phi_k,w against their
+ * maximum, q_k = rint(2^24 p_k / max p) (all 1 when max p = 0), and takes
+ * the first k with t < q_0 + ... + q_k, t = (j Q) >> 23, Q the sum of the
+ * q_k, j = (u 2^24 - 1) / 2.  Context: layout ITEMS, F32, kinds U, N, E
+ * enabled, at least n_topics + n_docs items; topic k is unit k, document d
+ * unit n_topics + d, and every call continues those units' streams.
+ * The state is the assignment d_z (int32 per token, in/out): a call first
+ * recounts n_dk and n_kw from it, then runs `sweeps` sweeps; on return z,
+ * n_dk ([n_docs][n_topics] int32) and n_kw ([n_topics][n_vocab] int32) are
+ * consistent, and theta ([n_docs][n_topics]) and phi ([n_topics][n_vocab])
+ * hold the last sweep's draws (float).  Tokens of document d are
+ * [d_doc_offsets[d], d_doc_offsets[d+1]) clamped to [0, n_tokens); a word
+ * id outside [0, n_vocab) gets z = -1, no count, and still takes its
+ * uniform.  All arrays are caller-owned device memory.
+ * Limits: 1 <= n_topics <= 64, 1 <= n_vocab <= 4096, alpha, beta > 0.
+ * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_UNSUPPORTED, BRNG_E_HIP. */
+typedef struct {
+    uint32_t n_docs;
+    uint32_t n_topics;
+    uint32_t n_vocab;
+    uint32_t sweeps;
+    int32_t n_tokens;
+    float alpha;               /* document-topic prior */
+    float beta;                /* topic-word prior */
+    uint32_t pad;
+    const int32_t *d_doc_offsets; /* n_docs + 1 token offsets */
+    const int32_t *d_words;    /* word id per token */
+    int32_t *d_z;              /* topic per token (in/out) */
+    int32_t *d_ndk;            /* out: [n_docs][n_topics] */
+    int32_t *d_nkw;            /* out: [n_topics][n_vocab] */
+    float *d_theta;            /* out: [n_docs][n_topics] */
+    float *d_phi;              /* out: [n_topics][n_vocab] */
+} brng_lda_full_desc;
+brng_status brng_run_lda_full(brng_ctx *ctx, const brng_lda_full_desc *h_desc);
+
 /* ---------------------------------------------------------------------- */
 /* Chain drivers (Fig. 1 generalised): many independent Gibbs chains, state */
 /* in registers, one kernel for all steps.                                */

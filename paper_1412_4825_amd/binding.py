@@ -30,7 +30,7 @@ EXPORTS = [
     "brng_create", "brng_destroy", "brng_fill_base", "brng_step_uniform", "brng_step_normal",
     "brng_step_exp", "brng_step_gamma", "brng_step_laplace", "brng_step_weibull", "brng_step_poisson",
     "brng_step_binomial", "brng_step_multinomial",
-    "brng_step_dirichlet", "brng_run_gibbs",
+    "brng_step_dirichlet", "brng_run_gibbs", "brng_run_lda_full",
     "brng_sort_by_length", "brng_get_cursors", "brng_set_cursors", "brng_get_window",
     "brng_get_info", "brng_set_launch", "brng_time_next_launch", "brng_status_string",
     "brng_last_hip_error",
@@ -67,6 +67,26 @@ class brng_gibbs_desc(C.Structure):
         ("trace_stride", C.c_int64),
         ("d_offsets", C.c_void_p),
         ("d_ntok", C.c_void_p),
+    ]
+
+
+class brng_lda_full_desc(C.Structure):
+    _fields_ = [
+        ("n_docs", C.c_uint32),
+        ("n_topics", C.c_uint32),
+        ("n_vocab", C.c_uint32),
+        ("sweeps", C.c_uint32),
+        ("n_tokens", C.c_int32),
+        ("alpha", C.c_float),
+        ("beta", C.c_float),
+        ("pad", C.c_uint32),
+        ("d_doc_offsets", C.c_void_p),
+        ("d_words", C.c_void_p),
+        ("d_z", C.c_void_p),
+        ("d_ndk", C.c_void_p),
+        ("d_nkw", C.c_void_p),
+        ("d_theta", C.c_void_p),
+        ("d_phi", C.c_void_p),
     ]
 
 
@@ -145,6 +165,7 @@ def _load():
     L.brng_step_multinomial.argtypes = [vp, vp, vp, vp, vp]
     L.brng_step_dirichlet.argtypes = [vp, vp, vp, vp]
     L.brng_run_gibbs.argtypes = [vp, C.POINTER(brng_gibbs_desc), C.c_uint32]
+    L.brng_run_lda_full.argtypes = [vp, C.POINTER(brng_lda_full_desc)]
     L.brng_sort_by_length.argtypes = [C.c_uint32, vp, vp]
     L.brng_get_cursors.argtypes = [vp, vp]
     L.brng_set_cursors.argtypes = [vp, vp]
@@ -347,6 +368,20 @@ def brng_get_window(ctx: int, kind: int, unit: int):
 
 def brng_set_launch(ctx: int, waves_per_block: int) -> None:
     _check(_lib.brng_set_launch(ctx, waves_per_block, 0), "brng_set_launch")
+
+
+def brng_run_lda_full(ctx: int, n_topics: int, n_vocab: int, sweeps: int, alpha: float,
+                      beta: float, doc_offsets, words, z, ndk, nkw, theta, phi) -> None:
+    """Full LDA sweeps over the corpus (device int32 doc_offsets, words, z;
+    outputs ndk, nkw, theta, phi)."""
+    d = brng_lda_full_desc()
+    d.n_docs = int(doc_offsets.numel()) - 1
+    d.n_topics, d.n_vocab, d.sweeps = int(n_topics), int(n_vocab), int(sweeps)
+    d.n_tokens = int(words.numel()) if words is not None else 0
+    d.alpha, d.beta = float(alpha), float(beta)
+    d.d_doc_offsets, d.d_words, d.d_z = _ptr(doc_offsets), _ptr(words), _ptr(z)
+    d.d_ndk, d.d_nkw, d.d_theta, d.d_phi = _ptr(ndk), _ptr(nkw), _ptr(theta), _ptr(phi)
+    _check(_lib.brng_run_lda_full(ctx, C.byref(d)), "brng_run_lda_full")
 
 
 def brng_time_next_launch(ctx: int, start=None, stop=None) -> None:

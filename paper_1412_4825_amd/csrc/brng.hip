@@ -11,6 +11,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -475,39 +476,159 @@ __global__ __launch_bounds__(512) void k_step_gamma(Meta* meta, Pools P, uint32_
 // Dirichlet: one wave per item, any K (the component gammas go to `out`,
 // then are scaled by their sum, accumulated in the same order as in the LDA
 // model).
-__global__ __launch_bounds__(512) void k_step_dirichlet(Meta* meta, Pools P, uint32_t n_items,
-                                                        const int32_t* offsets,
-                                                        const float* alpha, float* out) {
-    const uint32_t item = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
-    if (item >= n_items) return;
+// One Dirichlet draw by unit `unit` (one wave): shapes alpha[k], or base +
+// cnt[k] when alpha is null, for K components; the normalised draw goes to
+// out[0..K).  Gammas in rounds (gamma_rounds), straight from the windows.
+__device__ void dirichlet_unit(Meta* meta, const Pools& P, uint32_t unit, int K,
+                               const float* alpha, const int32_t* cnt, float base, float* out) {
     const uint32_t lane = lane_id();
-    const int32_t off = offsets[item];
-    const int K = offsets[item + 1] - off;
-    if (K < 1) return;
     DirectReader<KIND_N> rn;
     DirectReader<KIND_E> re;
-    rn.open(meta[item], P.n + (size_t)item * P.W[KIND_N], P.W[KIND_N]);
-    re.open(meta[item], P.e + (size_t)item * P.W[KIND_E], P.W[KIND_E]);
+    rn.open(meta[unit], P.n + (size_t)unit * P.W[KIND_N], P.W[KIND_N]);
+    re.open(meta[unit], P.e + (size_t)unit * P.W[KIND_E], P.W[KIND_E]);
     CompSrc src;
     src.K = K;
-    src.alpha = alpha + off;
-    src.cnt = nullptr;
-    src.y = out + off;
+    src.alpha = alpha;
+    src.cnt = cnt;
+    src.base = base;
+    src.y = out;
     gamma_rounds<false>(rn, re, src, 4096u + 64u * (uint32_t)min(K, 1 << 24));
     // component gammas were written by whichever lane drew them
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     float part = 0.0f;
     for (int b0 = 0; b0 < K; b0 += 64) {
         const int k = b0 + (int)lane;
-        if (k < K) part += out[off + k];
+        if (k < K) part += out[k];
     }
     const float S = wave_sum(part);
     for (int b0 = 0; b0 < K; b0 += 64) {
         const int k = b0 + (int)lane;
-        if (k < K) out[off + k] = S > 0.0f ? out[off + k] / S : 0.0f;
+        if (k < K) out[k] = S > 0.0f ? out[k] / S : 0.0f;
     }
-    rn.close(meta[item]);
-    re.close(meta[item]);
+    rn.close(meta[unit]);
+    re.close(meta[unit]);
+}
+
+__global__ __launch_bounds__(512) void k_step_dirichlet(Meta* meta, Pools P, uint32_t n_items,
+                                                        const int32_t* offsets,
+                                                        const float* alpha, float* out) {
+    const uint32_t item = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (item >= n_items) return;
+    const int32_t off = offsets[item];
+    const int K = offsets[item + 1] - off;
+    if (K < 1) return;
+    dirichlet_unit(meta, P, item, K, alpha + off, nullptr, 0.0f, out + off);
+}
+
+// ---------------------------------------------------------------------------
+// Full LDA: the uncollapsed Gibbs sampler of the LDA model whose Dirichlet
+// redraws motivate the method (Sec. 1 and its footnote).  Per sweep,
+// phi_k ~ Dir(beta + n_k.) for every topic, theta_d ~ Dir(alpha + n_d.) for
+// every document, then every token's topic z ~ Cat(theta_d,k phi_k,w).
+// Topic k is unit k, document d is unit K + d.  Token indices are clamped to
+// [0, n_tokens), so malformed offsets read nothing outside the arrays.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_zero_i32(int32_t* p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// Counts of an assignment (n_dk and n_kw zero on entry); one wave per document.
+__global__ __launch_bounds__(512) void k_ldaf_recount(uint32_t D, int K, int V,
+                                                      const int32_t* doff, int32_t n_tokens,
+                                                      const int32_t* words, const int32_t* z,
+                                                      int32_t* ndk, int32_t* nkw) {
+    const uint32_t d = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (d >= D) return;
+    const int32_t a = max(doff[d], 0), b = min(doff[d + 1], n_tokens);
+    for (int32_t i = a + (int32_t)lane_id(); i < b; i += 64) {
+        const int32_t k = z[i], w = words[i];
+        if (k >= 0 && k < K && w >= 0 && w < V) {
+            atomicAdd(&ndk[(size_t)d * K + k], 1);
+            atomicAdd(&nkw[(size_t)k * V + w], 1);
+        }
+    }
+}
+
+// phi_k ~ Dir(beta + n_k.), one wave per topic.
+__global__ __launch_bounds__(512) void k_ldaf_topics(Meta* meta, Pools P, int K, int V, float beta,
+                                                     const int32_t* nkw, float* phi) {
+    const uint32_t k = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (k >= (uint32_t)K) return;
+    dirichlet_unit(meta, P, k, V, nullptr, nkw + (size_t)k * V, beta, phi + (size_t)k * V);
+}
+
+// theta_d ~ Dir(alpha + n_d.), then one uniform per token (token order) and
+// its topic: p_k = theta_k phi_k,w in fp32, q_k = rint(2^24 p_k / max p) (all
+// 1 when max p = 0), C_k = q_0 + ... + q_k, j = (u 2^24 - 1) / 2,
+// t = (j C_{K-1}) >> 23, z = the number of k with C_k <= t.  A word outside
+// [0, V) gets z = -1 and no count but still takes its uniform.  New n_d. in
+// place (from LDS counts), n_kw added atomically (zero on entry).  K <= 64:
+// lane k holds theta_k and the token loop reads it with readlane.
+__global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t D, int K, int V,
+                                                   float alpha, const int32_t* doff,
+                                                   int32_t n_tokens, const int32_t* words,
+                                                   const float* phi, float* theta, int32_t* z,
+                                                   int32_t* ndk, int32_t* nkw) {
+    extern __shared__ int32_t ldaf_lds[];
+    const uint32_t d = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (d >= D) return;
+    const uint32_t lane = lane_id();
+    const uint32_t unit = (uint32_t)K + d;
+    int32_t* cnt = ldaf_lds + 64 * wave_in_block();
+    float* th_row = theta + (size_t)d * K;
+    int32_t* ndk_row = ndk + (size_t)d * K;
+    dirichlet_unit(meta, P, unit, K, nullptr, ndk_row, alpha, th_row);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    const float th = (int)lane < K ? th_row[lane] : 0.0f;
+    cnt[lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    DirectReader<KIND_U> ru;
+    ru.open(meta[unit], P.u + (size_t)unit * P.W[KIND_U], P.W[KIND_U]);
+    const int32_t a = max(doff[d], 0), b = min(doff[d + 1], n_tokens);
+    for (int32_t i0 = a; i0 < b; i0 += 64) {
+        const int32_t i = i0 + (int32_t)lane;
+        const bool act = i < b;
+        const float u = ru.take(act);
+        const int32_t w = act ? words[i] : -1;
+        const bool ok = act && w >= 0 && w < V;
+        const float* col = phi + (ok ? w : 0);
+        float m = 0.0f;
+        for (int k = 0; k < K; ++k) {
+            const float tk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(th), k));
+            if (ok) m = fmaxf(m, tk * col[(size_t)k * V]);
+        }
+        uint32_t Q = 0;
+        for (int k = 0; k < K; ++k) {
+            const float tk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(th), k));
+            const float p = ok ? tk * col[(size_t)k * V] : 0.0f;
+            Q += m > 0.0f ? (uint32_t)rintf((p / m) * 16777216.0f) : 1u;
+        }
+        const uint32_t j = (((uint32_t)(u * 16777216.0f)) - 1u) >> 1;
+        const uint32_t t = (uint32_t)(((uint64_t)j * Q) >> 23);
+        int32_t zi = 0;
+        uint32_t C = 0;
+        for (int k = 0; k < K; ++k) {
+            const float tk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(th), k));
+            const float p = ok ? tk * col[(size_t)k * V] : 0.0f;
+            C += m > 0.0f ? (uint32_t)rintf((p / m) * 16777216.0f) : 1u;
+            zi += C <= t ? 1 : 0;
+        }
+        if (!ok) zi = -1;
+        if (act) z[i] = zi;
+        if (zi >= 0) {
+            atomicAdd(&cnt[zi], 1);
+            atomicAdd(&nkw[(size_t)zi * V + w], 1);
+        }
+    }
+    ru.close(meta[unit]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if ((int)lane < K) ndk_row[lane] = cnt[lane];
 }
 
 template <int MODEL>
@@ -938,6 +1059,47 @@ brng_status brng_step_dirichlet(brng_ctx* c, const int32_t* offsets, const float
     return BRNG_OK;
 }
 
+
+brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
+    if (!c || !d) return BRNG_E_ARG;
+    if (c->cfg.layout != BRNG_LAYOUT_ITEMS) return BRNG_E_ARG;
+    if (c->cfg.prec != BRNG_F32) return BRNG_E_UNSUPPORTED;
+    const uint32_t D = d->n_docs, K = d->n_topics, V = d->n_vocab;
+    if (D == 0 || K < 1 || K > 64 || V < 1 || V > 4096 || d->n_tokens < 0) return BRNG_E_ARG;
+    if ((uint64_t)K + D > c->n_units) return BRNG_E_ARG;
+    if (!(d->alpha > 0.0f) || !(d->beta > 0.0f) || !std::isfinite(d->alpha) ||
+        !std::isfinite(d->beta))
+        return BRNG_E_ARG;
+    if (!d->d_doc_offsets || !d->d_ndk || !d->d_nkw || !d->d_theta || !d->d_phi) return BRNG_E_ARG;
+    if (d->n_tokens > 0 && (!d->d_words || !d->d_z)) return BRNG_E_ARG;
+    if (!c->cfg.window[BRNG_U] || !c->cfg.window[BRNG_N] || !c->cfg.window[BRNG_E])
+        return BRNG_E_KIND_DISABLED;
+    const Pools P = make_pools(c);
+    const int wpb = c->wpb;
+    const dim3 blk(64 * wpb);
+    auto zero = [&](int32_t* p, uint64_t n) {
+        const uint64_t g = std::min<uint64_t>((n + 255) / 256, 4096);
+        if (g) hipLaunchKernelGGL(k_zero_i32, dim3((uint32_t)g), dim3(256), 0, c->stream, p, n);
+    };
+    zero(d->d_ndk, (uint64_t)D * K);
+    zero(d->d_nkw, (uint64_t)K * V);
+    hipLaunchKernelGGL(k_ldaf_recount, dim3((D + wpb - 1) / wpb), blk, 0, c->stream, D, (int)K,
+                       (int)V, d->d_doc_offsets, d->n_tokens, d->d_words, d->d_z, d->d_ndk,
+                       d->d_nkw);
+    HIPCHK(hipGetLastError());
+    for (uint32_t s = 0; s < d->sweeps; ++s) {
+        hipLaunchKernelGGL(k_ldaf_topics, dim3((K + wpb - 1) / wpb), blk, 0, c->stream, c->meta, P,
+                           (int)K, (int)V, d->beta, d->d_nkw, d->d_phi);
+        zero(d->d_nkw, (uint64_t)K * V);
+        hipLaunchKernelGGL(k_ldaf_docs, dim3((D + wpb - 1) / wpb), blk, (size_t)wpb * 64 * 4,
+                           c->stream, c->meta, P, D, (int)K, (int)V, d->alpha, d->d_doc_offsets,
+                           d->n_tokens, d->d_words, d->d_phi, d->d_theta, d->d_z, d->d_ndk,
+                           d->d_nkw);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipGetLastError());
+    return BRNG_OK;
+}
 
 static brng_status check_desc(const brng_ctx* c, const brng_gibbs_desc& d) {
     if (d.model < 0 || d.model >= BRNG_NMODELS) return BRNG_E_ARG;

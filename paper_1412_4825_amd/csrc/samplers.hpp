@@ -232,11 +232,12 @@ struct CompSrc {
     int K;
     uint32_t next;  // wave-uniform
     int comp;
-    const float* alpha;  // per component, or null: 0.1 + cnt[k]
+    const float* alpha;  // per component, or null: base + cnt[k]
     const int32_t* cnt;
     float* y;
+    float base = 0.1f;  // prior added to the counts
     __device__ __forceinline__ float shape(int k) const {
-        return alpha ? alpha[k] : 0.1f + (float)cnt[k];
+        return alpha ? alpha[k] : base + (float)cnt[k];
     }
     __device__ __forceinline__ float first() {
         comp = (int)lane_id();

@@ -50,6 +50,33 @@ def lda(n_docs: int = 16384, sweeps: int = 100, mean_len: float = 200.0,
     return dict(n_docs=n_docs, sweeps=sweeps, K=K, ntok=ntok, offsets=offsets)
 
 
+def lda_corpus(n_docs: int = 16384, n_topics: int = 64, n_vocab: int = 4096,
+               mean_len: float = 200.0, seed: int = WORKLOAD_SEED):
+    """A synthetic corpus drawn from the LDA generative model: topic-word
+    distributions ~ Dir(0.05), document-topic ~ Dir(0.1), n_d ~
+    Poisson(mean_len) tokens, each token's topic from its document and its
+    word from that topic; the starting assignment is uniform over topics."""
+    r = _rng(seed, 9)
+    phi = r.dirichlet(np.full(n_vocab, 0.05), size=n_topics)
+    theta = r.dirichlet(np.full(n_topics, 0.1), size=n_docs)
+    ntok = r.poisson(mean_len, size=n_docs).astype(np.int32)
+    offsets = np.zeros(n_docs + 1, dtype=np.int32)
+    offsets[1:] = np.cumsum(ntok)
+    total = int(offsets[-1])
+    doc = np.repeat(np.arange(n_docs), ntok)
+    zt = (r.random(total)[:, None] > np.cumsum(theta, axis=1)[doc]).sum(axis=1)
+    zt = np.minimum(zt, n_topics - 1)
+    cphi = np.cumsum(phi, axis=1)
+    words = np.empty(total, dtype=np.int32)
+    u = r.random(total)
+    for k in range(n_topics):
+        sel = np.nonzero(zt == k)[0]
+        words[sel] = np.minimum(np.searchsorted(cphi[k], u[sel], side="right"), n_vocab - 1)
+    z0 = r.integers(0, n_topics, size=total).astype(np.int32)
+    return dict(n_docs=n_docs, n_topics=n_topics, n_vocab=n_vocab, offsets=offsets,
+                words=words, z0=z0, ntok=ntok)
+
+
 def step_params(n: int, seed: int = WORKLOAD_SEED):
     """Per-chain parameters for one-at-a-time calls: U(a,b), N(mu,sigma),
     Exp(lambda), Gamma(alpha) with alpha log-uniform on [0.05, 5000]."""

@@ -32,6 +32,7 @@ def test_every_declared_function_is_exported():
 def test_struct_layouts_match_header(tmp_path):
     """ctypes layouts equal what a C compiler makes of include/brng.h."""
     classes = {"brng_config": b.brng_config, "brng_gibbs_desc": b.brng_gibbs_desc,
+               "brng_lda_full_desc": b.brng_lda_full_desc,
                "brng_serve_config": b.brng_serve_config, "brng_serve_done": b.brng_serve_done,
                "brng_serve_stats": b.brng_serve_stats}
     fields = {k: [f[0] for f in c._fields_] for k, c in classes.items()}
@@ -72,6 +73,7 @@ def test_null_context_rejected():
     lib = b.lib()
     assert lib.brng_fill_base(None, 0) == b.BRNG_E_ARG
     assert lib.brng_run_gibbs(None, None, 0) == b.BRNG_E_ARG
+    assert lib.brng_run_lda_full(None, None) == b.BRNG_E_ARG
     assert lib.brng_destroy(None) == b.BRNG_OK
     assert b.brng_status_string(b.BRNG_E_KIND_DISABLED).startswith("pool kind disabled")
 
