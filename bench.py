@@ -13,7 +13,9 @@ of every step.  Chains continue from step to step.
 Other workloads (--workload): triangle (Eq. 1 / Fig. 1, 1,024 chains x 10,000
 iterations, fp64), gamma (262,144 chains of uneven length 50..1,000 with
 alpha_{t+1} = 0.1 + g_t), lda (16,384 documents, Dirichlet + multinomial,
-100 sweeps), served (the mixed request stream alone).
+100 sweeps), lda_full (full LDA on a synthetic corpus: 16,384 documents, 64
+topics, 4,096 words, per sweep the topic-word and document-topic Dirichlets
+and one topic per token), served (the mixed request stream alone).
 
 Prints one JSON line: deviates/s, the roofline of the dominant kernel
 (algorithmic bytes over its duration against 8 TB/s; the duration from HIP
@@ -324,6 +326,79 @@ def setup_lda(torch, b, args):
                         "generator": "Philox4x32-10"})
 
 
+def _cpu_lda_full(a):
+    seed, K, V, off, words, z0, alpha, beta = a
+    import oracle
+    t = time.perf_counter()
+    oracle.lda_full_sweep(seed, oracle.new_cursors(K + off.size - 1), K, V, alpha, beta, off,
+                          words, z0)
+    return time.perf_counter() - t
+
+
+def setup_lda_full(torch, b, args):
+    """Full LDA on a synthetic corpus: per sweep K topic-word Dirichlets over
+    the vocabulary, one document-topic Dirichlet per document and one topic
+    per token.  A step is one call of `sweeps_per_step` sweeps."""
+    from paper_1412_4825_amd import workloads
+    nd = args.chains or 16384
+    K, V = 64, 4096
+    sweeps = args.chain_steps or 5
+    alpha, beta = 0.1, 0.05
+    c = workloads.lda_corpus(n_docs=nd, n_topics=K, n_vocab=V, seed=args.seed)
+    T = int(c["offsets"][-1])
+    W = args.window or 512
+    dev = torch.device("cuda:0")
+    ctx = b.brng_create(args.seed, K + nd, [W, W, W, 0], layout=b.BRNG_LAYOUT_ITEMS,
+                        stream=torch.cuda.current_stream())
+    toff = torch.from_numpy(c["offsets"]).to(dev)
+    tw = torch.from_numpy(c["words"]).to(dev)
+    tz = torch.from_numpy(c["z0"]).to(dev)
+    ndk = torch.zeros(nd * K, dtype=torch.int32, device=dev)
+    nkw = torch.zeros(K * V, dtype=torch.int32, device=dev)
+    th = torch.zeros(nd * K, dtype=torch.float32, device=dev)
+    phi = torch.zeros(K * V, dtype=torch.float32, device=dev)
+
+    def run():
+        b.brng_run_lda_full(ctx, K, V, sweeps, alpha, beta, toff, tw, tz, ndk, nkw, th, phi)
+
+    dv = sweeps * (K * V + nd * K + T)
+    # outputs per sweep: phi, theta, z, n_dk, n_kw, and the corpus's words read
+    out_b = sweeps * 4.0 * (2 * K * V + 2 * nd * K + 2 * T)
+
+    def kernel_bytes(delta):
+        # the document kernel of one sweep: its units' consumed entries (the
+        # document units K..), written once and read once, plus theta, z,
+        # n_d., the n_kw increments and the words it reads
+        ent = delta[K:, [b.BRNG_U, b.BRNG_N, b.BRNG_E]].sum() / sweeps
+        return 8.0 * ent + 4.0 * (2 * nd * K + 3 * T)
+
+    def cpu(workers):
+        sd = min(nd, args.cpu_units or 4096)
+        off = c["offsets"][:sd + 1].astype(np.int32)
+        n = int(off[-1])
+        busy = _cpu_lda_full((args.seed, K, V, off, c["words"][:n], c["z0"][:n], alpha, beta))
+        sdv = K * V + sd * K + n
+        return {"value": sdv / busy, "unit": "deviates/s", "cores": 1, "kind": "oracle",
+                "sample": "one sweep of the first %d of %d documents (all %d x %d topic-word "
+                          "draws, %d tokens; %.3g deviates) in one process; %.1f s"
+                          % (sd, nd, K, V, n, sdv, busy)}
+
+    return dict(ctx=ctx, run=run, kinds=[b.BRNG_U, b.BRNG_N, b.BRNG_E],
+                keep=(toff, tw, tz, ndk, nkw, th, phi),
+                entry_bytes={b.BRNG_U: 4, b.BRNG_N: 4, b.BRNG_E: 4},
+                windows={b.BRNG_U: W, b.BRNG_N: W, b.BRNG_E: W},
+                deviates=dv, out_bytes=out_b, dtype="f32", cpu=cpu,
+                kernel="k_ldaf_docs", kernel_bytes=kernel_bytes,
+                config={"workload": "full LDA, uncollapsed Gibbs on a synthetic corpus: "
+                                    "phi_k~Dir(beta+n_k.), theta_d~Dir(alpha+n_d.), "
+                                    "z~Cat(theta_d phi_.w)",
+                        "documents": nd, "topics": K, "vocabulary": V, "tokens": T,
+                        "tokens_per_document": "Poisson(200)", "alpha": alpha, "beta": beta,
+                        "sweeps_per_step": sweeps, "window_per_unit_per_kind": W,
+                        "precision": "fp32 deviates, int32 topics and counts",
+                        "generator": "Philox4x32-10"})
+
+
 def copy_bandwidth(torch, b, nbytes=1 << 30, reps=10):
     """Achievable HBM bandwidth for context: the library's streaming
     conversion kernel (brng_convert, uniform kind: one 16-byte load and one
@@ -541,7 +616,7 @@ def served_main(torch, args):
 
 
 WORKLOADS = {"normexp": setup_normexp, "triangle": setup_triangle, "gamma": setup_gamma,
-             "lda": setup_lda}
+             "lda": setup_lda, "lda_full": setup_lda_full}
 
 
 def main():
@@ -612,10 +687,16 @@ def main():
             b.brng_time_next_launch(ctx, *kpair)
             ev.pairs.setdefault("chains", []).append(kpair)
         e = ev.span("chains_span")
-        b.brng_run_gibbs(ctx, Wk["resume"])
+        if "run" in Wk:
+            Wk["run"]()
+        else:
+            b.brng_run_gibbs(ctx, Wk["resume"])
         e.record()
 
-    b.brng_run_gibbs(ctx, Wk["fresh"])  # fresh start: streams at 0
+    if "run" in Wk:
+        Wk["run"]()
+    else:
+        b.brng_run_gibbs(ctx, Wk["fresh"])  # fresh start: streams at 0
     for _ in range(max(0, args.warmup - 1)):
         step()
     # kernel event pairs, created (recorded once) before the timed region
@@ -652,7 +733,7 @@ def main():
         pool_b += 2.0 * eb * delta[:, k].sum()
         fill_b += eb * np.minimum(delta[:, k], Wk["windows"][k]).sum()
     step_b = pool_b + Wk["out_bytes"]
-    chain_b = step_b - fill_b
+    chain_b = Wk["kernel_bytes"](delta) if "kernel_bytes" in Wk else step_b - fill_b
     chain_ms = float(np.mean(ev.ms("chains")))
     span_ms = float(np.mean(ev.ms("chains_span")))
     gbs = chain_b / (chain_ms / 1e3) / 1e9

@@ -183,8 +183,9 @@ brng_status brng_step_dirichlet(brng_ctx *ctx, const int32_t *d_offsets,
  * sweep: phi_k ~ Dir(beta + n_k.) over the vocabulary for every topic,
  * theta_d ~ Dir(alpha + n_d.) for every document, then every token's topic
  * z ~ Cat(theta_d,k phi_k,w), one uniform per token in token order.  The
- * token draw quantises its fp32 weights p_k = theta_k phi_k,w against their
- * maximum, q_k = rint(2^24 p_k / max p) (all 1 when max p = 0), and takes
+ * token draw quantises its fp32 weights p_k = theta_k phi_w,k against the
+ * binade of their maximum, q_k = rint(p_k 2^(24 - e)) with max p = f 2^e,
+ * f in [1/2, 1) (all 1 when max p = 0), and takes
  * the first k with t < q_0 + ... + q_k, t = (j Q) >> 23, Q the sum of the
  * q_k, j = (u 2^24 - 1) / 2.  Context: layout ITEMS, F32, kinds U, N, E
  * enabled, at least n_topics + n_docs items; topic k is unit k, document d
@@ -192,8 +193,9 @@ brng_status brng_step_dirichlet(brng_ctx *ctx, const int32_t *d_offsets,
  * The state is the assignment d_z (int32 per token, in/out): a call first
  * recounts n_dk and n_kw from it, then runs `sweeps` sweeps; on return z,
  * n_dk ([n_docs][n_topics] int32) and n_kw ([n_topics][n_vocab] int32) are
- * consistent, and theta ([n_docs][n_topics]) and phi ([n_topics][n_vocab])
- * hold the last sweep's draws (float).  Tokens of document d are
+ * consistent, and theta ([n_docs][n_topics]) and phi ([n_vocab][n_topics],
+ * word-major: a token's topic weights are one row) hold the last sweep's
+ * draws (float).  Tokens of document d are
  * [d_doc_offsets[d], d_doc_offsets[d+1]) clamped to [0, n_tokens); a word
  * id outside [0, n_vocab) gets z = -1, no count, and still takes its
  * uniform.  All arrays are caller-owned device memory.
@@ -214,7 +216,7 @@ typedef struct {
     int32_t *d_ndk;            /* out: [n_docs][n_topics] */
     int32_t *d_nkw;            /* out: [n_topics][n_vocab] */
     float *d_theta;            /* out: [n_docs][n_topics] */
-    float *d_phi;              /* out: [n_topics][n_vocab] */
+    float *d_phi;              /* out: [n_vocab][n_topics] */
 } brng_lda_full_desc;
 brng_status brng_run_lda_full(brng_ctx *ctx, const brng_lda_full_desc *h_desc);
 
@@ -334,8 +336,10 @@ brng_status brng_set_launch(brng_ctx *ctx, int32_t waves_per_block, int32_t rese
  * kernel alone, as the paper times its generators).  start_event and
  * stop_event are hipEvent_t handles the caller created with timing enabled
  * and owns.  The next brng_run_gibbs call in the plain form (one request)
- * launches its chain kernel so that start_event is recorded when the kernel
- * starts and stop_event when it ends: their elapsed time is the kernel's own
+ * launches its chain kernel, or the next brng_run_lda_full call with at
+ * least one sweep its last sweep's document kernel, so that start_event is
+ * recorded when the kernel starts and stop_event when it ends: their
+ * elapsed time is the kernel's own
  * duration, without the dispatch gap that events recorded on the stream
  * around the call include.  The pair is used once and then forgotten; a
  * batched call leaves it pending.  Both NULL clears a pending pair.

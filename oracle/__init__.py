@@ -416,8 +416,10 @@ def lda_full_token_topic(theta_d, phi, w, u):
     """One token's topic from the fp32 theta row of its document, the fp32
     topic-word matrix, its word id and its uniform u (a pool entry).  The
     weights p_k = theta_k phi_k,w are formed in fp32 and quantised against
-    their maximum, q_k = rint(2^24 p_k / max p), so that the decision is an
-    integer one and both sides take it in the same precision; with
+    the binade of their maximum m = f 2^e (f in [1/2, 1)): q_k =
+    rint(p_k 2^(24 - e)), an exact scaling, so q of the largest weight is in
+    [2^23, 2^24] and the decision is an integer one that both sides take in
+    the same precision; with
     C_k = q_0 + ... + q_k, j = (u 2^24 - 1) / 2 and t = (j C_{K-1}) >> 23, the
     topic is the first k with t < C_k (the multinomial rule of the chain
     model, over per-token weights).  A word outside [0, V) gives -1."""
@@ -427,7 +429,8 @@ def lda_full_token_topic(theta_d, phi, w, u):
     p = np.asarray(theta_d, dtype=np.float32) * np.asarray(phi[:, w], dtype=np.float32)
     m = p.max()
     if m > 0:
-        q = np.rint((p / m).astype(np.float32) * np.float32(16777216.0)).astype(np.int64)
+        e = int(np.frexp(m)[1])
+        q = np.rint(np.ldexp(p, 24 - e)).astype(np.int64)
     else:
         q = np.ones(K, dtype=np.int64)
     c = np.cumsum(q)

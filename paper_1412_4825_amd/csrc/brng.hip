@@ -478,9 +478,11 @@ __global__ __launch_bounds__(512) void k_step_gamma(Meta* meta, Pools P, uint32_
 // model).
 // One Dirichlet draw by unit `unit` (one wave): shapes alpha[k], or base +
 // cnt[k] when alpha is null, for K components; the normalised draw goes to
-// out[0..K).  Gammas in rounds (gamma_rounds), straight from the windows.
+// out[k * os], k < K.  Gammas in rounds (gamma_rounds), straight from the
+// windows.
 __device__ void dirichlet_unit(Meta* meta, const Pools& P, uint32_t unit, int K,
-                               const float* alpha, const int32_t* cnt, float base, float* out) {
+                               const float* alpha, const int32_t* cnt, float base, float* out,
+                               int os = 1) {
     const uint32_t lane = lane_id();
     DirectReader<KIND_N> rn;
     DirectReader<KIND_E> re;
@@ -492,18 +494,19 @@ __device__ void dirichlet_unit(Meta* meta, const Pools& P, uint32_t unit, int K,
     src.cnt = cnt;
     src.base = base;
     src.y = out;
+    src.ys = os;
     gamma_rounds<false>(rn, re, src, 4096u + 64u * (uint32_t)min(K, 1 << 24));
     // component gammas were written by whichever lane drew them
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     float part = 0.0f;
     for (int b0 = 0; b0 < K; b0 += 64) {
         const int k = b0 + (int)lane;
-        if (k < K) part += out[k];
+        if (k < K) part += out[(size_t)k * os];
     }
     const float S = wave_sum(part);
     for (int b0 = 0; b0 < K; b0 += 64) {
         const int k = b0 + (int)lane;
-        if (k < K) out[k] = S > 0.0f ? out[k] / S : 0.0f;
+        if (k < K) out[(size_t)k * os] = S > 0.0f ? out[(size_t)k * os] / S : 0.0f;
     }
     rn.close(meta[unit]);
     re.close(meta[unit]);
@@ -551,41 +554,42 @@ __global__ __launch_bounds__(512) void k_ldaf_recount(uint32_t D, int K, int V,
     }
 }
 
-// phi_k ~ Dir(beta + n_k.), one wave per topic.
+// phi_k ~ Dir(beta + n_k.), one wave per topic; phi is word-major
+// ([V][K]), so that a token's K weights are one contiguous row.
 __global__ __launch_bounds__(512) void k_ldaf_topics(Meta* meta, Pools P, int K, int V, float beta,
                                                      const int32_t* nkw, float* phi) {
     const uint32_t k = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
     if (k >= (uint32_t)K) return;
-    dirichlet_unit(meta, P, k, V, nullptr, nkw + (size_t)k * V, beta, phi + (size_t)k * V);
+    dirichlet_unit(meta, P, k, V, nullptr, nkw + (size_t)k * V, beta, phi + k, K);
 }
 
 // theta_d ~ Dir(alpha + n_d.), then one uniform per token (token order) and
-// its topic: p_k = theta_k phi_k,w in fp32, q_k = rint(2^24 p_k / max p) (all
-// 1 when max p = 0), C_k = q_0 + ... + q_k, j = (u 2^24 - 1) / 2,
-// t = (j C_{K-1}) >> 23, z = the number of k with C_k <= t.  A word outside
-// [0, V) gets z = -1 and no count but still takes its uniform.  New n_d. in
-// place (from LDS counts), n_kw added atomically (zero on entry).  K <= 64:
-// lane k holds theta_k and the token loop reads it with readlane.
+// its topic: p_k = theta_k phi_w,k in fp32, q_k = rint(p_k 2^(24 - e)) with
+// max p = f 2^e, f in [1/2, 1) (an exact scaling; all 1 when max p = 0),
+// C_k = q_0 + ... + q_k, j = (u 2^24 - 1) / 2, t = (j C_{K-1}) >> 23,
+// z = the number of k with C_k <= t.  A word outside [0, V) gets z = -1 and
+// no count but still takes its uniform.  The uniforms are taken 64 at a time
+// (one per lane, in token order); then the wave works on one token at a
+// time with lane k on topic k (K <= 64): one coalesced read of the token's
+// phi row, the maximum and the prefix sums by DPP, the topic by a ballot.
+// New n_d. in place (lane k counts topic k), n_kw added atomically (zero on
+// entry).
 __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t D, int K, int V,
                                                    float alpha, const int32_t* doff,
                                                    int32_t n_tokens, const int32_t* words,
                                                    const float* phi, float* theta, int32_t* z,
                                                    int32_t* ndk, int32_t* nkw) {
-    extern __shared__ int32_t ldaf_lds[];
     const uint32_t d = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
     if (d >= D) return;
     const uint32_t lane = lane_id();
     const uint32_t unit = (uint32_t)K + d;
-    int32_t* cnt = ldaf_lds + 64 * wave_in_block();
+    const bool topic = (int)lane < K;
     float* th_row = theta + (size_t)d * K;
     int32_t* ndk_row = ndk + (size_t)d * K;
     dirichlet_unit(meta, P, unit, K, nullptr, ndk_row, alpha, th_row);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    const float th = (int)lane < K ? th_row[lane] : 0.0f;
-    cnt[lane] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const float th = topic ? th_row[lane] : 0.0f;
+    int32_t mycnt = 0;  // tokens of topic `lane`
     DirectReader<KIND_U> ru;
     ru.open(meta[unit], P.u + (size_t)unit * P.W[KIND_U], P.W[KIND_U]);
     const int32_t a = max(doff[d], 0), b = min(doff[d + 1], n_tokens);
@@ -593,42 +597,30 @@ __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t
         const int32_t i = i0 + (int32_t)lane;
         const bool act = i < b;
         const float u = ru.take(act);
-        const int32_t w = act ? words[i] : -1;
-        const bool ok = act && w >= 0 && w < V;
-        const float* col = phi + (ok ? w : 0);
-        float m = 0.0f;
-        for (int k = 0; k < K; ++k) {
-            const float tk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(th), k));
-            if (ok) m = fmaxf(m, tk * col[(size_t)k * V]);
+        const int32_t wl = act ? words[i] : -1;
+        const uint32_t jl = (((uint32_t)(u * 16777216.0f)) - 1u) >> 1;
+        const int ntk = min(64, b - i0);
+        int32_t zl = -1;  // topic of token i0 + lane
+        for (int r = 0; r < ntk; ++r) {
+            const int32_t w = __builtin_amdgcn_readlane(wl, r);
+            if (w < 0 || w >= V) continue;  // wave-uniform
+            const float p = topic ? th * phi[(size_t)w * K + lane] : 0.0f;
+            const float m = __int_as_float(wave_minmax<true>(__float_as_int(p)));
+            uint32_t q = 1u;
+            if (m > 0.0f) q = (uint32_t)rintf(ldexpf(p, 24 - __builtin_amdgcn_frexp_expf(m)));
+            const int32_t C = wave_incl_scan(topic ? (int32_t)q : 0);
+            const uint32_t Q = (uint32_t)__builtin_amdgcn_readlane(C, K - 1);
+            const uint32_t j = (uint32_t)__builtin_amdgcn_readlane((int32_t)jl, r);
+            const uint32_t t = (uint32_t)(((uint64_t)j * Q) >> 23);
+            const int32_t zt = (int32_t)__popcll(wave_ballot(topic && (uint32_t)C <= t));
+            if ((int)lane == r) zl = zt;
+            if ((int)lane == zt) ++mycnt;
+            if (lane == 0) atomicAdd(&nkw[(size_t)zt * V + w], 1);
         }
-        uint32_t Q = 0;
-        for (int k = 0; k < K; ++k) {
-            const float tk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(th), k));
-            const float p = ok ? tk * col[(size_t)k * V] : 0.0f;
-            Q += m > 0.0f ? (uint32_t)rintf((p / m) * 16777216.0f) : 1u;
-        }
-        const uint32_t j = (((uint32_t)(u * 16777216.0f)) - 1u) >> 1;
-        const uint32_t t = (uint32_t)(((uint64_t)j * Q) >> 23);
-        int32_t zi = 0;
-        uint32_t C = 0;
-        for (int k = 0; k < K; ++k) {
-            const float tk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(th), k));
-            const float p = ok ? tk * col[(size_t)k * V] : 0.0f;
-            C += m > 0.0f ? (uint32_t)rintf((p / m) * 16777216.0f) : 1u;
-            zi += C <= t ? 1 : 0;
-        }
-        if (!ok) zi = -1;
-        if (act) z[i] = zi;
-        if (zi >= 0) {
-            atomicAdd(&cnt[zi], 1);
-            atomicAdd(&nkw[(size_t)zi * V + w], 1);
-        }
+        if (act) z[i] = zl;
     }
     ru.close(meta[unit]);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if ((int)lane < K) ndk_row[lane] = cnt[lane];
+    if (topic) ndk_row[lane] = mycnt;
 }
 
 template <int MODEL>
@@ -1087,14 +1079,25 @@ brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
                        (int)V, d->d_doc_offsets, d->n_tokens, d->d_words, d->d_z, d->d_ndk,
                        d->d_nkw);
     HIPCHK(hipGetLastError());
+    // a pending event pair (brng_time_next_launch) times the last sweep's
+    // document kernel
+    hipEvent_t ts = c->t_start, te = c->t_stop;
+    if (d->sweeps) c->t_start = c->t_stop = nullptr;
     for (uint32_t s = 0; s < d->sweeps; ++s) {
         hipLaunchKernelGGL(k_ldaf_topics, dim3((K + wpb - 1) / wpb), blk, 0, c->stream, c->meta, P,
                            (int)K, (int)V, d->beta, d->d_nkw, d->d_phi);
         zero(d->d_nkw, (uint64_t)K * V);
-        hipLaunchKernelGGL(k_ldaf_docs, dim3((D + wpb - 1) / wpb), blk, (size_t)wpb * 64 * 4,
-                           c->stream, c->meta, P, D, (int)K, (int)V, d->alpha, d->d_doc_offsets,
-                           d->n_tokens, d->d_words, d->d_phi, d->d_theta, d->d_z, d->d_ndk,
-                           d->d_nkw);
+        const dim3 grid((D + wpb - 1) / wpb);
+        const size_t lds = 0;
+        if (ts && s + 1 == d->sweeps)
+            hipExtLaunchKernelGGL(k_ldaf_docs, grid, blk, (uint32_t)lds, c->stream, ts, te, 0u,
+                                  c->meta, P, D, (int)K, (int)V, d->alpha, d->d_doc_offsets,
+                                  d->n_tokens, d->d_words, (const float*)d->d_phi, d->d_theta,
+                                  d->d_z, d->d_ndk, d->d_nkw);
+        else
+            hipLaunchKernelGGL(k_ldaf_docs, grid, blk, lds, c->stream, c->meta, P, D, (int)K,
+                               (int)V, d->alpha, d->d_doc_offsets, d->n_tokens, d->d_words,
+                               d->d_phi, d->d_theta, d->d_z, d->d_ndk, d->d_nkw);
         HIPCHK(hipGetLastError());
     }
     HIPCHK(hipGetLastError());

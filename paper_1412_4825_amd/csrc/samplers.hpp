@@ -236,6 +236,7 @@ struct CompSrc {
     const int32_t* cnt;
     float* y;
     float base = 0.1f;  // prior added to the counts
+    int ys = 1;         // element stride of y
     __device__ __forceinline__ float shape(int k) const {
         return alpha ? alpha[k] : base + (float)cnt[k];
     }
@@ -247,7 +248,7 @@ struct CompSrc {
     __device__ __forceinline__ bool holding() const { return comp < K; }
     __device__ __forceinline__ float complete(uint64_t md, float gv, float al) {
         const bool done = lane_in(md);
-        if (done) y[comp] = gv;
+        if (done) y[(size_t)comp * ys] = gv;
         float a = al;
         if (done) {
             comp = (int)(next + mask_rank(md));

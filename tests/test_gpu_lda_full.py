@@ -80,11 +80,12 @@ def test_lda_full_sweep_replay(dev, K, V, D, mean_len):
         for s in range(sweeps):
             b.brng_run_lda_full(ctx, K, V, 1, alpha, beta, toff, buf["words"], buf["z"],
                                 buf["ndk"], buf["nkw"], buf["theta"], buf["phi"])
-            gz, gth, gphi = _np(buf["z"]), _np(buf["theta"]), _np(buf["phi"])
+            gz, gth = _np(buf["z"]), _np(buf["theta"])
+            gphi = np.ascontiguousarray(_np(buf["phi"]).reshape(V, K).T)  # word-major on device
             gndk, gnkw = _np(buf["ndk"]), _np(buf["nkw"])
             gcur = b.brng_get_cursors(ctx)[:K + D]
             r = oracle.lda_full_sweep(seed, cur, K, V, alpha, beta, off, words, z_in,
-                                      theta32=gth, phi32=gphi)
+                                      theta32=gth, phi32=gphi.ravel())
             flipped = set()
             okp = within(gphi.reshape(K, V), r["phi"], r["phi_tol"])
             for k in range(K):
