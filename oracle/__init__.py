@@ -403,12 +403,10 @@ def lda_full_counts(K, V, doc_offsets, words, z):
     D = doc_offsets.size - 1
     ndk = np.zeros((D, K), dtype=np.int32)
     nkw = np.zeros((K, V), dtype=np.int32)
-    for d in range(D):
-        for i in range(doc_offsets[d], doc_offsets[d + 1]):
-            k, w = z[i], words[i]
-            if 0 <= k < K and 0 <= w < V:
-                ndk[d, k] += 1
-                nkw[k, w] += 1
+    doc = np.repeat(np.arange(D), np.diff(doc_offsets))
+    ok = (z >= 0) & (z < K) & (words >= 0) & (words < V)
+    np.add.at(ndk, (doc[ok], z[ok]), 1)
+    np.add.at(nkw, (z[ok], words[ok]), 1)
     return ndk, nkw
 
 
@@ -440,7 +438,7 @@ def lda_full_token_topic(theta_d, phi, w, u):
 
 
 def lda_full_sweep(seed, cursors, K, V, alpha, beta, doc_offsets, words, z_in,
-                   theta32=None, phi32=None):
+                   theta32=None, phi32=None, docs=None):
     """One sweep from assignment z_in.  Topic k draws phi_k ~ Dir(beta + n_k.)
     from its pools, document d draws theta_d ~ Dir(alpha + n_d.) from its
     pools, then takes one uniform per token in token order and draws the
@@ -449,7 +447,10 @@ def lda_full_sweep(seed, cursors, K, V, alpha, beta, doc_offsets, words, z_in,
     theta32 / phi32 when given (the device's fp32 values, for replay), else
     this sweep's own values rounded to fp32.  cursors ([K + D][4], uint64)
     advance in place.  Returns the fp64 phi and theta with their tolerances
-    and decision margins, the new assignment and its counts."""
+    and decision margins, the new assignment and its counts.  With `docs`
+    (document indices) only those documents draw (every topic still does):
+    the other documents' theta rows are NaN, their tokens keep z_in, and no
+    counts are returned."""
     doc_offsets = np.ascontiguousarray(doc_offsets, dtype=np.int32)
     words = np.asarray(words, dtype=np.int64)
     D = doc_offsets.size - 1
@@ -461,11 +462,22 @@ def lda_full_sweep(seed, cursors, K, V, alpha, beta, doc_offsets, words, z_in,
     ct = cursors[:K]
     cd = cursors[K:]
     phi, phi_t, phi_m = step_dirichlet(seed, ct, off_phi, a_phi, unit0=0)
-    th, th_t, th_m = step_dirichlet(seed, cd, off_th, a_th, unit0=K)
+    if docs is None:
+        th, th_t, th_m = step_dirichlet(seed, cd, off_th, a_th, unit0=K)
+        todo = range(D)
+    else:
+        th, th_t, th_m = np.full(D * K, np.nan), np.full(D * K, np.nan), np.full(D, np.nan)
+        for d in docs:
+            c1 = cd[d:d + 1]  # this document's cursors, advanced in place
+            o1 = np.array([0, K], dtype=np.int32)
+            r1 = step_dirichlet(seed, c1, o1, a_th[d * K:(d + 1) * K], unit0=K + int(d))
+            th[d * K:(d + 1) * K], th_t[d * K:(d + 1) * K], th_m[d] = r1[0], r1[1], r1[2][0]
+        todo = docs
     phi_f = (phi.astype(np.float32) if phi32 is None else np.asarray(phi32, np.float32)).reshape(K, V)
     th_f = (th.astype(np.float32) if theta32 is None else np.asarray(theta32, np.float32)).reshape(D, K)
-    z = np.full(words.size, -1, dtype=np.int32)
-    for d in range(D):
+    z = (np.full(words.size, -1, dtype=np.int32) if docs is None
+         else np.asarray(z_in, dtype=np.int32).copy())
+    for d in todo:
         a, b = int(doc_offsets[d]), int(doc_offsets[d + 1])
         if b == a:
             continue
@@ -473,7 +485,7 @@ def lda_full_sweep(seed, cursors, K, V, alpha, beta, doc_offsets, words, z_in,
         cd[d, KIND_U] += np.uint64(b - a)
         for i in range(a, b):
             z[i] = lda_full_token_topic(th_f[d], phi_f, int(words[i]), u[i - a])
-    ndk2, nkw2 = lda_full_counts(K, V, doc_offsets, words, z)
+    ndk2, nkw2 = lda_full_counts(K, V, doc_offsets, words, z) if docs is None else (None, None)
     return dict(phi=phi.reshape(K, V), phi_tol=phi_t.reshape(K, V), phi_margin=phi_m,
                 theta=th.reshape(D, K), theta_tol=th_t.reshape(D, K), theta_margin=th_m,
                 z=z, ndk=ndk2, nkw=nkw2, cursors=cursors)

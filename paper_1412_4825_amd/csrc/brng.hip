@@ -554,13 +554,45 @@ __global__ __launch_bounds__(512) void k_ldaf_recount(uint32_t D, int K, int V,
     }
 }
 
-// phi_k ~ Dir(beta + n_k.), one wave per topic; phi is word-major
-// ([V][K]), so that a token's K weights are one contiguous row.
-__global__ __launch_bounds__(512) void k_ldaf_topics(Meta* meta, Pools P, int K, int V, float beta,
-                                                     const int32_t* nkw, float* phi) {
-    const uint32_t k = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+// phi_k ~ Dir(beta + n_k.), one wave (and workgroup) per topic, its pools
+// staged through LDS by the epoch readers of the LDA kernel (a topic has
+// thousands of components, so its rounds are many and sequential); phi is
+// word-major ([V][K]), so that a token's K weights are one contiguous row.
+constexpr int LDAF_TOPIC_LDS = LdaRN::LDS_BYTES + LdaRE::LDS_BYTES;
+__global__ __launch_bounds__(64) void k_ldaf_topics(Meta* meta, Pools P, int K, int V, float beta,
+                                                    const int32_t* nkw, float* phi) {
+    __shared__ __align__(16) unsigned char lds[LDAF_TOPIC_LDS];
+    const uint32_t k = blockIdx.x;
     if (k >= (uint32_t)K) return;
-    dirichlet_unit(meta, P, k, V, nullptr, nkw + (size_t)k * V, beta, phi + k, K);
+    const uint32_t lane = lane_id();
+    const Meta m = meta[k];
+    LdaRN rn;
+    LdaRE re;
+    rn.open(m, P.n + (size_t)k * P.W[KIND_N], P.W[KIND_N], reinterpret_cast<float*>(lds));
+    re.open(m, P.e + (size_t)k * P.W[KIND_E], P.W[KIND_E],
+            reinterpret_cast<float*>(lds + LdaRN::LDS_BYTES));
+    float* out = phi + k;
+    CompSrc src;
+    src.K = V;
+    src.alpha = nullptr;
+    src.cnt = nkw + (size_t)k * V;
+    src.base = beta;
+    src.y = out;
+    src.ys = K;
+    gamma_rounds<true, LDA_EPOCH>(rn, re, src, 4096u + 64u * (uint32_t)V);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    float part = 0.0f;
+    for (int b0 = 0; b0 < V; b0 += 64) {
+        const int c = b0 + (int)lane;
+        if (c < V) part += out[(size_t)c * K];
+    }
+    const float S = wave_sum(part);
+    for (int b0 = 0; b0 < V; b0 += 64) {
+        const int c = b0 + (int)lane;
+        if (c < V) out[(size_t)c * K] = S > 0.0f ? out[(size_t)c * K] / S : 0.0f;
+    }
+    rn.close(meta[k]);
+    re.close(meta[k]);
 }
 
 // theta_d ~ Dir(alpha + n_d.), then one uniform per token (token order) and
@@ -1084,8 +1116,8 @@ brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
     hipEvent_t ts = c->t_start, te = c->t_stop;
     if (d->sweeps) c->t_start = c->t_stop = nullptr;
     for (uint32_t s = 0; s < d->sweeps; ++s) {
-        hipLaunchKernelGGL(k_ldaf_topics, dim3((K + wpb - 1) / wpb), blk, 0, c->stream, c->meta, P,
-                           (int)K, (int)V, d->beta, d->d_nkw, d->d_phi);
+        hipLaunchKernelGGL(k_ldaf_topics, dim3(K), dim3(64), 0, c->stream, c->meta, P, (int)K,
+                           (int)V, d->beta, d->d_nkw, d->d_phi);
         zero(d->d_nkw, (uint64_t)K * V);
         const dim3 grid((D + wpb - 1) / wpb);
         const size_t lds = 0;

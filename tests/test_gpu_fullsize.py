@@ -214,3 +214,66 @@ def test_lda_full_size(dev):
                 break
     print("lda full-size diverged docs", diverged, flush=True)
     assert diverged <= 1
+
+
+def test_lda_full_full_size(dev):
+    """Full LDA at the bench's size (16,384 documents, 64 topics, 4,096
+    words, window 512): two calls of one sweep; every topic's phi and eight
+    sampled documents (theta, every token's topic, n_d.) against the oracle
+    replayed from the device's state, n_kw against the counts of the new
+    assignment."""
+    import torch
+    b = _b()
+    K, V, D = 64, 4096, 16384
+    c = workloads.lda_corpus(n_docs=D, n_topics=K, n_vocab=V, seed=SEED)
+    off, words, z0 = c["offsets"], c["words"], c["z0"]
+    T = int(off[-1])
+    _say("lda_full full size", D, K, V, T)
+    ctx = b.brng_create(SEED, K + D, [512, 512, 512, 0], layout=b.BRNG_LAYOUT_ITEMS,
+                        stream=torch.cuda.current_stream())
+    tz = _t(z0, dev)
+    ndk = torch.zeros(D * K, dtype=torch.int32, device=dev)
+    nkw = torch.zeros(K * V, dtype=torch.int32, device=dev)
+    th = torch.zeros(D * K, dtype=torch.float32, device=dev)
+    phi = torch.zeros(K * V, dtype=torch.float32, device=dev)
+    docs = [0, 1, 777, 4096, 9000, 12345, 16000, D - 1]
+    cur = oracle.new_cursors(K + D)
+    z_in = z0.copy()
+    flips = 0
+    try:
+        toff, tw = _t(off, dev), _t(words, dev)
+        for call in range(2):
+            b.brng_run_lda_full(ctx, K, V, 1, 0.1, 0.05, toff, tw, tz, ndk, nkw, th, phi)
+            gz = tz.cpu().numpy()
+            gth = th.cpu().numpy()
+            gphi = np.ascontiguousarray(phi.cpu().numpy().reshape(V, K).T)
+            gndk = ndk.cpu().numpy().reshape(D, K)
+            gnkw = nkw.cpu().numpy().reshape(K, V)
+            gcur = b.brng_get_cursors(ctx)
+            torch.cuda.synchronize()
+            r = oracle.lda_full_sweep(SEED, cur, K, V, 0.1, 0.05, off, words, z_in,
+                                      theta32=gth, phi32=gphi.ravel(), docs=docs)
+            okp = within(gphi, r["phi"], r["phi_tol"])
+            bad_topics = [k for k in range(K) if not okp[k].all()]
+            for k in bad_topics:
+                assert r["phi_margin"][k] <= 1.0, (call, k)
+            flips += len(bad_topics)
+            for d in docs:
+                okt = within(gth.reshape(D, K)[d], r["theta"][d], r["theta_tol"][d]).all()
+                if not okt:
+                    assert r["theta_margin"][d] <= 1.0, (call, d)
+                    flips += 1
+                sl = slice(off[d], off[d + 1])
+                assert np.array_equal(gz[sl], r["z"][sl]), (call, d)
+            ndk_ref, nkw_ref = oracle.lda_full_counts(K, V, off, words, gz)
+            assert np.array_equal(gndk[docs], ndk_ref[docs]), call
+            assert np.array_equal(gnkw, nkw_ref), call
+            units = list(range(K)) + [K + d for d in docs]
+            same = [u for u in units if np.array_equal(gcur[u], cur[u])]
+            assert len(same) >= len(units) - 2, call
+            cur[:] = gcur
+            z_in = gz
+    finally:
+        b.brng_destroy(ctx)
+    print("lda_full full-size flips", flips, flush=True)
+    assert flips <= 2

@@ -149,3 +149,23 @@ def test_dirichlet_shapes_are_prior_plus_counts():
     se_th = np.sqrt(m_th * (1 - m_th) / (b0 + 1) / n)
     assert (np.abs(phis.mean(axis=0) - m_phi) < 5 * se_phi + 1e-12).all()
     assert (np.abs(ths.mean(axis=0) - m_th) < 5 * se_th + 1e-12).all()
+
+
+def test_document_subset_equals_full_sweep_on_those_documents():
+    rng = np.random.default_rng(6)
+    K, V, D = 6, 30, 10
+    off, words = _corpus(rng, D, V, 0, 40)
+    z0 = rng.integers(0, K, size=words.size).astype(np.int32)
+    full = oracle.lda_full_sweep(8, oracle.new_cursors(K + D), K, V, 0.1, 0.05, off, words, z0)
+    docs = [1, 4, 9]
+    cur = oracle.new_cursors(K + D)
+    sub = oracle.lda_full_sweep(8, cur, K, V, 0.1, 0.05, off, words, z0, docs=docs)
+    assert np.array_equal(sub["phi"], full["phi"])
+    for d in docs:
+        assert np.array_equal(sub["theta"][d], full["theta"][d])
+        sl = slice(off[d], off[d + 1])
+        assert np.array_equal(sub["z"][sl], full["z"][sl])
+        assert np.array_equal(cur[K + d], full["cursors"][K + d])
+    others = [d for d in range(D) if d not in docs]
+    assert np.isnan(sub["theta"][others]).all()
+    assert (cur[[K + d for d in others]] == 0).all()
