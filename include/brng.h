@@ -191,7 +191,9 @@ brng_status brng_step_dirichlet(brng_ctx *ctx, const int32_t *d_offsets,
  * enabled, at least n_topics + n_docs items; topic k is unit k, document d
  * unit n_topics + d, and every call continues those units' streams.
  * The state is the assignment d_z (int32 per token, in/out): a call first
- * recounts n_dk and n_kw from it, then runs `sweeps` sweeps; on return z,
+ * recounts n_dk and n_kw from it (skipped with flags BRNG_LDAF_COUNTS_VALID,
+ * when d_ndk and d_nkw already hold the counts of d_z, as a previous call
+ * returned them), then runs `sweeps` sweeps; on return z,
  * n_dk ([n_docs][n_topics] int32) and n_kw ([n_topics][n_vocab] int32) are
  * consistent, and theta ([n_docs][n_topics]) and phi ([n_vocab][n_topics],
  * word-major: a token's topic weights are one row) hold the last sweep's
@@ -209,7 +211,7 @@ typedef struct {
     int32_t n_tokens;
     float alpha;               /* document-topic prior */
     float beta;                /* topic-word prior */
-    uint32_t pad;
+    uint32_t flags;            /* BRNG_LDAF_COUNTS_VALID or 0 */
     const int32_t *d_doc_offsets; /* n_docs + 1 token offsets */
     const int32_t *d_words;    /* word id per token */
     int32_t *d_z;              /* topic per token (in/out) */
@@ -218,6 +220,7 @@ typedef struct {
     float *d_theta;            /* out: [n_docs][n_topics] */
     float *d_phi;              /* out: [n_vocab][n_topics] */
 } brng_lda_full_desc;
+enum { BRNG_LDAF_COUNTS_VALID = 1u };
 brng_status brng_run_lda_full(brng_ctx *ctx, const brng_lda_full_desc *h_desc);
 
 /* ---------------------------------------------------------------------- */

@@ -22,6 +22,7 @@ BRNG_F32, BRNG_F64 = 0, 1
 BRNG_LAYOUT_CHAINS, BRNG_LAYOUT_ITEMS = 0, 1
 BRNG_MODEL_TRIANGLE_F64, BRNG_MODEL_NORMEXP, BRNG_MODEL_GAMMA_CHAIN, BRNG_MODEL_LDA, BRNG_MODEL_EXP_CHAIN = range(5)
 BRNG_FLAG_RESUME = 1
+BRNG_LDAF_COUNTS_VALID = 1
 UNIT_WIDTH = 64
 WINDOW_ALIGN = 256
 WINDOW_MIN = 512
@@ -79,7 +80,7 @@ class brng_lda_full_desc(C.Structure):
         ("n_tokens", C.c_int32),
         ("alpha", C.c_float),
         ("beta", C.c_float),
-        ("pad", C.c_uint32),
+        ("flags", C.c_uint32),
         ("d_doc_offsets", C.c_void_p),
         ("d_words", C.c_void_p),
         ("d_z", C.c_void_p),
@@ -371,10 +372,13 @@ def brng_set_launch(ctx: int, waves_per_block: int) -> None:
 
 
 def brng_run_lda_full(ctx: int, n_topics: int, n_vocab: int, sweeps: int, alpha: float,
-                      beta: float, doc_offsets, words, z, ndk, nkw, theta, phi) -> None:
+                      beta: float, doc_offsets, words, z, ndk, nkw, theta, phi,
+                      counts_valid: bool = False) -> None:
     """Full LDA sweeps over the corpus (device int32 doc_offsets, words, z;
-    outputs ndk, nkw, theta, phi)."""
+    outputs ndk, nkw, theta, phi); counts_valid skips the recount of ndk and
+    nkw from z."""
     d = brng_lda_full_desc()
+    d.flags = BRNG_LDAF_COUNTS_VALID if counts_valid else 0
     d.n_docs = int(doc_offsets.numel()) - 1
     d.n_topics, d.n_vocab, d.sweeps = int(n_topics), int(n_vocab), int(sweeps)
     d.n_tokens = int(words.numel()) if words is not None else 0

@@ -1105,12 +1105,15 @@ brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
         const uint64_t g = std::min<uint64_t>((n + 255) / 256, 4096);
         if (g) hipLaunchKernelGGL(k_zero_i32, dim3((uint32_t)g), dim3(256), 0, c->stream, p, n);
     };
-    zero(d->d_ndk, (uint64_t)D * K);
-    zero(d->d_nkw, (uint64_t)K * V);
-    hipLaunchKernelGGL(k_ldaf_recount, dim3((D + wpb - 1) / wpb), blk, 0, c->stream, D, (int)K,
-                       (int)V, d->d_doc_offsets, d->n_tokens, d->d_words, d->d_z, d->d_ndk,
-                       d->d_nkw);
-    HIPCHK(hipGetLastError());
+    if (d->flags & ~(uint32_t)BRNG_LDAF_COUNTS_VALID) return BRNG_E_ARG;
+    if (!(d->flags & BRNG_LDAF_COUNTS_VALID)) {
+        zero(d->d_ndk, (uint64_t)D * K);
+        zero(d->d_nkw, (uint64_t)K * V);
+        hipLaunchKernelGGL(k_ldaf_recount, dim3((D + wpb - 1) / wpb), blk, 0, c->stream, D, (int)K,
+                           (int)V, d->d_doc_offsets, d->n_tokens, d->d_words, d->d_z, d->d_ndk,
+                           d->d_nkw);
+        HIPCHK(hipGetLastError());
+    }
     // a pending event pair (brng_time_next_launch) times the last sweep's
     // document kernel
     hipEvent_t ts = c->t_start, te = c->t_stop;

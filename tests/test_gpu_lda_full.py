@@ -116,28 +116,32 @@ def test_lda_full_sweep_replay(dev, K, V, D, mean_len):
 
 
 def test_lda_full_many_sweeps_equal_single_sweeps(dev):
-    """Six sweeps in one call equal six calls of one sweep, bit for bit, and
-    the counts returned are those of the final assignment."""
+    """Six sweeps in one call equal six calls of one sweep, bit for bit, with
+    or without the recount between calls, and the counts returned are those
+    of the final assignment."""
     import torch
     b = _b()
     K, V, D, seed = 16, 256, 30, 4242
     off, words, z0 = _corpus(D, K, V, 80.0, seed=5)
     _say("lda_full sweeps in one call", K, V, D)
     res = []
-    for calls, per in ((1, 6), (6, 1)):
+    for calls, per, valid in ((1, 6, False), (6, 1, False), (6, 1, True)):
         ctx = b.brng_create(seed, K + D, [512, 512, 512, 0], layout=b.BRNG_LAYOUT_ITEMS,
                             stream=torch.cuda.current_stream())
         buf = _bufs(dev, D, K, V, words, z0)
         try:
-            for _ in range(calls):
+            for c in range(calls):
+                # with `valid`, calls after the first skip the recount
                 b.brng_run_lda_full(ctx, K, V, per, 0.1, 0.05, _t(off, dev), buf["words"],
-                                    buf["z"], buf["ndk"], buf["nkw"], buf["theta"], buf["phi"])
+                                    buf["z"], buf["ndk"], buf["nkw"], buf["theta"], buf["phi"],
+                                    counts_valid=valid and c > 0)
             res.append([_np(buf[k]) for k in ("z", "ndk", "nkw", "theta", "phi")] +
                        [b.brng_get_cursors(ctx)])
         finally:
             b.brng_destroy(ctx)
-    for x, y in zip(res[0], res[1]):
-        assert np.array_equal(x, y)
+    for r in res[1:]:
+        for x, y in zip(res[0], r):
+            assert np.array_equal(x, y)
     ndk, nkw = oracle.lda_full_counts(K, V, off, words, res[0][0])
     assert np.array_equal(res[0][1].reshape(D, K), ndk)
     assert np.array_equal(res[0][2].reshape(K, V), nkw)
