@@ -11,8 +11,9 @@ sweep replayed by the oracle from the device's own state:
 - cursors equal for every unit without such a decision.
 
 Cases: ragged documents (empty ones, up to a few hundred tokens) with a few
-word ids outside the vocabulary, topic counts 1, 13 and 64 (the limit), and
-a launch of all sweeps at once equal to the sweep-by-sweep calls."""
+word ids outside the vocabulary, topic counts 1, 13 and 64 (the limit), a
+launch of all sweeps at once equal to the sweep-by-sweep calls, and window
+length and workgroup size changing nothing."""
 import numpy as np
 import pytest
 
@@ -163,3 +164,30 @@ def test_lda_full_rejects_bad_arguments(dev):
                                     buf["ndk"], buf["nkw"], buf["theta"], buf["phi"])
     finally:
         b.brng_destroy(ctx)
+
+
+def test_lda_full_window_and_launch_shape_invariance(dev):
+    """Window length and waves per workgroup are speed knobs only: three
+    configurations give the same topics, counts, draws and cursors bit for
+    bit over three sweeps."""
+    import torch
+    b = _b()
+    K, V, D, seed = 24, 700, 50, 99
+    off, words, z0 = _corpus(D, K, V, 90.0, seed=7)
+    _say("lda_full window/launch invariance", K, V, D)
+    res = []
+    for win, wpb in ((512, 4), (4096, 1), (1024, 8)):
+        ctx = b.brng_create(seed, K + D, [win, win, win, 0], layout=b.BRNG_LAYOUT_ITEMS,
+                            stream=torch.cuda.current_stream())
+        buf = _bufs(dev, D, K, V, words, z0)
+        try:
+            b.brng_set_launch(ctx, wpb)
+            b.brng_run_lda_full(ctx, K, V, 3, 0.1, 0.05, _t(off, dev), buf["words"], buf["z"],
+                                buf["ndk"], buf["nkw"], buf["theta"], buf["phi"])
+            res.append([_np(buf[k]) for k in ("z", "ndk", "nkw", "theta", "phi")] +
+                       [b.brng_get_cursors(ctx)])
+        finally:
+            b.brng_destroy(ctx)
+    for r in res[1:]:
+        for x, y in zip(res[0], r):
+            assert np.array_equal(x, y)
