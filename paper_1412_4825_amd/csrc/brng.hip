@@ -604,24 +604,29 @@ __global__ __launch_bounds__(64) void k_ldaf_topics(Meta* meta, Pools P, int K, 
 // (one per lane, in token order); then the wave works on one token at a
 // time with lane k on topic k (K <= 64): one coalesced read of the token's
 // phi row, the maximum and the prefix sums by DPP, the topic by a ballot.
-// New n_d. in place (lane k counts topic k), n_kw added atomically (zero on
-// entry).
+// New n_d. in place (LDS counts), n_kw added atomically (zero on entry), both
+// once per group of 64 tokens.
 __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t D, int K, int V,
                                                    float alpha, const int32_t* doff,
                                                    int32_t n_tokens, const int32_t* words,
                                                    const float* phi, float* theta, int32_t* z,
                                                    int32_t* ndk, int32_t* nkw) {
+    extern __shared__ int32_t ldaf_cnt[];
     const uint32_t d = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
     if (d >= D) return;
     const uint32_t lane = lane_id();
     const uint32_t unit = (uint32_t)K + d;
     const bool topic = (int)lane < K;
+    int32_t* cnt = ldaf_cnt + 64 * wave_in_block();  // tokens per topic
     float* th_row = theta + (size_t)d * K;
     int32_t* ndk_row = ndk + (size_t)d * K;
     dirichlet_unit(meta, P, unit, K, nullptr, ndk_row, alpha, th_row);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     const float th = topic ? th_row[lane] : 0.0f;
-    int32_t mycnt = 0;  // tokens of topic `lane`
+    cnt[lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     DirectReader<KIND_U> ru;
     ru.open(meta[unit], P.u + (size_t)unit * P.W[KIND_U], P.W[KIND_U]);
     const int32_t a = max(doff[d], 0), b = min(doff[d + 1], n_tokens);
@@ -646,13 +651,19 @@ __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t
             const uint32_t t = (uint32_t)(((uint64_t)j * Q) >> 23);
             const int32_t zt = (int32_t)__popcll(wave_ballot(topic && (uint32_t)C <= t));
             if ((int)lane == r) zl = zt;
-            if ((int)lane == zt) ++mycnt;
-            if (lane == 0) atomicAdd(&nkw[(size_t)zt * V + w], 1);
         }
+        // the group's counts: one atomic per token, issued together
         if (act) z[i] = zl;
+        if (zl >= 0) {
+            atomicAdd(&cnt[zl], 1);
+            atomicAdd(&nkw[(size_t)zl * V + wl], 1);
+        }
     }
     ru.close(meta[unit]);
-    if (topic) ndk_row[lane] = mycnt;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (topic) ndk_row[lane] = cnt[lane];
 }
 
 template <int MODEL>
@@ -1123,7 +1134,7 @@ brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
                            (int)V, d->beta, d->d_nkw, d->d_phi);
         zero(d->d_nkw, (uint64_t)K * V);
         const dim3 grid((D + wpb - 1) / wpb);
-        const size_t lds = 0;
+        const size_t lds = (size_t)wpb * 64 * sizeof(int32_t);
         if (ts && s + 1 == d->sweeps)
             hipExtLaunchKernelGGL(k_ldaf_docs, grid, blk, (uint32_t)lds, c->stream, ts, te, 0u,
                                   c->meta, P, D, (int)K, (int)V, d->alpha, d->d_doc_offsets,
