@@ -554,18 +554,34 @@ __global__ __launch_bounds__(512) void k_ldaf_recount(uint32_t D, int K, int V,
     }
 }
 
-// phi_k ~ Dir(beta + n_k.), one wave (and workgroup) per topic, its pools
-// staged through LDS by the epoch readers of the LDA kernel (a topic has
-// thousands of components, so its rounds are many and sequential); phi is
-// word-major ([V][K]), so that a token's K weights are one contiguous row.
+// The sweep's Dirichlets in one launch, one wave (and workgroup) each: the
+// first K workgroups draw phi_k ~ Dir(beta + n_k.) (topic k), the others
+// theta_d ~ Dir(alpha + n_d.) (document d = block - K), so that the few long
+// topic draws run beside the many short document ones.  A topic's pools are
+// staged through LDS by the epoch readers of the LDA kernel (its thousands of
+// components are many sequential rounds); phi is word-major ([V][K]), so
+// that a token's K weights are one contiguous row.
 constexpr int LDAF_TOPIC_LDS = LdaRN::LDS_BYTES + LdaRE::LDS_BYTES;
-__global__ __launch_bounds__(64) void k_ldaf_topics(Meta* meta, Pools P, int K, int V, float beta,
-                                                    const int32_t* nkw, float* phi) {
+__global__ __launch_bounds__(64) void k_ldaf_dirichlets(Meta* meta, Pools P, uint32_t D, int K,
+                                                        int V, float alpha, float beta,
+                                                        const int32_t* ndk, const int32_t* nkw,
+                                                        float* theta, float* phi) {
     __shared__ __align__(16) unsigned char lds[LDAF_TOPIC_LDS];
-    const uint32_t k = blockIdx.x;
-    if (k >= (uint32_t)K) return;
+    const uint32_t blk = blockIdx.x;
+    if (blk >= (uint32_t)K) {
+        const uint32_t d = blk - (uint32_t)K;
+        if (d >= D) return;
+        dirichlet_unit(meta, P, blk, K, nullptr, ndk + (size_t)d * K, alpha,
+                       theta + (size_t)d * K);
+        return;
+    }
+    const uint32_t k = blk;
     const uint32_t lane = lane_id();
-    const Meta m = meta[k];
+    Meta m = meta[k];
+    // the key words feed the scalar key schedule: make them provably uniform
+    m.key_unit = __builtin_amdgcn_readfirstlane(m.key_unit);
+    m.key_seed = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(m.key_seed >> 32)) << 32) |
+                 (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)m.key_seed);
     LdaRN rn;
     LdaRE re;
     rn.open(m, P.n + (size_t)k * P.W[KIND_N], P.W[KIND_N], reinterpret_cast<float*>(lds));
@@ -595,8 +611,8 @@ __global__ __launch_bounds__(64) void k_ldaf_topics(Meta* meta, Pools P, int K, 
     re.close(meta[k]);
 }
 
-// theta_d ~ Dir(alpha + n_d.), then one uniform per token (token order) and
-// its topic: p_k = theta_k phi_w,k in fp32, q_k = rint(p_k 2^(24 - e)) with
+// One uniform per token of document d (token order; theta_d drawn by the
+// Dirichlet launch before) and the token's topic: p_k = theta_k phi_w,k in fp32, q_k = rint(p_k 2^(24 - e)) with
 // max p = f 2^e, f in [1/2, 1) (an exact scaling; all 1 when max p = 0),
 // C_k = q_0 + ... + q_k, j = (u 2^24 - 1) / 2, t = (j C_{K-1}) >> 23,
 // z = the number of k with C_k <= t.  A word outside [0, V) gets z = -1 and
@@ -607,10 +623,10 @@ __global__ __launch_bounds__(64) void k_ldaf_topics(Meta* meta, Pools P, int K, 
 // New n_d. in place (LDS counts), n_kw added atomically (zero on entry), both
 // once per group of 64 tokens.
 __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t D, int K, int V,
-                                                   float alpha, const int32_t* doff,
-                                                   int32_t n_tokens, const int32_t* words,
-                                                   const float* phi, float* theta, int32_t* z,
-                                                   int32_t* ndk, int32_t* nkw) {
+                                                   const int32_t* doff, int32_t n_tokens,
+                                                   const int32_t* words, const float* phi,
+                                                   const float* theta, int32_t* z, int32_t* ndk,
+                                                   int32_t* nkw) {
     extern __shared__ int32_t ldaf_cnt[];
     const uint32_t d = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
     if (d >= D) return;
@@ -618,10 +634,8 @@ __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t
     const uint32_t unit = (uint32_t)K + d;
     const bool topic = (int)lane < K;
     int32_t* cnt = ldaf_cnt + 64 * wave_in_block();  // tokens per topic
-    float* th_row = theta + (size_t)d * K;
+    const float* th_row = theta + (size_t)d * K;
     int32_t* ndk_row = ndk + (size_t)d * K;
-    dirichlet_unit(meta, P, unit, K, nullptr, ndk_row, alpha, th_row);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     const float th = topic ? th_row[lane] : 0.0f;
     cnt[lane] = 0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1130,20 +1144,22 @@ brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
     hipEvent_t ts = c->t_start, te = c->t_stop;
     if (d->sweeps) c->t_start = c->t_stop = nullptr;
     for (uint32_t s = 0; s < d->sweeps; ++s) {
-        hipLaunchKernelGGL(k_ldaf_topics, dim3(K), dim3(64), 0, c->stream, c->meta, P, (int)K,
-                           (int)V, d->beta, d->d_nkw, d->d_phi);
+        hipLaunchKernelGGL(k_ldaf_dirichlets, dim3(K + D), dim3(64), 0, c->stream, c->meta, P, D,
+                           (int)K, (int)V, d->alpha, d->beta, (const int32_t*)d->d_ndk,
+                           (const int32_t*)d->d_nkw, d->d_theta, d->d_phi);
         zero(d->d_nkw, (uint64_t)K * V);
         const dim3 grid((D + wpb - 1) / wpb);
         const size_t lds = (size_t)wpb * 64 * sizeof(int32_t);
         if (ts && s + 1 == d->sweeps)
             hipExtLaunchKernelGGL(k_ldaf_docs, grid, blk, (uint32_t)lds, c->stream, ts, te, 0u,
-                                  c->meta, P, D, (int)K, (int)V, d->alpha, d->d_doc_offsets,
-                                  d->n_tokens, d->d_words, (const float*)d->d_phi, d->d_theta,
+                                  c->meta, P, D, (int)K, (int)V, d->d_doc_offsets, d->n_tokens,
+                                  d->d_words, (const float*)d->d_phi, (const float*)d->d_theta,
                                   d->d_z, d->d_ndk, d->d_nkw);
         else
             hipLaunchKernelGGL(k_ldaf_docs, grid, blk, lds, c->stream, c->meta, P, D, (int)K,
-                               (int)V, d->alpha, d->d_doc_offsets, d->n_tokens, d->d_words,
-                               d->d_phi, d->d_theta, d->d_z, d->d_ndk, d->d_nkw);
+                               (int)V, d->d_doc_offsets, d->n_tokens, d->d_words,
+                               (const float*)d->d_phi, (const float*)d->d_theta, d->d_z, d->d_ndk,
+                               d->d_nkw);
         HIPCHK(hipGetLastError());
     }
     HIPCHK(hipGetLastError());
