@@ -327,11 +327,11 @@ def setup_lda(torch, b, args):
 
 
 def _cpu_lda_full(a):
-    seed, K, V, off, words, z0, alpha, beta = a
+    seed, K, V, off, words, z0, alpha, beta, docs = a
     import oracle
     t = time.perf_counter()
     oracle.lda_full_sweep(seed, oracle.new_cursors(K + off.size - 1), K, V, alpha, beta, off,
-                          words, z0)
+                          words, z0, docs=docs)
     return time.perf_counter() - t
 
 
@@ -379,15 +379,20 @@ def setup_lda_full(torch, b, args):
         return 8.0 * ent + 4.0 * (2 * nd * K + 3 * T)
 
     def cpu(workers):
+        # one sweep over the first sd documents, the documents split over the
+        # workers (each also draws the topics, counted once)
         sd = min(nd, args.cpu_units or 4096)
         off = c["offsets"][:sd + 1].astype(np.int32)
         n = int(off[-1])
-        busy = _cpu_lda_full((args.seed, K, V, off, c["words"][:n], c["z0"][:n], alpha, beta))
+        jobs = [(args.seed, K, V, off, c["words"][:n], c["z0"][:n], alpha, beta,
+                 list(range(d0, d1))) for d0, d1 in _slices(sd, workers)]
+        wall, busy = _pool_run(_cpu_lda_full, jobs)
         sdv = K * V + sd * K + n
-        return {"value": sdv / busy, "unit": "deviates/s", "cores": 1, "kind": "oracle",
-                "sample": "one sweep of the first %d of %d documents (all %d x %d topic-word "
-                          "draws, %d tokens; %.3g deviates) in one process; %.1f s"
-                          % (sd, nd, K, V, n, sdv, busy)}
+        return {"value": sdv / wall, "unit": "deviates/s", "cores": len(jobs), "kind": "oracle",
+                "sample": "one sweep of the first %d of %d documents (%d x %d topic-word draws, "
+                          "%d tokens; %.3g deviates) over %d processes, each drawing the topics "
+                          "and its documents; %.1f s of CPU work"
+                          % (sd, nd, K, V, n, sdv, len(jobs), busy)}
 
     return dict(ctx=ctx, run=run, kinds=[b.BRNG_U, b.BRNG_N, b.BRNG_E],
                 keep=(toff, tw, tz, ndk, nkw, th, phi),
