@@ -94,6 +94,12 @@ def _declare(L):
     L.or_expchain.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, _dp, _u64p, _dp, _dp]
     L.or_gamma_chain.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _i32p, _i32p, _dp, _u64p, _dp, _dp, _dp,
                                  _i32p, _i32p]
+    L.or_normexp_replay.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
+                                    _dp, _dp, _u64p, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.or_expchain_replay.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
+                                     _dp, _u64p, _dp, _dp, _dp, _dp]
+    L.or_gamma_chain_replay.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _i32p, _i32p, _dp,
+                                        _u64p, _dp, _dp, _dp, _i32p, _i32p]
     L.or_lda.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _i32p, _i32p, C.c_uint32, _i32p, _u64p, _dp, _dp, _i32p, _dp, _dp]
 
 
@@ -365,6 +371,77 @@ def gamma_chain(seed, alpha0, steps, perm=None, cursors=None, width=UNIT_WIDTH, 
                          _p(gr0, _i32p), _p(gr1, _i32p))
     return dict(alpha=alpha, gtrace=gtr, gtol=gtol, gmargin=gmar, gr0=gr0, gr1=gr1, perm=perm,
                 cursors=cur)
+
+
+# --------------------------------------------------------------------------
+# Per-step replay of the fp32 chain models: every output recomputed from the
+# state the tested run held before that step (an exact input), so that each
+# output is held to the single-result bar instead of a bound propagated along
+# the chain.
+# --------------------------------------------------------------------------
+
+def normexp_replay(seed, s_in, sp_in, fresh, cursors=None, width=UNIT_WIDTH, unit0=0):
+    """s_in[t][c]: state before step t; sp_in[t][c]: the s' the tested run
+    used for step t's exponential.  fresh: the starting N call is consumed
+    (s0/s0tol report it).  Returns dict with strace/stol/etrace/etol."""
+    s_in = _d(s_in)
+    sp_in = _d(sp_in)
+    steps, n = s_in.shape
+    nu = _n_units(n, width)
+    cur = new_cursors(nu) if cursors is None else cursors
+    s0, s0t = np.zeros(n), np.zeros(n)
+    str_, etr, stol, etol = (np.zeros((steps, n)) for _ in range(4))
+    lib().or_normexp_replay(seed, unit0, n, width, steps, 1 if fresh else 0, _p(s_in, _dp),
+                            _p(sp_in, _dp), _p(cur, _u64p), _p(s0, _dp), _p(s0t, _dp),
+                            _p(str_, _dp), _p(etr, _dp), _p(stol, _dp), _p(etol, _dp))
+    return dict(s0=s0, s0tol=s0t, strace=str_, stol=stol, etrace=etr, etol=etol, cursors=cur)
+
+
+def expchain_replay(seed, e_in, fresh, cursors=None, width=UNIT_WIDTH, unit0=0):
+    """e_in[t][c]: state before step t.  fresh: the starting E call is
+    consumed (e0/e0tol report it)."""
+    e_in = _d(e_in)
+    steps, n = e_in.shape
+    nu = _n_units(n, width)
+    cur = new_cursors(nu) if cursors is None else cursors
+    e0, e0t = np.zeros(n), np.zeros(n)
+    etr, etol = np.zeros((steps, n)), np.zeros((steps, n))
+    lib().or_expchain_replay(seed, unit0, n, width, steps, 1 if fresh else 0, _p(e_in, _dp),
+                             _p(cur, _u64p), _p(e0, _dp), _p(e0t, _dp), _p(etr, _dp), _p(etol, _dp))
+    return dict(e0=e0, e0tol=e0t, etrace=etr, etol=etol, cursors=cur)
+
+
+def gamma_chain_replay(seed, shape, steps, perm=None, cursors=None, width=UNIT_WIDTH, unit0=0):
+    """shape[t][slot]: the shape of each slot's draw at step t (exact).
+    steps per chain (user order), perm slot -> chain.  Outputs as
+    gamma_chain (traces [t][slot])."""
+    shape = _d(shape)
+    steps = np.ascontiguousarray(steps, dtype=np.int32)
+    smax, n = shape.shape
+    if perm is None:
+        perm = sort_by_length(steps)
+    perm = np.ascontiguousarray(perm, dtype=np.int32)
+    nu = _n_units(n, width)
+    cur = new_cursors(nu) if cursors is None else cursors
+    gtr, gtol, gmar = (np.full((smax, n), np.nan) for _ in range(3))
+    gr0, gr1 = (np.full((smax, n), -1, dtype=np.int32) for _ in range(2))
+    lib().or_gamma_chain_replay(seed, unit0, n, width, _p(perm, _i32p), _p(steps, _i32p),
+                                _p(shape, _dp), _p(cur, _u64p), _p(gtr, _dp), _p(gtol, _dp),
+                                _p(gmar, _dp), _p(gr0, _i32p), _p(gr1, _i32p))
+    return dict(gtrace=gtr, gtol=gtol, gmargin=gmar, gr0=gr0, gr1=gr1, perm=perm, cursors=cur)
+
+
+def chain_shapes_fp32(alpha0_slots, g):
+    """Shapes an fp32 gamma chain forms: row 0 the starting shapes, row t the
+    fp32 sum 0.1f + g[t-1] (g: [t][slot] fp32 draws).  Plain fp32 addition,
+    correctly rounded, as the chain's definition alpha' = 0.1 + g states it
+    in that precision."""
+    g32 = np.asarray(g, dtype=np.float32)
+    out = np.empty(g32.shape, dtype=np.float32)
+    out[0] = np.asarray(alpha0_slots, dtype=np.float32)
+    if g32.shape[0] > 1:
+        out[1:] = np.float32(0.1) + g32[:-1]
+    return out.astype(np.float64)
 
 
 def lda(seed, offsets, ntok, sweeps, counts0=None, cursors=None, unit0=0):

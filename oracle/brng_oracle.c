@@ -1345,6 +1345,7 @@ typedef struct {
     uint32_t n, lo;
     double *gtr, *gtol, *gmar;
     int32_t *gr0, *gr1;
+    const double *ash; /* replay: the shape of every draw, [t][slot], or NULL */
 } chains_t;
 
 static int chains_next(gsrc_t *g, int k, double *alpha, double *abound)
@@ -1366,12 +1367,19 @@ static void chains_done(gsrc_t *g, int k, const gdraw_t *r)
     if (c->gmar) c->gmar[o] = r->margin;
     if (c->gr0) c->gr0[o] = r->r0;
     if (c->gr1) c->gr1[o] = r->r1;
+    c->t[k]++;
+    if (c->ash) {
+        /* replay: the next draw's shape is given exactly */
+        if (c->t[k] < c->L[k])
+            c->a[k] = c->ash[(size_t)c->t[k] * c->n + c->lo + (size_t)k];
+        c->ab[k] = 0.0;
+        return;
+    }
     double an = 0.1 + r->g;
     /* the next shape carries g's bound plus the fp32 rounding of 0.1 + g
      * and of the constant 0.1 itself */
     c->ab[k] = r->tol + ulp32(an) + 2e-9;
     c->a[k] = an;
-    c->t[k]++;
 }
 
 void or_gamma_chain(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, const int32_t *perm,
@@ -1394,6 +1402,7 @@ void or_gamma_chain(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, c
         cs->gmar = gmar;
         cs->gr0 = gr0;
         cs->gr1 = gr1;
+        cs->ash = NULL;
         for (int k = 0; k < ns; k++) {
             uint32_t ch = perm ? (uint32_t)perm[lo + k] : lo + k;
             cs->a[k] = alpha[ch];
@@ -1407,6 +1416,139 @@ void or_gamma_chain(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width, c
             uint32_t ch = perm ? (uint32_t)perm[lo + k] : lo + k;
             alpha[ch] = cs->a[k];
         }
+    }
+    free(cs);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-step replay of the fp32 chain models.  A free-running chain in fp32  */
+/* drifts away from its double-precision twin: each step amplifies the      */
+/* rounding of the state it starts from.  Replay removes the drift from the */
+/* check.  Every output is recomputed here from the state the implementation */
+/* under test actually held before that step (given as input, exact), from  */
+/* the same pool entries, in the same consumption order, so that each        */
+/* output carries only its own step's rounding and is held to the single-   */
+/* result bar max(4 ulp32(M), 1e-6 M).  The state values are inputs only:   */
+/* nothing of the implementation's arithmetic enters the recomputation.     */
+/* ------------------------------------------------------------------------ */
+
+/* Normal/exponential chain, replayed.  s_in[t][chain] is the state before
+ * step t (for t = 0 the starting state; for t > 0 the value the tested run
+ * produced at step t - 1); sp_in[t][chain] is the s' of step t that the
+ * tested run then used for its exponential.  fresh: the run first drew its
+ * starting state as one N call, which is consumed here too (s0_ref receives
+ * those Gaussians and s0_tol their bar; the replay itself starts from
+ * s_in[0]).  Outputs as or_normexp, with local bars only. */
+void or_normexp_replay(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width,
+                       uint32_t steps, int fresh, const double *s_in, const double *sp_in,
+                       uint64_t *cursors, double *s0_ref, double *s0_tol, double *str,
+                       double *etr, double *stol, double *etol)
+{
+    if (width == 0 || width > OR_MAXSLOT)
+        return;
+    uint32_t nu = (n + width - 1) / width;
+    for (uint32_t u = 0; u < nu; u++) {
+        stream_t st = {seed, unit0 + u, cursors + 4 * (size_t)u};
+        uint32_t lo, hi;
+        unit_range(n, width, u, &lo, &hi);
+        if (fresh) {
+            for (uint32_t c = lo; c < hi; c++) {
+                double z0 = take(&st, OR_N);
+                if (s0_ref) s0_ref[c] = z0;
+                if (s0_tol) s0_tol[c] = or_tol(z0);
+            }
+        }
+        for (uint32_t t = 0; t < steps; t++) {
+            size_t row = (size_t)t * n;
+            for (uint32_t c = lo; c < hi; c++) { /* N call */
+                double z = take(&st, OR_N);
+                double s = s_in[row + c];
+                double mu = 0.9 * s, sigma = 0.5 + fabs(s);
+                double sp = mu + sigma * z;
+                str[row + c] = sp;
+                stol[row + c] = or_tol(dmax(fabs(sp), dmax(fabs(mu), fabs(sigma * z))));
+            }
+            for (uint32_t c = lo; c < hi; c++) { /* E call */
+                double e = take(&st, OR_E);
+                double s = sp_in[row + c];
+                double v = e / (1.0 + s * s);
+                etr[row + c] = v;
+                etol[row + c] = or_tol(v);
+            }
+        }
+    }
+}
+
+/* Exponential chain, replayed: e_in[t][chain] is the state before step t
+ * (as or_normexp_replay's s_in); fresh: the starting E call is consumed and
+ * reported in e0_ref/e0_tol. */
+void or_expchain_replay(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width,
+                        uint32_t steps, int fresh, const double *e_in, uint64_t *cursors,
+                        double *e0_ref, double *e0_tol, double *etr, double *etol)
+{
+    if (width == 0 || width > OR_MAXSLOT)
+        return;
+    uint32_t nu = (n + width - 1) / width;
+    for (uint32_t u = 0; u < nu; u++) {
+        stream_t st = {seed, unit0 + u, cursors + 4 * (size_t)u};
+        uint32_t lo, hi;
+        unit_range(n, width, u, &lo, &hi);
+        if (fresh) {
+            for (uint32_t c = lo; c < hi; c++) {
+                double e0 = take(&st, OR_E);
+                if (e0_ref) e0_ref[c] = e0;
+                if (e0_tol) e0_tol[c] = or_tol(e0);
+            }
+        }
+        for (uint32_t t = 0; t < steps; t++) {
+            size_t row = (size_t)t * n;
+            for (uint32_t c = lo; c < hi; c++) {
+                double E = take(&st, OR_E);
+                double v = e_in[row + c];
+                double nv = E / (1.0 + v * v);
+                etr[row + c] = nv;
+                etol[row + c] = or_tol(nv);
+            }
+        }
+    }
+}
+
+/* Varying-shape gamma chain, replayed: shape[t][slot] is the shape of the
+ * slot's draw at step t (for t = 0 the starting shape; for t > 0 what the
+ * tested run formed from its own draw at step t - 1).  The slots run the
+ * gamma rounds exactly as in or_gamma_chain, but every draw starts from its
+ * given shape, which carries no error bound; outputs as or_gamma_chain. */
+void or_gamma_chain_replay(uint64_t seed, uint32_t unit0, uint32_t n, uint32_t width,
+                           const int32_t *perm, const int32_t *steps, const double *shape,
+                           uint64_t *cursors, double *gtr, double *gtol, double *gmar,
+                           int32_t *gr0, int32_t *gr1)
+{
+    if (width == 0 || width > OR_MAXSLOT)
+        return;
+    uint32_t nu = (n + width - 1) / width;
+    chains_t *cs = (chains_t *)malloc(sizeof(chains_t));
+    for (uint32_t u = 0; u < nu; u++) {
+        stream_t st = {seed, unit0 + u, cursors + 4 * (size_t)u};
+        uint32_t lo, hi;
+        unit_range(n, width, u, &lo, &hi);
+        int ns = (int)(hi - lo);
+        cs->n = n;
+        cs->lo = lo;
+        cs->gtr = gtr;
+        cs->gtol = gtol;
+        cs->gmar = gmar;
+        cs->gr0 = gr0;
+        cs->gr1 = gr1;
+        cs->ash = shape;
+        for (int k = 0; k < ns; k++) {
+            uint32_t ch = perm ? (uint32_t)perm[lo + k] : lo + k;
+            cs->a[k] = shape[lo + (size_t)k];
+            cs->ab[k] = 0.0;
+            cs->t[k] = 0;
+            cs->L[k] = steps[ch];
+        }
+        gsrc_t src = {chains_next, chains_done, cs};
+        or_gamma_rounds(&st, ns, &src);
     }
     free(cs);
 }

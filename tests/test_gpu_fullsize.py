@@ -56,6 +56,9 @@ def test_normexp_full_size(dev):
     te = torch.zeros((steps, n), dtype=torch.float32, device=dev)
     units = [0, 1, 511, 777, 1023]
     try:
+        # the starting states the fresh run draws (entries 0..63 of each
+        # sampled unit's Gaussian window, filled by brng_create)
+        s_first = np.concatenate([b.brng_get_window(ctx, b.BRNG_N, u)[2][:64] for u in units])
         b.brng_set_launch(ctx, 4)
         kw = dict(max_steps=steps, seed=SEED, trace=ts, trace2=te, trace_stride=n)
         b.brng_run_gibbs(ctx, b.gibbs_desc(b.BRNG_MODEL_NORMEXP, n, st, **kw))
@@ -71,6 +74,29 @@ def test_normexp_full_size(dev):
         cur = b.brng_get_cursors(ctx)
     finally:
         b.brng_destroy(ctx)
+    # the gate: per-step replay from the GPU's own states, both launches,
+    # every output at the single-result bar
+    for i, u in enumerate(units):
+        sl = slice(64 * i, 64 * i + 64)
+        starts = (s_first[sl], s_mid[64 * u:64 * u + 64])
+        qcur = None
+        for k, (gs, ge) in enumerate(runs):
+            s_in = np.vstack([starts[k][None, :], gs[:-1, sl]])
+            q = oracle.normexp_replay(SEED, s_in, gs[:, sl], k == 0, cursors=qcur, unit0=u)
+            qcur = q["cursors"]
+            if k == 0:
+                assert within(starts[0], q["s0"], q["s0tol"]).all(), u
+            for g, ref, tol, name in ((gs[:, sl], q["strace"], q["stol"], "s"),
+                                      (ge[:, sl], q["etrace"], q["etol"], "e")):
+                ok = within(g, ref, tol)
+                if not ok.all():
+                    t, c = np.argwhere(~ok)[0]
+                    print("normexp replay mismatch unit", u, "run", k, name, "step", t, "chain",
+                          c, "gpu", g[t, c], "ref", ref[t, c], "tol", tol[t, c], "count",
+                          int((~ok).sum()), flush=True)
+                assert ok.all(), (u, k, name)
+        assert np.array_equal(cur[u], qcur[0]), u
+    # free-running against the fp64 chains (bounds propagated along them)
     for i, u in enumerate(units):
         sl = slice(64 * i, 64 * i + 64)
         r1 = oracle.normexp(SEED, 64, steps, unit0=u)
@@ -121,6 +147,36 @@ def test_gamma_full_size(dev):
         cur = b.brng_get_cursors(ctx)
     finally:
         b.brng_destroy(ctx)
+    # the gate: every draw replayed from the shape the GPU formed for it
+    replay_flips = 0
+    for i, u in enumerate(units):
+        chains = perm[64 * u:64 * u + 64]
+        ident = np.arange(64, dtype=np.int32)
+        sl = slice(64 * i, 64 * i + 64)
+        qcur = None
+        for k, (g, a0) in enumerate(zip(runs, (w["alpha0"][chains], a_mid[chains]))):
+            shape = oracle.chain_shapes_fp32(a0, g[:, sl])
+            q = oracle.gamma_chain_replay(SEED, shape, w["steps"][chains], perm=ident,
+                                          cursors=qcur, unit0=u)
+            qcur = q["cursors"]
+            bad, flips = compare_rounds(g[:, sl], q["gtrace"], q["gtol"], q["gmargin"], q["gr0"],
+                                        q["gr1"], np.zeros(64, dtype=np.int64))
+            if bad:
+                ok = within(g[:, sl], q["gtrace"], q["gtol"]) | (q["gr1"] < 0)
+                rb = q["gr1"][~ok].min()
+                tt, c = np.argwhere(~ok & (q["gr1"] == rb))[0]
+                print("gamma replay mismatch unit", u, "run", k, "round", rb, "step", tt, "slot",
+                      c, "gpu", g[tt, sl][c], "ref", q["gtrace"][tt, c], "tol", q["gtol"][tt, c],
+                      "margin", q["gmargin"][tt, c], flush=True)
+            assert bad == 0, (u, k)
+            replay_flips += len(flips)
+            if flips:
+                break
+        else:
+            assert np.array_equal(cur[u], qcur[0]), u
+    print("gamma full-size replay flips", replay_flips, flush=True)
+    assert replay_flips <= 2
+    # free-running against the fp64 chains (shape bounds propagated)
     flips_total = 0
     for i, u in enumerate(units):
         chains = perm[64 * u:64 * u + 64]
@@ -149,6 +205,52 @@ def test_gamma_full_size(dev):
             assert np.array_equal(cur[u], r2["cursors"][0]), u
     print("gamma full-size flips", flips_total, flush=True)
     assert flips_total <= 2
+
+
+def test_expchain_full_size(dev):
+    """Exponential chains (the served exponential kind) at the served
+    stream's largest request: 65,536 chains x 10,000 steps, window 4,096,
+    a fresh launch then a resumed one, replayed on sampled units."""
+    import torch
+    b = _b()
+    n, steps, W = 65536, 10000, 4096
+    _say("expchain full size", n, steps, W)
+    ctx = b.brng_create(SEED, n, [0, 0, W, 0], stream=torch.cuda.current_stream())
+    st = torch.zeros(n, dtype=torch.float32, device=dev)
+    te = torch.zeros((steps, n), dtype=torch.float32, device=dev)
+    units = [0, 3, 600, 1023]
+    cols = [64 * u + c for u in units for c in range(64)]
+    try:
+        e_first = np.concatenate([b.brng_get_window(ctx, b.BRNG_E, u)[2][:64] for u in units])
+        b.brng_set_launch(ctx, 4)
+        kw = dict(max_steps=steps, seed=SEED, trace=te, trace_stride=n)
+        b.brng_run_gibbs(ctx, b.gibbs_desc(b.BRNG_MODEL_EXP_CHAIN, n, st, **kw))
+        runs = [_cols(te, cols)]
+        e_mid = st.cpu().numpy().copy()
+        b.brng_fill_base(ctx, b.BRNG_E)
+        b.brng_run_gibbs(ctx, b.gibbs_desc(b.BRNG_MODEL_EXP_CHAIN, n, st,
+                                           flags=b.BRNG_FLAG_RESUME, **kw))
+        runs.append(_cols(te, cols))
+        cur = b.brng_get_cursors(ctx)
+    finally:
+        b.brng_destroy(ctx)
+    for i, u in enumerate(units):
+        sl = slice(64 * i, 64 * i + 64)
+        starts = (e_first[sl], e_mid[64 * u:64 * u + 64])
+        qcur = None
+        for k, ge in enumerate(runs):
+            e_in = np.vstack([starts[k][None, :], ge[:-1, sl]])
+            q = oracle.expchain_replay(SEED, e_in, k == 0, cursors=qcur, unit0=u)
+            qcur = q["cursors"]
+            if k == 0:
+                assert within(starts[0], q["e0"], q["e0tol"]).all(), u
+            ok = within(ge[:, sl], q["etrace"], q["etol"])
+            if not ok.all():
+                t, c = np.argwhere(~ok)[0]
+                print("expchain replay mismatch unit", u, "run", k, "step", t, "chain", c, "gpu",
+                      ge[t, sl][c], "ref", q["etrace"][t, c], "tol", q["etol"][t, c], flush=True)
+            assert ok.all(), (u, k)
+        assert np.array_equal(cur[u], qcur[0]), u
 
 
 def test_lda_full_size(dev):

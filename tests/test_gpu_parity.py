@@ -308,6 +308,21 @@ def test_step_dirichlet_ragged(dev):
         b.brng_destroy(ctx)
 
 
+def _first_entries(ctx, kind, n):
+    """The first entries of every unit's window of `kind` as the library
+    holds them (fp32), read right after brng_create filled the windows from
+    cursor 0: the starting state a fresh chain run draws with its first
+    call (lane c of unit u takes entry c)."""
+    b = _b()
+    out = np.zeros(n, dtype=np.float32)
+    for u in range((n + 63) // 64):
+        base, ln, win = b.brng_get_window(ctx, kind, u)
+        assert base == 0 and ln >= 64
+        k = min(64, n - 64 * u)
+        out[64 * u:64 * u + k] = win[:k]
+    return out
+
+
 def _gibbs(ctx, model, n, state, max_steps, seed, dev, trace=None, trace2=None, stride=0, **kw):
     b = _b()
     d = b.gibbs_desc(model, n, state, max_steps=max_steps, seed=seed, trace=trace, trace2=trace2,
@@ -354,13 +369,24 @@ def test_normexp_chains(dev, window):
     ts = torch.zeros((steps, n), dtype=torch.float32, device=dev)
     te = torch.zeros((steps, n), dtype=torch.float32, device=dev)
     try:
+        s_first = _first_entries(ctx, b.BRNG_N, n)
         _gibbs(ctx, b.BRNG_MODEL_NORMEXP, n, st, steps, seed, dev, ts, te, n)
-        r = oracle.normexp(seed, n, steps)
         gs, ge = _np(ts), _np(te)
-        ok_s = within(gs, r["strace"], r["stol"])
-        ok_e = within(ge, r["etrace"], r["etol"])
+        gcur = b.brng_get_cursors(ctx)
+        # the gate: every step replayed from the state the GPU held before
+        # it, each output at the single-result bar
+        q = oracle.normexp_replay(seed, np.vstack([s_first[None, :], gs[:-1]]), gs, True)
+        assert within(s_first, q["s0"], q["s0tol"]).all()
+        ok_s = within(gs, q["strace"], q["stol"])
+        ok_e = within(ge, q["etrace"], q["etol"])
+        print("normexp replay: s bad", int((~ok_s).sum()), "e bad", int((~ok_e).sum()), flush=True)
         assert ok_s.all() and ok_e.all()
-        assert np.array_equal(b.brng_get_cursors(ctx), r["cursors"])
+        assert np.array_equal(gcur, q["cursors"])
+        # free-running against the fp64 chain (bound propagated along it)
+        r = oracle.normexp(seed, n, steps)
+        assert within(gs, r["strace"], r["stol"]).all()
+        assert within(ge, r["etrace"], r["etol"]).all()
+        assert np.array_equal(gcur, r["cursors"])
     finally:
         b.brng_destroy(ctx)
 
@@ -401,10 +427,19 @@ def test_expchain(dev, window):
     st = torch.zeros(n, dtype=torch.float32, device=dev)
     te = torch.zeros((steps, n), dtype=torch.float32, device=dev)
     try:
+        e_first = _first_entries(ctx, b.BRNG_E, n)
         _gibbs(ctx, b.BRNG_MODEL_EXP_CHAIN, n, st, steps, seed, dev, te, None, n)
+        ge = _np(te)
+        gcur = b.brng_get_cursors(ctx)
+        q = oracle.expchain_replay(seed, np.vstack([e_first[None, :], ge[:-1]]), True)
+        assert within(e_first, q["e0"], q["e0tol"]).all()
+        ok = within(ge, q["etrace"], q["etol"])
+        print("expchain replay: bad", int((~ok).sum()), flush=True)
+        assert ok.all()
+        assert np.array_equal(gcur, q["cursors"])
         r = oracle.expchain(seed, n, steps)
-        assert within(_np(te), r["etrace"], r["etol"]).all()
-        assert np.array_equal(b.brng_get_cursors(ctx), r["cursors"])
+        assert within(ge, r["etrace"], r["etol"]).all()
+        assert np.array_equal(gcur, r["cursors"])
     finally:
         b.brng_destroy(ctx)
 
@@ -432,15 +467,24 @@ def test_gamma_chains(dev):
     seed = 31
     _say("gamma_chain", w["n_chains"], seed)
     g, alpha, cur, perm = _run_gamma_chain(dev, w, seed, W_SMALL)
-    r = oracle.gamma_chain(seed, w["alpha0"], w["steps"], perm=perm)
     assert np.array_equal(perm, oracle.sort_by_length(w["steps"]))
     units = np.arange(w["n_chains"]) // 64
-    bad, flips = compare_rounds(g, r["gtrace"], r["gtol"], r["gmargin"], r["gr0"], r["gr1"], units)
-    print("gamma flips", len(flips), "bad", bad, flush=True)
+    # the gate: every draw replayed from the shape the GPU formed for it
+    # (0.1f + its previous draw), at the single-result bar
+    shape = oracle.chain_shapes_fp32(w["alpha0"][perm], g)
+    q = oracle.gamma_chain_replay(seed, shape, w["steps"], perm=perm)
+    bad, flips = compare_rounds(g, q["gtrace"], q["gtol"], q["gmargin"], q["gr0"], q["gr1"], units)
+    print("gamma replay flips", len(flips), "bad", bad, flush=True)
     assert bad == 0
     assert len(flips) <= 2
     keep = np.array([u not in flips for u in range(cur.shape[0])])
-    assert np.array_equal(cur[keep], r["cursors"][keep])
+    assert np.array_equal(cur[keep], q["cursors"][keep])
+    # free-running against the fp64 chain (shape bound propagated along it)
+    r = oracle.gamma_chain(seed, w["alpha0"], w["steps"], perm=perm)
+    bad, flips = compare_rounds(g, r["gtrace"], r["gtol"], r["gmargin"], r["gr0"], r["gr1"], units)
+    print("gamma free-run flips", len(flips), "bad", bad, flush=True)
+    assert bad == 0
+    assert len(flips) <= 2
 
 
 def test_lda(dev):

@@ -162,3 +162,101 @@ def test_gamma_chain_boost_branch_is_a_decision():
     # and the branch matters: the two sides draw very different values
     ga, gb = a["gtrace"][1, 0], b["gtrace"][1, 0]
     assert abs(ga - gb) > 1e-3 * max(abs(ga), abs(gb))
+
+
+# --------------------------------------------------------------------------
+# Per-step replay (the gate for the fp32 chain models): fed the free-running
+# oracle's own double-precision states, the replay must reproduce that run
+# exactly, value for value and cursor for cursor, so that the two share their
+# pins (the PIT tests above); fed other states (here: the same trajectories
+# rounded to fp32, as an fp32 run holds them), every replayed output must be
+# distributed as the chain's conditional law given its input state.
+# --------------------------------------------------------------------------
+
+def test_normexp_replay_reproduces_free_run():
+    n, steps, seed = 200, 40, 11
+    for s0 in (None, np.random.default_rng(4).normal(size=n) * 3.0):
+        r = oracle.normexp(seed, n, steps, s0=s0)
+        if s0 is None:
+            # the free run's starting state is its first Gaussian per chain
+            q = oracle.normexp_replay(seed, np.zeros((steps, n)), np.zeros((steps, n)), True)
+            start = q["s0"]
+        else:
+            start = np.asarray(s0, dtype=np.float64)
+        s_in = np.vstack([start[None, :], r["strace"][:-1]])
+        q = oracle.normexp_replay(seed, s_in, r["strace"], s0 is None)
+        assert np.array_equal(q["strace"], r["strace"])
+        assert np.array_equal(q["etrace"], r["etrace"])
+        assert np.array_equal(q["cursors"], r["cursors"])
+        # local bars never exceed the free run's propagated ones
+        assert np.all(q["stol"] <= r["stol"]) and np.all(q["etol"] <= r["etol"] * (1 + 1e-12))
+
+
+def test_normexp_replay_conditional_law():
+    n, steps, seed = 1024, 60, 12
+    r = oracle.normexp(seed, n, steps)
+    q0 = oracle.normexp_replay(seed, np.zeros((steps, n)), np.zeros((steps, n)), True)
+    s32 = r["strace"].astype(np.float32).astype(np.float64)
+    s_in = np.vstack([q0["s0"].astype(np.float32).astype(np.float64)[None, :], s32[:-1]])
+    q = oracle.normexp_replay(seed, s_in, s32, True)
+    pit_s = special.ndtr((q["strace"] - 0.9 * s_in) / (0.5 + np.abs(s_in)))
+    assert stats.kstest(pit_s.ravel(), "uniform").pvalue > 1e-3
+    pit_e = -np.expm1(-(1.0 + s32 * s32) * q["etrace"])
+    assert stats.kstest(pit_e.ravel(), "uniform").pvalue > 1e-3
+    # an off-by-one state (step t started from the state after step t)
+    # breaks the law
+    bad = oracle.normexp_replay(seed, s32, s32, True)
+    pit_b = special.ndtr((bad["strace"] - 0.9 * s_in) / (0.5 + np.abs(s_in)))
+    assert stats.kstest(pit_b.ravel(), "uniform").pvalue < 1e-6
+
+
+def test_expchain_replay_reproduces_free_run_and_law():
+    n, steps, seed = 300, 50, 13
+    r = oracle.expchain(seed, n, steps)
+    q0 = oracle.expchain_replay(seed, np.zeros((steps, n)), True)
+    e_in = np.vstack([q0["e0"][None, :], r["etrace"][:-1]])
+    q = oracle.expchain_replay(seed, e_in, True)
+    assert np.array_equal(q["etrace"], r["etrace"])
+    assert np.array_equal(q["cursors"], r["cursors"])
+    e32 = np.vstack([q0["e0"][None, :], r["etrace"][:-1]]).astype(np.float32).astype(np.float64)
+    q2 = oracle.expchain_replay(seed, e32, True)
+    pit = -np.expm1(-(1.0 + e32 * e32) * q2["etrace"])
+    assert stats.kstest(pit.ravel(), "uniform").pvalue > 1e-3
+
+
+def test_gamma_chain_replay_reproduces_free_run_and_law():
+    w = workloads.gamma_chain(n_chains=700, lmin=3, lmax=50, seed=14)
+    seed = 15
+    r = oracle.gamma_chain(seed, w["alpha0"], w["steps"])
+    perm = r["perm"]
+    G = r["gtrace"]
+    a0 = w["alpha0"][perm].astype(np.float64)
+    shape = np.vstack([a0[None, :], 0.1 + G[:-1]])
+    q = oracle.gamma_chain_replay(seed, shape, w["steps"], perm=perm)
+    live = ~np.isnan(G)
+    assert np.array_equal(np.isnan(q["gtrace"]), ~live)
+    assert np.array_equal(q["gtrace"][live], G[live])
+    assert np.array_equal(q["gr0"], r["gr0"]) and np.array_equal(q["gr1"], r["gr1"])
+    assert np.array_equal(q["cursors"], r["cursors"])
+    # exact shapes carry no bound: local bars only, no boost-branch margin
+    assert np.all(q["gtol"][live] <= r["gtol"][live] * (1 + 1e-12))
+    # shapes as an fp32 chain forms them (0.1f + g in fp32): every replayed
+    # draw is Gamma(shape, 1)
+    sh32 = oracle.chain_shapes_fp32(a0, G)
+    q2 = oracle.gamma_chain_replay(seed, sh32, w["steps"], perm=perm)
+    live2 = ~np.isnan(q2["gtrace"])
+    assert live2.sum() == w["steps"].sum()
+    pit = special.gammainc(sh32[live2], q2["gtrace"][live2])
+    assert stats.kstest(pit, "uniform").pvalue > 1e-3
+
+
+def test_chain_shapes_fp32_is_fp32_sum():
+    g = np.array([[0.5, 3.0e-9, 1.0e4], [2.0, 0.0, 7.25]], dtype=np.float32)
+    sh = oracle.chain_shapes_fp32(np.array([1.5, 0.2, 30.0], dtype=np.float32), g)
+    assert sh.shape == (2, 3)
+    assert np.array_equal(sh[0], np.array([1.5, 0.2, 30.0], dtype=np.float32).astype(np.float64))
+    for j in range(3):
+        want = float(np.float32(np.float32(0.1) + np.float32(g[0, j])))
+        assert sh[1, j] == want
+    # 0.1f + tiny rounds to 0.1f, not to the double 0.1
+    assert sh[1, 1] == float(np.float32(0.1)) and sh[1, 1] != 0.1
