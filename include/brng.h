@@ -53,7 +53,8 @@ enum {
     BRNG_E_HIP = 3,           /* HIP runtime error */
     BRNG_E_KIND_DISABLED = 4, /* call needs a pool whose window length is 0 */
     BRNG_E_BUSY = 5,          /* served form: no slot or memory available */
-    BRNG_E_UNSUPPORTED = 6    /* combination not provided (e.g. fp64 gamma) */
+    BRNG_E_UNSUPPORTED = 6,   /* combination not provided (e.g. fp64 gamma) */
+    BRNG_E_TOO_LARGE = 7      /* request exceeds the static scratch area */
 };
 
 /* Pool kinds (Sec. 2.1: reducible base distributions). */
@@ -286,6 +287,32 @@ typedef struct {
  * max_steps rows of trace_stride elements.
  * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_HIP. */
 brng_status brng_run_gibbs(brng_ctx *ctx, const brng_gibbs_desc *h_descs, uint32_t n_desc);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * request run as brng_run_gibbs runs it on a context with these windows,
+ * without a context.  Its unit records and pool windows live in a fixed
+ * device array of BRNG_STATIC_SCRATCH_MB MiB that the library holds on each
+ * GPU it runs on until the process ends; the call allocates nothing and
+ * launches only the model's chain kernel on `hip_stream` (a hipStream_t, or
+ * NULL for the default stream).  The request must start fresh (flags 0,
+ * unit_base 0): every run draws from cursor 0 of its own streams, keyed by
+ * (request-local unit, d->seed), so the results equal brng_run_gibbs on a
+ * fresh context with window4.  window4[kind] as in brng_config (the model's
+ * kinds must be enabled); wpb = waves per workgroup (1, 2, 4 or 8, halved
+ * while a workgroup's LDS would exceed 64 KiB).  The footprint is, per kind
+ * the model reads, n_units x window x entry size, plus 96 bytes per unit
+ * (each term rounded up to 256 bytes); a request beyond the array returns
+ * BRNG_E_TOO_LARGE.  Caller-owned device arrays as in brng_gibbs_desc.
+ * Every call on one GPU uses the same array: calls that overlap on that GPU
+ * (other streams, other threads) race and give undefined results; calls in
+ * one stream's order are safe.  The array keeps the last call's contents,
+ * which no later call reads.
+ * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_TOO_LARGE,
+ * BRNG_E_UNSUPPORTED (device index above 63), BRNG_E_HIP. */
+#define BRNG_STATIC_SCRATCH_MB 32
+brng_status brng_run_gibbs_static(const brng_gibbs_desc *h_desc, const uint32_t *h_window4,
+                                  int32_t wpb, void *hip_stream);
 
 /* A scheduling aid with no counterpart in the paper.  Slot order for uneven
  * chain lengths: perm[p] = chain in slot p, chains

@@ -16,7 +16,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbrng.so")
 
-BRNG_OK, BRNG_E_ARG, BRNG_E_NOMEM, BRNG_E_HIP, BRNG_E_KIND_DISABLED, BRNG_E_BUSY, BRNG_E_UNSUPPORTED = range(7)
+BRNG_OK, BRNG_E_ARG, BRNG_E_NOMEM, BRNG_E_HIP, BRNG_E_KIND_DISABLED, BRNG_E_BUSY, BRNG_E_UNSUPPORTED, BRNG_E_TOO_LARGE = range(8)
+STATIC_SCRATCH_MB = 32
 BRNG_U, BRNG_N, BRNG_E, BRNG_U64 = 0, 1, 2, 3
 BRNG_F32, BRNG_F64 = 0, 1
 BRNG_LAYOUT_CHAINS, BRNG_LAYOUT_ITEMS = 0, 1
@@ -31,7 +32,7 @@ EXPORTS = [
     "brng_create", "brng_destroy", "brng_fill_base", "brng_step_uniform", "brng_step_normal",
     "brng_step_exp", "brng_step_gamma", "brng_step_laplace", "brng_step_weibull", "brng_step_poisson",
     "brng_step_binomial", "brng_step_multinomial",
-    "brng_step_dirichlet", "brng_run_gibbs", "brng_run_lda_full",
+    "brng_step_dirichlet", "brng_run_gibbs", "brng_run_gibbs_static", "brng_run_lda_full",
     "brng_sort_by_length", "brng_get_cursors", "brng_set_cursors", "brng_get_window",
     "brng_get_info", "brng_set_launch", "brng_time_next_launch", "brng_status_string",
     "brng_last_hip_error",
@@ -166,6 +167,7 @@ def _load():
     L.brng_step_multinomial.argtypes = [vp, vp, vp, vp, vp]
     L.brng_step_dirichlet.argtypes = [vp, vp, vp, vp]
     L.brng_run_gibbs.argtypes = [vp, C.POINTER(brng_gibbs_desc), C.c_uint32]
+    L.brng_run_gibbs_static.argtypes = [C.POINTER(brng_gibbs_desc), vp, C.c_int32, vp]
     L.brng_run_lda_full.argtypes = [vp, C.POINTER(brng_lda_full_desc)]
     L.brng_sort_by_length.argtypes = [C.c_uint32, vp, vp]
     L.brng_get_cursors.argtypes = [vp, vp]
@@ -324,6 +326,12 @@ def brng_run_gibbs(ctx: int, descs) -> None:
         descs = [descs]
     arr = (brng_gibbs_desc * len(descs))(*descs)
     _check(_lib.brng_run_gibbs(ctx, arr, len(descs)), "brng_run_gibbs")
+
+
+def brng_run_gibbs_static(desc: brng_gibbs_desc, window, wpb: int = 4, stream=None) -> None:
+    w = (C.c_uint32 * 4)(*[int(x) for x in window])
+    _check(_lib.brng_run_gibbs_static(C.byref(desc), w, wpb, _stream_handle(stream)),
+           "brng_run_gibbs_static")
 
 
 def brng_sort_by_length(steps) -> np.ndarray:

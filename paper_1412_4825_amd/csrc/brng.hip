@@ -906,6 +906,7 @@ const char* brng_status_string(brng_status s) {
         case BRNG_E_KIND_DISABLED: return "pool kind disabled (window length 0)";
         case BRNG_E_BUSY: return "no capacity available";
         case BRNG_E_UNSUPPORTED: return "unsupported combination";
+        case BRNG_E_TOO_LARGE: return "request exceeds the static scratch area";
         default: return "unknown status";
     }
 }
@@ -1166,14 +1167,14 @@ brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
     return BRNG_OK;
 }
 
-static brng_status check_desc(const brng_ctx* c, const brng_gibbs_desc& d) {
+// A request against units [0, n_units) and windows W.
+static brng_status check_desc_w(uint64_t n_units, const uint32_t* W, const brng_gibbs_desc& d) {
     if (d.model < 0 || d.model >= BRNG_NMODELS) return BRNG_E_ARG;
     if (d.n_chains == 0 || d.max_steps < 0 || !d.d_state) return BRNG_E_ARG;
     const uint64_t nu = desc_unit_count(d);
-    if ((uint64_t)d.unit_base + nu > c->n_units) return BRNG_E_ARG;
+    if ((uint64_t)d.unit_base + nu > n_units) return BRNG_E_ARG;
     const int64_t width = d.model == BRNG_MODEL_LDA ? 0 : (int64_t)d.n_chains;
     if ((d.d_trace || d.d_trace2) && d.trace_stride < width) return BRNG_E_ARG;
-    const uint32_t* W = c->cfg.window;
     switch (d.model) {
         case BRNG_MODEL_TRIANGLE_F64:
             if (!W[BRNG_U64]) return BRNG_E_KIND_DISABLED;
@@ -1193,31 +1194,34 @@ static brng_status check_desc(const brng_ctx* c, const brng_gibbs_desc& d) {
     return BRNG_OK;
 }
 
+static brng_status check_desc(const brng_ctx* c, const brng_gibbs_desc& d) {
+    return check_desc_w(c->n_units, c->cfg.window, d);
+}
 
-// Waves per block for a model: the configured count, halved while a block's
+
+// Waves per block for a model: the requested count, halved while a block's
 // LDS would exceed 64 KiB.
-static int model_wpb(const brng_ctx* c, int model) {
-    int w = c->wpb;
+static int model_wpb(int wpb, int model) {
+    int w = wpb;
     while (w > 1 && (size_t)w * model_lds_bytes(model) > 65536) w >>= 1;
     return w;
 }
 
-static brng_status launch_plain(brng_ctx* c, const DescDev& D) {
-    const int wpb = model_wpb(c, D.model);
+// One request's chain kernel over unit records `meta` and pools P; with an
+// event pair (ts, te) the launch records them at the kernel's own start and
+// end.
+static brng_status launch_gibbs(hipStream_t stream, int wpb_req, const DescDev& D, Meta* meta,
+                                const Pools& P, hipEvent_t ts, hipEvent_t te) {
+    const int wpb = model_wpb(wpb_req, D.model);
     const dim3 grid((D.n_units + wpb - 1) / wpb), block(64 * wpb);
     const size_t lds = (size_t)wpb * model_lds_bytes(D.model);
-    const Pools P = make_pools(c);
-    // with a pending event pair the launch records them at the kernel's own
-    // start and end (then forgets them)
-    hipEvent_t ts = c->t_start, te = c->t_stop;
-    c->t_start = c->t_stop = nullptr;
 #define BRNG_LAUNCH_GIBBS(MODEL)                                                               \
     do {                                                                                      \
         if (ts)                                                                               \
-            hipExtLaunchKernelGGL(k_gibbs<MODEL>, grid, block, (uint32_t)lds, c->stream, ts,  \
-                                  te, 0u, D, c->meta, P);                                     \
+            hipExtLaunchKernelGGL(k_gibbs<MODEL>, grid, block, (uint32_t)lds, stream, ts, te, \
+                                  0u, D, meta, P);                                            \
         else                                                                                  \
-            hipLaunchKernelGGL(k_gibbs<MODEL>, grid, block, lds, c->stream, D, c->meta, P);   \
+            hipLaunchKernelGGL(k_gibbs<MODEL>, grid, block, lds, stream, D, meta, P);         \
     } while (0)
     switch (D.model) {
         case M_TRIANGLE: BRNG_LAUNCH_GIBBS(M_TRIANGLE); break;
@@ -1229,6 +1233,13 @@ static brng_status launch_plain(brng_ctx* c, const DescDev& D) {
 #undef BRNG_LAUNCH_GIBBS
     HIPCHK(hipGetLastError());
     return BRNG_OK;
+}
+
+static brng_status launch_plain(brng_ctx* c, const DescDev& D) {
+    // a pending event pair is used by this launch, then forgotten
+    hipEvent_t ts = c->t_start, te = c->t_stop;
+    c->t_start = c->t_stop = nullptr;
+    return launch_gibbs(c->stream, c->wpb, D, c->meta, make_pools(c), ts, te);
 }
 
 
@@ -1278,6 +1289,85 @@ brng_status brng_run_gibbs(brng_ctx* c, const brng_gibbs_desc* descs, uint32_t n
     if (n_desc == 1) return launch_plain(c, desc_to_device(descs[0]));
     // several requests (independent: their units are disjoint) share launches
     return launch_batched(c, descs, n_desc);
+}
+
+// ---------------------------------------------------------------------------
+// Chain runs without allocation: the unit records and pool windows of the
+// request live in one file-scope device array of fixed size, which each GPU
+// holds until the process ends.  Host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device (the array's
+// name is a host-side stand-in, not a device address).
+// ---------------------------------------------------------------------------
+constexpr uint64_t STATIC_SCRATCH_BYTES = (uint64_t)BRNG_STATIC_SCRATCH_MB << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[SCRATCH_MAX_DEVICES];
+
+// Address of this device's scratch array, looked up once per device with
+// that device current.
+static brng_status scratch_address(void** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return BRNG_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return BRNG_E_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BRNG_OK;
+}
+
+static uint64_t scratch_round(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
+
+brng_status brng_run_gibbs_static(const brng_gibbs_desc* d, const uint32_t* window4, int32_t wpb,
+                                  void* stream) {
+    if (!d || !window4) return BRNG_E_ARG;
+    if (!(wpb == 1 || wpb == 2 || wpb == 4 || wpb == 8)) return BRNG_E_ARG;
+    for (int k = 0; k < 4; ++k)
+        if (!window_ok(window4[k])) return BRNG_E_ARG;
+    // a fresh request on request-local units 0..n_units-1
+    if (d->unit_base != 0 || (d->flags & BRNG_FLAG_RESUME) || d->flags != 0) return BRNG_E_ARG;
+    const uint64_t nu = desc_unit_count(*d);
+    brng_status st = check_desc_w(nu, window4, *d);
+    if (st != BRNG_OK) return st;
+    // the kinds the model reads, each n_units windows; then the unit records
+    bool need[4] = {false, false, false, false};
+    switch (d->model) {
+        case BRNG_MODEL_TRIANGLE_F64: need[BRNG_U64] = true; break;
+        case BRNG_MODEL_NORMEXP:
+        case BRNG_MODEL_GAMMA_CHAIN: need[BRNG_N] = need[BRNG_E] = true; break;
+        case BRNG_MODEL_EXP_CHAIN: need[BRNG_E] = true; break;
+        default: need[BRNG_U] = need[BRNG_N] = need[BRNG_E] = true; break;
+    }
+    uint64_t off[4] = {0, 0, 0, 0}, total = 0;
+    for (int k = 0; k < 4; ++k) {
+        if (!need[k]) continue;
+        off[k] = total;
+        total += scratch_round(nu * window4[k] * kind_elem(k));
+    }
+    const uint64_t meta_off = total;
+    total += scratch_round(nu * sizeof(Meta));
+    if (total > STATIC_SCRATCH_BYTES) return BRNG_E_TOO_LARGE;
+    void* base = nullptr;
+    st = scratch_address(&base);
+    if (st != BRNG_OK) return st;
+    char* b = static_cast<char*>(base);
+    Pools P;
+    P.u = need[BRNG_U] ? reinterpret_cast<float*>(b + off[BRNG_U]) : nullptr;
+    P.n = need[BRNG_N] ? reinterpret_cast<float*>(b + off[BRNG_N]) : nullptr;
+    P.e = need[BRNG_E] ? reinterpret_cast<float*>(b + off[BRNG_E]) : nullptr;
+    P.u64 = need[BRNG_U64] ? reinterpret_cast<double*>(b + off[BRNG_U64]) : nullptr;
+    for (int k = 0; k < 4; ++k) P.W[k] = need[k] ? window4[k] : 0;
+    // a fresh request reads nothing of the array before writing it: its
+    // windows start empty (regenerated on first use) and its unit records
+    // are built in registers and written at the end
+    return launch_gibbs((hipStream_t)stream, wpb, desc_to_device(*d),
+                        reinterpret_cast<Meta*>(b + meta_off), P, nullptr, nullptr);
 }
 
 brng_status brng_sort_by_length(uint32_t n, const int32_t* steps, int32_t* perm) {

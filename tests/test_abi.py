@@ -101,3 +101,36 @@ def test_serve_arguments_checked_without_device():
     assert b._lib.brng_serve_close(None) == b.BRNG_OK
     t0 = b.brng_serve_now()
     assert b.brng_serve_now() >= t0 > 0
+
+
+def test_static_run_refusals_without_device():
+    """brng_run_gibbs_static refuses requests the fixed array cannot hold,
+    resumed requests, bad launch shapes and disabled kinds before any HIP
+    call (addresses below are never dereferenced)."""
+    fake = 1 << 20
+    big = b.gibbs_desc(b.BRNG_MODEL_NORMEXP, 64 * 4096, fake, max_steps=1, seed=1)
+    with pytest.raises(b.BrngError) as e:
+        b.brng_run_gibbs_static(big, [0, 4096, 4096, 0])
+    assert e.value.status == b.BRNG_E_TOO_LARGE
+    assert "static scratch" in str(e.value)
+    # just above the limit: 8 MiB of N and E windows per 256 units of 4,096
+    # entries, plus the unit records
+    mb = b.STATIC_SCRATCH_MB
+    units = (mb << 20) // (2 * 4096 * 4)
+    edge = b.gibbs_desc(b.BRNG_MODEL_NORMEXP, 64 * units, fake, max_steps=1, seed=1)
+    with pytest.raises(b.BrngError) as e:
+        b.brng_run_gibbs_static(edge, [0, 4096, 4096, 0])
+    assert e.value.status == b.BRNG_E_TOO_LARGE
+    ok = b.gibbs_desc(b.BRNG_MODEL_NORMEXP, 64, fake, max_steps=1, seed=1)
+    for desc, window, wpb, status in (
+            (b.gibbs_desc(b.BRNG_MODEL_NORMEXP, 64, fake, max_steps=1, seed=1,
+                          flags=b.BRNG_FLAG_RESUME), [0, 4096, 4096, 0], 4, b.BRNG_E_ARG),
+            (b.gibbs_desc(b.BRNG_MODEL_NORMEXP, 64, fake, max_steps=1, seed=1, unit_base=1),
+             [0, 4096, 4096, 0], 4, b.BRNG_E_ARG),
+            (ok, [0, 4096, 4096, 0], 3, b.BRNG_E_ARG),
+            (ok, [0, 4000, 4096, 0], 4, b.BRNG_E_ARG),
+            (ok, [0, 0, 4096, 0], 4, b.BRNG_E_KIND_DISABLED)):
+        with pytest.raises(b.BrngError) as e:
+            b.brng_run_gibbs_static(desc, window, wpb=wpb)
+        assert e.value.status == status
+    assert b._lib.brng_run_gibbs_static(None, None, 4, None) == b.BRNG_E_ARG
