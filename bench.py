@@ -1,30 +1,38 @@
 #!/usr/bin/env python3
 """Benchmark of the varying-parameter pool RNG on one MI355X.
 
-Default workload (normal/exponential chains): 65,536 chains x 1,000 steps,
-s' ~ N(0.9 s, 0.5 + |s|) then e ~ Exp(1 + s'^2), fp32, Philox4x32-10 pools
-with a window of 4,096 entries per unit (64 chains) per kind, refilled on
-exhaustion.  One timed step is the whole hot path over that batch: bulk
-refill of the pool windows (one 128-bit store per Philox block) followed by
-one launch that runs every chain for all its steps from the pools
-(regenerating each window in place when it runs out), writing every output
-of every step.  Chains continue from step to step.
+Headline workload (LDA-style Dirichlet resampling): 16,384 documents with
+K uniform on {8, 16, 64, 256} components and Poisson(200) tokens, 100 sweeps
+per step; each sweep draws theta ~ Dirichlet(0.1 + counts) from K gammas and
+then counts ~ Multinomial(n, theta) from the document's uniforms.  fp32
+deviates, int32 counts, Philox4x32-10 pools of an autotuned window per
+document per kind, regenerated in place when they run out.  One timed step
+is the whole hot path over that batch: bulk refill of the pool windows (one
+128-bit store per Philox block) followed by one launch that runs every
+document for all its sweeps, writing theta and the counts of every sweep.
+Documents continue from step to step.
 
-Other workloads (--workload): triangle (Eq. 1 / Fig. 1, 1,024 chains x 10,000
-iterations, fp64), gamma (262,144 chains of uneven length 50..1,000 with
-alpha_{t+1} = 0.1 + g_t), lda (16,384 documents, Dirichlet + multinomial,
-100 sweeps), lda_full (full LDA on a synthetic corpus: 16,384 documents, 64
-topics, 4,096 words, per sweep the topic-word and document-topic Dirichlets
-and one topic per token), served (the mixed request stream alone).
+After it, under "workloads": the varying-shape gamma chains (262,144 chains
+of uneven length 50..1,000 with alpha_{t+1} = 0.1 + g_t) and the
+normal/exponential chains (65,536 chains x 1,000 steps, s' ~ N(0.9 s,
+0.5 + |s|) then e ~ Exp(1 + s'^2)), measured the same way.  --workload runs
+one workload alone: triangle (Eq. 1 / Fig. 1, 1,024 chains x 10,000
+iterations, fp64), normexp, gamma, lda, lda_full (full LDA on a synthetic
+corpus: 16,384 documents, 64 topics, 4,096 words, per sweep the topic-word
+and document-topic Dirichlets and one topic per token), served (the mixed
+request stream alone).
 
 Prints one JSON line: deviates/s, the roofline of the dominant kernel
 (algorithmic bytes over its duration against 8 TB/s; the duration from HIP
 events that the launch itself records at the kernel's start and end, with
-the span of the call on the stream beside it), the CPU
-oracle timed on the host over the workload or a stated sample of it, and
-(unless --no-served) the served form against per-request plain launches on
-a mixed request stream: throughput with every request queued, and p50/p99
-latency under Poisson arrivals at 70% of the plain capacity.
+the span of the call on the stream beside it), the CPU oracle timed on the
+host over a stated sample (all worker processes, and one thread with its
+cycles per deviate at the host's nominal clock; CPU model, logical CPUs,
+sockets and clock recorded), and (unless --no-served) the served form
+against per-request plain launches on a mixed request stream at the full
+size ranges (chains log-U[1, 65,536], steps log-U[10, 10,000]): throughput
+with every request queued, and p50/p99 latency under Poisson arrivals at 70%
+of the plain capacity.
 """
 from __future__ import annotations
 
@@ -170,12 +178,19 @@ def setup_normexp(torch, b, args):
                 "sample": "whole workload (%d chains x %d steps, %.3g deviates) split by unit "
                           "over %d processes; %.1f s of CPU work" % (n, steps, dv, len(jobs), busy)}
 
+    def cpu1():
+        nu = min(units, 16)
+        busy = _cpu_normexp((args.seed, 0, min(n, 64 * nu), steps))
+        dv = 2 * min(n, 64 * nu) * steps
+        return {"value": dv / busy, "unit": "deviates/s", "threads": 1,
+                "sample": "the first %d units (%d chains x %d steps) in one thread" % (nu, min(n, 64 * nu), steps)}
+
     # `keep` holds the device arrays the descriptors point to for as long as
     # the descriptors are used
     return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_N, b.BRNG_E], keep=(st, ts, te),
                 entry_bytes={b.BRNG_N: 4, b.BRNG_E: 4}, windows={b.BRNG_N: W, b.BRNG_E: W},
                 deviates=2 * n * steps, out_bytes=2 * n * steps * 4, dtype="f32", cpu=cpu,
-                kernel="k_gibbs<NORMEXP>",
+                cpu1=cpu1, kernel="k_gibbs<NORMEXP>",
                 config={"workload": "normal/exponential chains: s'~N(0.9s,0.5+|s|), e~Exp(1+s'^2)",
                         "chains": n, "steps": steps, "window_per_unit_per_kind": W,
                         "unit_chains": 64, "precision": "fp32", "generator": "Philox4x32-10"})
@@ -202,9 +217,16 @@ def setup_triangle(torch, b, args):
                 "sample": "whole workload (%d chains x %d iterations) split by unit over %d "
                           "processes; %.1f s of CPU work" % (n, iters, len(jobs), busy)}
 
+    def cpu1():
+        nu = min(units, 4)
+        m = min(n, 64 * nu)
+        busy = _cpu_triangle((args.seed, 0, m, iters))
+        return {"value": 2 * m * iters / busy, "unit": "deviates/s", "threads": 1,
+                "sample": "the first %d units (%d chains x %d iterations) in one thread" % (nu, m, iters)}
+
     return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_U64], keep=(st, tx, ty),
                 entry_bytes={b.BRNG_U64: 8}, windows={b.BRNG_U64: W},
-                deviates=2 * n * iters, out_bytes=2 * n * iters * 8, dtype="f64", cpu=cpu,
+                deviates=2 * n * iters, out_bytes=2 * n * iters * 8, dtype="f64", cpu=cpu, cpu1=cpu1,
                 kernel="k_gibbs<TRIANGLE>",
                 config={"workload": "triangle Gibbs sampler of Eq. 1 / Fig. 1: x~U(0,1-y), y~U(0,1-x)",
                         "chains": n, "iterations": iters, "window_per_unit": W,
@@ -243,6 +265,14 @@ def setup_gamma(torch, b, args):
                 "sample": "%d of %d units (the longest chains first, %.3g gamma draws) over %d "
                           "processes; %.1f s of CPU work" % (su, units, dv, len(jobs), busy)}
 
+    def cpu1():
+        nu = min(units, 16)
+        sl = perm[:min(n, 64 * nu)]
+        busy = _cpu_gamma((args.seed, 0, wl["alpha0"][sl].astype(np.float64), wl["steps"][sl]))
+        dv = int(wl["steps"][sl].sum())
+        return {"value": dv / busy, "unit": "deviates/s", "threads": 1,
+                "sample": "the first %d units (the longest chains, %d gamma draws) in one thread" % (nu, dv)}
+
     def oaat(events):
         """The same shapes drawn with one launch per step (brng_step_gamma)."""
         c2 = b.brng_create(args.seed + 1, n, [0, W, W, 0], stream=torch.cuda.current_stream())
@@ -267,7 +297,7 @@ def setup_gamma(torch, b, args):
     return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_N, b.BRNG_E],
                 keep=(st, tg, tsteps, tperm),
                 entry_bytes={b.BRNG_N: 4, b.BRNG_E: 4}, windows={b.BRNG_N: W, b.BRNG_E: W},
-                deviates=draws, out_bytes=draws * 4, dtype="f32", cpu=cpu, oaat=oaat,
+                deviates=draws, out_bytes=draws * 4, dtype="f32", cpu=cpu, cpu1=cpu1, oaat=oaat,
                 kernel="k_gibbs<GAMMA_CHAIN>",
                 config={"workload": "varying-shape gamma chains: g~Gamma(alpha,1), alpha'=0.1+g, "
                                     "Marsaglia-Tsang with the alpha<1 boost",
@@ -312,11 +342,19 @@ def setup_lda(torch, b, args):
                 "sample": "%d of %d documents x %d sweeps (%.3g deviates) over %d processes; "
                           "%.1f s of CPU work" % (sd, nd, sweeps, sdv, len(jobs), busy)}
 
+    def cpu1():
+        sd = min(nd, 64)
+        off = wl["offsets"][:sd + 1].astype(np.int32)
+        busy = _cpu_lda((args.seed, 0, off, wl["ntok"][:sd], sweeps))
+        sdv = sweeps * (int(off[-1]) + int(wl["ntok"][:sd].sum()))
+        return {"value": sdv / busy, "unit": "deviates/s", "threads": 1,
+                "sample": "the first %d documents x %d sweeps (%.3g deviates) in one thread" % (sd, sweeps, sdv)}
+
     return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_U, b.BRNG_N, b.BRNG_E],
                 keep=(counts, th, ct, toff, tntok, tperm),
                 entry_bytes={b.BRNG_U: 4, b.BRNG_N: 4, b.BRNG_E: 4},
                 windows={b.BRNG_U: W, b.BRNG_N: W, b.BRNG_E: W},
-                deviates=dv, out_bytes=sweeps * total * 8, dtype="f32", cpu=cpu,
+                deviates=dv, out_bytes=sweeps * total * 8, dtype="f32", cpu=cpu, cpu1=cpu1,
                 kernel="k_gibbs<LDA>",
                 config={"workload": "LDA-style Dirichlet resampling: theta~Dir(0.1+counts), "
                                     "counts~Mult(n_d, theta)",
@@ -394,11 +432,22 @@ def setup_lda_full(torch, b, args):
                           "and its documents; %.1f s of CPU work"
                           % (sd, nd, K, V, n, sdv, len(jobs), busy)}
 
+    def cpu1():
+        sd = min(nd, 256)
+        off = c["offsets"][:sd + 1].astype(np.int32)
+        n = int(off[-1])
+        busy = _cpu_lda_full((args.seed, K, V, off, c["words"][:n], c["z0"][:n], alpha, beta,
+                              list(range(sd))))
+        sdv = K * V + sd * K + n
+        return {"value": sdv / busy, "unit": "deviates/s", "threads": 1,
+                "sample": "one sweep of the topics and the first %d documents (%.3g deviates) "
+                          "in one thread" % (sd, sdv)}
+
     return dict(ctx=ctx, run=run, kinds=[b.BRNG_U, b.BRNG_N, b.BRNG_E],
                 keep=(toff, tw, tz, ndk, nkw, th, phi),
                 entry_bytes={b.BRNG_U: 4, b.BRNG_N: 4, b.BRNG_E: 4},
                 windows={b.BRNG_U: W, b.BRNG_N: W, b.BRNG_E: W},
-                deviates=dv, out_bytes=out_b, dtype="f32", cpu=cpu,
+                deviates=dv, out_bytes=out_b, dtype="f32", cpu=cpu, cpu1=cpu1,
                 kernel="k_ldaf_docs", kernel_bytes=kernel_bytes,
                 config={"workload": "full LDA, uncollapsed Gibbs on a synthetic corpus: "
                                     "phi_k~Dir(beta+n_k.), theta_d~Dir(alpha+n_d.), "
@@ -546,7 +595,8 @@ def served_section(torch, args, n_req):
     dev = torch.device("cuda:0")
     qs = workloads.served_requests(n_req, chains_max=args.served_chains_max,
                                    steps_max=args.served_steps_max, seed=args.seed)
-    reqs = [serve.Request(torch, q, dev) for q in qs]
+    # every request returns its final state and per-chain sums of its outputs
+    reqs = [serve.Request(torch, q, dev, sums=True) for q in qs]
     W = [4096] * 4
     deviates = sum(r.deviates for r in reqs)
     for r in reqs:
@@ -568,7 +618,8 @@ def served_section(torch, args, n_req):
     arrivals = workloads.poisson_arrivals(n_req, rate, seed=args.seed)
     lat_plain = serve.fifo_latency(arrivals, service)
     kw = dict(budget=args.served_budget_mb << 20, window=W, max_active=args.served_slots,
-              tick_steps=args.served_tick_steps, tick_sweeps=args.served_tick_sweeps)
+              tick_steps=args.served_tick_steps, tick_sweeps=args.served_tick_sweeps,
+              max_bypass_ms=args.served_bypass_ms)
     kw["on_done"] = lambda d: say("served", d, "of", n_req) if d % 100 == 0 else None
     for r in reqs:
         r.reset()
@@ -594,7 +645,8 @@ def served_section(torch, args, n_req):
         "steps": "log-U[10, %d]" % args.served_steps_max,
         "server": dict(budget_mb=args.served_budget_mb, slots=args.served_slots,
                        tick_steps=args.served_tick_steps, tick_sweeps=args.served_tick_sweeps,
-                       window=W[0]),
+                       max_bypass_ms=args.served_bypass_ms, window=W[0]),
+        "outputs": "final state + per-chain sum and sum of squares of every output",
     }
 
 
@@ -630,61 +682,77 @@ WORKLOADS = {"normexp": setup_normexp, "triangle": setup_triangle, "gamma": setu
              "lda": setup_lda, "lda_full": setup_lda_full}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="normexp", choices=sorted(WORKLOADS) + ["served"])
-    ap.add_argument("--chains", type=int, default=0)
-    ap.add_argument("--chain-steps", type=int, default=0)
-    ap.add_argument("--window", type=int, default=0)
-    ap.add_argument("--seed", type=int, default=20141217)
-    ap.add_argument("--wpb", type=int, default=4)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-workers", type=int, default=0)
-    ap.add_argument("--cpu-units", type=int, default=0)
-    ap.add_argument("--oaat-steps", type=int, default=100)
-    ap.add_argument("--no-oaat", action="store_true",
-                    help="skip the one-launch-per-step comparison (gamma)")
-    ap.add_argument("--served-requests", type=int, default=2000)
-    ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--no-dist", action="store_true",
-                    help="skip the per-distribution rates (fill and one-at-a-time calls)")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="gamma/lda: use --window/--wpb as given instead of timing candidates")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one conversion of 2^26 words (256 MiB read, 256 MiB "
-                         "written): the known-size kernel that scales rocprof's "
-                         "FETCH_SIZE/WRITE_SIZE to bytes")
-    ap.add_argument("--served-chains-max", type=int, default=4096)
-    ap.add_argument("--served-steps-max", type=int, default=1000)
-    ap.add_argument("--served-budget-mb", type=int, default=4096)
-    ap.add_argument("--served-slots", type=int, default=64)
-    ap.add_argument("--served-tick-steps", type=int, default=256)
-    ap.add_argument("--served-tick-sweeps", type=int, default=4)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this library has no multi-GPU path "
-              "(each GPU would run its own independent units); use --gpus 1",
-              file=sys.stderr, flush=True)
-        sys.exit(2)
+def host_cpu_info():
+    """The host's CPU model, logical CPUs, sockets and nominal clock (GHz), as
+    the system reports them; fields it does not report are None."""
+    info = {"cpu_model": None, "nproc": os.cpu_count(), "sockets": None, "nominal_ghz": None,
+            "nominal_ghz_source": None}
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = {}
+        for line in txt.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        info["cpu_model"] = kv.get("Model name")
+        if kv.get("Socket(s)", "").isdigit():
+            info["sockets"] = int(kv["Socket(s)"])
+        if "CPU max MHz" in kv:
+            info["max_ghz"] = round(float(kv["CPU max MHz"]) / 1e3, 3)
+    except Exception:
+        pass
+    try:
+        info["nproc"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    # nominal (base) clock: the cpufreq driver's nominal or base frequency
+    # (kHz), else a frequency printed in the model name
+    for f in ("amd_pstate_nominal_freq", "base_frequency"):
+        path = "/sys/devices/system/cpu/cpu0/cpufreq/" + f
+        try:
+            with open(path) as fh:
+                info["nominal_ghz"] = round(int(fh.read().strip()) / 1e6, 3)
+                info["nominal_ghz_source"] = path
+                break
+        except Exception:
+            continue
+    if info["nominal_ghz"] is None and info["cpu_model"] and "GHz" in info["cpu_model"]:
+        import re
+        m = re.search(r"([0-9.]+)\s*GHz", info["cpu_model"])
+        if m:
+            info["nominal_ghz"] = float(m.group(1))
+            info["nominal_ghz_source"] = "model name"
+    if info["nominal_ghz"] is None and info.get("max_ghz"):
+        info["nominal_ghz"] = info["max_ghz"]
+        info["nominal_ghz_source"] = "lscpu CPU max MHz (no base clock exposed)"
+    if info["nominal_ghz"] is None:
+        # a virtual machine may expose no frequency but the clock the kernel
+        # measured at boot
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for line in fh:
+                    if line.startswith("cpu MHz"):
+                        info["nominal_ghz"] = round(float(line.split(":")[1]) / 1e3, 3)
+                        info["nominal_ghz_source"] = "/proc/cpuinfo cpu MHz (no base clock exposed)"
+                        break
+        except Exception:
+            pass
+    return info
 
-    import torch
 
-    from paper_1412_4825_amd import binding as b
-
-    if not torch.cuda.is_available():
-        print("no GPU visible", file=sys.stderr)
-        sys.exit(1)
-    if args.workload == "served":
-        served_main(torch, args)
-        return
+def measure(torch, b, args, workload):
+    """One workload: W untimed warmup steps, K timed steps (bulk refills + the
+    chain launch), the roofline of the chain kernel, and the CPU oracle legs.
+    Returns the fields of the bench line for it."""
+    import copy
+    args = copy.copy(args)
+    args.workload = workload
     tuned = None
-    if args.workload in ("gamma", "lda") and not args.no_autotune and not args.window:
+    if workload in ("gamma", "lda") and not args.no_autotune and not args.window:
         tuned = autotune_launch(torch, b, args)
         args.window, args.wpb = tuned["window"], tuned["wpb"]
-    Wk = WORKLOADS[args.workload](torch, b, args)
+    Wk = WORKLOADS[workload](torch, b, args)
     ctx = Wk["ctx"]
     b.brng_set_launch(ctx, args.wpb)
     ev = Events(torch)
@@ -753,23 +821,10 @@ def main():
             "kernel": Wk["kernel"],
             "kernel_ms": round(chain_ms, 4), "call_span_ms": round(span_ms, 4),
             "alg_bytes_per_launch": chain_b}
-    # context: what a plain copy reaches on this GPU
-    cgbs = copy_bandwidth(torch, b)
-    roof["copy_gbs"] = round(cgbs, 1)
-    roof["frac_of_copy"] = round(gbs / cgbs, 4)
     out = {
-        "metric": "varying-param deviates/s + % HBM roofline",
         "value": value,
-        "unit": "deviates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
         "dtype": Wk["dtype"],
-        "data": "synthetic",
         "config": Wk["config"],
         "roofline": roof,
         "step_alg_bytes": step_b,
@@ -785,8 +840,117 @@ def main():
         out["one_launch_per_step"] = Wk["oaat"](ev)
     if not args.no_cpu:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = Wk["cpu"](workers)
+        cb = Wk["cpu"](workers)
+        # one core: the same oracle in this process on a smaller sample, and
+        # its cycles per deviate at the host's nominal clock (the unit of the
+        # paper's results table)
+        one = Wk["cpu1"]()
+        ghz = args.host["nominal_ghz"]
+        if ghz:
+            one["cycles_per_deviate_at_nominal"] = round(ghz * 1e9 / one["value"], 1)
+        cb["one_core"] = one
+        cb.update({k: v for k, v in args.host.items()})
+        out["cpu_baseline"] = cb
     b.brng_destroy(ctx)
+    return out
+
+
+HEADLINE = "lda"
+EXTRA = ("gamma", "normexp")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="",
+                    choices=[""] + sorted(WORKLOADS) + ["served"],
+                    help="one workload alone; by default the LDA/Dirichlet workload is the "
+                         "headline and the gamma and normal/exponential chains follow under "
+                         "'workloads'")
+    ap.add_argument("--chains", type=int, default=0)
+    ap.add_argument("--chain-steps", type=int, default=0)
+    ap.add_argument("--window", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=20141217)
+    ap.add_argument("--wpb", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=0)
+    ap.add_argument("--cpu-units", type=int, default=0)
+    ap.add_argument("--oaat-steps", type=int, default=100)
+    ap.add_argument("--no-oaat", action="store_true",
+                    help="skip the one-launch-per-step comparison (gamma)")
+    ap.add_argument("--served-requests", type=int, default=1000)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default run: skip the gamma and normal/exponential workloads")
+    ap.add_argument("--no-dist", action="store_true",
+                    help="skip the per-distribution rates (fill and one-at-a-time calls)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="gamma/lda: use --window/--wpb as given instead of timing candidates")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one conversion of 2^26 words (256 MiB read, 256 MiB "
+                         "written): the known-size kernel that scales rocprof's "
+                         "FETCH_SIZE/WRITE_SIZE to bytes")
+    ap.add_argument("--served-chains-max", type=int, default=65536)
+    ap.add_argument("--served-steps-max", type=int, default=10000)
+    ap.add_argument("--served-budget-mb", type=int, default=16384)
+    ap.add_argument("--served-slots", type=int, default=64)
+    ap.add_argument("--served-tick-steps", type=int, default=256)
+    ap.add_argument("--served-tick-sweeps", type=int, default=4)
+    ap.add_argument("--served-bypass-ms", type=int, default=50,
+                    help="served form: later requests that fit may pass a waiting one for "
+                         "this long after its arrival")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this library has no multi-GPU path "
+              "(each GPU would run its own independent units); use --gpus 1",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1412_4825_amd import binding as b
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    if args.workload == "served":
+        served_main(torch, args)
+        return
+    args.host = host_cpu_info()
+    head = args.workload or HEADLINE
+    res = measure(torch, b, args, head)
+    print("[bench] %s: %.4g deviates/s, roofline %.3f" % (head, res["value"], res["roofline"]["frac"]),
+          file=sys.stderr, flush=True)
+    out = {
+        "metric": "varying-param deviates/s + % HBM roofline",
+        "value": res.pop("value"),
+        "unit": "deviates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res.pop("ms_per_step"),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": res.pop("dtype"),
+        "data": "synthetic",
+        "config": res.pop("config"),
+        "roofline": res.pop("roofline"),
+    }
+    out.update(res)
+    # context: what a plain copy reaches on this GPU
+    cgbs = copy_bandwidth(torch, b)
+    out["roofline"]["copy_gbs"] = round(cgbs, 1)
+    out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / cgbs, 4)
+    if not args.workload and not args.no_extra:
+        out["workloads"] = {}
+        for name in EXTRA:
+            r = measure(torch, b, args, name)
+            print("[bench] %s: %.4g deviates/s, roofline %.3f" % (name, r["value"], r["roofline"]["frac"]),
+                  file=sys.stderr, flush=True)
+            out["workloads"][name] = r
     if args.copy_calibration:
         nw = 1 << 26
         words = torch.randint(-2**31, 2**31 - 1, (nw,), dtype=torch.int32, device="cuda")

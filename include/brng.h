@@ -273,13 +273,31 @@ typedef struct {
                                total components) */
     const int32_t *d_offsets; /* LDA: n_docs + 1 component offsets */
     const int32_t *d_ntok;    /* LDA: tokens per document */
+    double *d_sums;           /* per-chain summaries, or NULL: for each output
+                                 its sum and its sum of squares over this
+                                 call's steps, ADDED to what the array holds
+                                 (zero it for a fresh total), user chain order:
+                                 TRIANGLE double[4][n] (x, x^2, y, y^2),
+                                 NORMEXP double[4][n] (s', s'^2, e, e^2),
+                                 GAMMA and EXP double[2][n] (g or e', square),
+                                 LDA double[2][total components] (theta,
+                                 theta^2).  Each step adds (double)v and
+                                 (double)v * (double)v in step order, so a run
+                                 split over several calls (or served in
+                                 slices) gives the same bits as one call */
 } brng_gibbs_desc;
+
+/* Requests one brng_run_gibbs call takes. */
+#define BRNG_BATCH_MAX 4096
 
 /* Run chains to completion on the context's stream: the one-at-a-time loop
  * of Sec. 1 (Eq. 1 / Fig. 1, the Dirichlet redraws of its footnote) for
- * many chains at once.  Each request is one
- * launch of its model's kernel (one wave per unit, every step of every chain
- * inside that launch); several requests run back to back on the stream.
+ * many chains at once.  One request is one launch of its model's kernel (one
+ * wave per unit, every step of every chain inside that launch).  Up to
+ * BRNG_BATCH_MAX requests, of any models, run as one launch over all their
+ * units (each wave runs its request's model), after small launches that copy
+ * the requests' descriptors into the context's device table; the sequence
+ * allocates nothing and can be captured in a graph.
  * Each request's units [unit_base, unit_base + n_units) must lie inside the
  * context and must not overlap another request's.  The needed kinds must be
  * enabled: TRIANGLE U64; NORMEXP N,E; GAMMA N,E; EXP E; LDA U,N,E.  LDA
@@ -381,7 +399,7 @@ brng_status brng_time_next_launch(brng_ctx *ctx, void *start_event, void *stop_e
 /* brng_gibbs_desc each) arrive at any time; the server admits them while  */
 /* device memory within its budget and a slot are free, keeps their unit   */
 /* tables and pools on the device, and advances every admitted request by  */
-/* a time slice per tick, the requests of one model sharing a launch.  A   */
+/* a time slice per tick, all admitted requests sharing one launch.  A     */
 /* request's results do not depend on what else runs (its streams are its */
 /* own: units keyed by (request-local unit id, request seed), Sec. 2.2's   */
 /* buffers kept per request), so they equal a plain brng_run_gibbs of the  */
@@ -400,7 +418,10 @@ typedef struct {
     uint32_t window[4];   /* pool window per unit per kind for every request
                              (as brng_config.window; kinds a model needs must
                              be non-zero) */
-    uint32_t pad;
+    uint32_t max_bypass_ms; /* while the oldest waiting request does not fit,
+                               later ones that fit are admitted past it until
+                               it has waited this long since its arrival
+                               (0: strictly in submission order) */
     void *hip_stream;     /* hipStream_t for all server work, NULL = default */
 } brng_serve_config;
 
@@ -437,8 +458,10 @@ uint64_t brng_serve_now(void);
  * arrays (state, steps, perm, traces, offsets, ntok) are the caller's and
  * must stay valid until the request is done; the state is updated in place.
  * t_arrive_ns is its arrival time (0: now).  Requests are admitted in
- * submission order.  Footprint = unit tables + pools of the kinds the model
- * uses.  Errors: BRNG_E_ARG (invalid request), BRNG_E_KIND_DISABLED (the
+ * submission order, but a request that does not fit may be passed by later
+ * ones for up to max_bypass_ms after its arrival (brng_serve_config).
+ * Footprint = unit tables + pools of the kinds the model uses (plus one
+ * int32 per chain slot for GAMMA).  Errors: BRNG_E_ARG (invalid request), BRNG_E_KIND_DISABLED (the
  * server's windows lack a kind the model needs), BRNG_E_NOMEM (footprint
  * above the whole budget: it could never be admitted). */
 brng_status brng_serve_submit(brng_server *srv, const brng_gibbs_desc *h_desc,

@@ -25,6 +25,7 @@ BRNG_MODEL_TRIANGLE_F64, BRNG_MODEL_NORMEXP, BRNG_MODEL_GAMMA_CHAIN, BRNG_MODEL_
 BRNG_FLAG_RESUME = 1
 BRNG_LDAF_COUNTS_VALID = 1
 UNIT_WIDTH = 64
+BATCH_MAX = 4096
 WINDOW_ALIGN = 256
 WINDOW_MIN = 512
 
@@ -69,6 +70,7 @@ class brng_gibbs_desc(C.Structure):
         ("trace_stride", C.c_int64),
         ("d_offsets", C.c_void_p),
         ("d_ntok", C.c_void_p),
+        ("d_sums", C.c_void_p),
     ]
 
 
@@ -99,7 +101,7 @@ class brng_serve_config(C.Structure):
         ("tick_steps", C.c_uint32),
         ("tick_sweeps", C.c_uint32),
         ("window", C.c_uint32 * 4),
-        ("pad", C.c_uint32),
+        ("max_bypass_ms", C.c_uint32),
         ("hip_stream", C.c_void_p),
     ]
 
@@ -302,7 +304,8 @@ def brng_step_dirichlet(ctx, offsets, alpha, out) -> None:
 
 def gibbs_desc(model: int, n_chains: int, state, *, max_steps: int, seed: int,
                unit_base: int = 0, flags: int = 0, steps=None, perm=None, trace=None,
-               trace2=None, trace_stride: int = 0, offsets=None, ntok=None) -> brng_gibbs_desc:
+               trace2=None, trace_stride: int = 0, offsets=None, ntok=None,
+               sums=None) -> brng_gibbs_desc:
     d = brng_gibbs_desc()
     d.model = model
     d.n_chains = n_chains
@@ -318,6 +321,7 @@ def gibbs_desc(model: int, n_chains: int, state, *, max_steps: int, seed: int,
     d.trace_stride = trace_stride
     d.d_offsets = _ptr(offsets)
     d.d_ntok = _ptr(ntok)
+    d.d_sums = _ptr(sums)
     return d
 
 
@@ -425,9 +429,10 @@ def brng_status_string(status: int) -> str:
 # ---------------------------------------------------------------------------
 
 def brng_serve_open(hbm_budget: int, window, *, max_active: int = 64, tick_steps: int = 64,
-                    tick_sweeps: int = 2, stream=None) -> int:
+                    tick_sweeps: int = 2, max_bypass_ms: int = 0, stream=None) -> int:
     cfg = brng_serve_config()
     cfg.hbm_budget = hbm_budget
+    cfg.max_bypass_ms = max_bypass_ms
     cfg.max_active = max_active
     cfg.tick_steps = tick_steps
     cfg.tick_sweeps = tick_sweeps

@@ -729,30 +729,122 @@ __global__ __launch_bounds__(512) void k_gibbs(DescDev D, Meta* meta, Pools P) {
     run_unit<MODEL>(D, meta, P, local, lds_all + w * model_lds_bytes(MODEL));
 }
 
-// Batched and served form: the units of up to MULTI_MAX requests in one
-// launch; a wave finds its request by binary search over the slots' unit
-// prefix (wave-uniform, in the kernel-argument segment).
-template <int MODEL>
-__global__ __launch_bounds__(512) void k_multi(const SlotTable T) {
-    extern __shared__ __align__(16) unsigned char lds_all[];
-    const uint32_t w = wave_in_block();
-    const uint32_t g = blockIdx.x * (blockDim.x >> 6) + w;
-    if (g >= T.total_units) return;
-    uint32_t lo = 0, hi = T.n - 1;
+// Batched and served form: the units of several requests in one launch.  A
+// wave finds its request by binary search over the slots' unit prefix in the
+// device table (the index is wave-uniform, so the search and the slot's
+// fields are scalar loads).  MODEL is one model, or M_MIXED: the wave then
+// runs its request's model.  lds_wave: LDS bytes per wave.
+constexpr int M_MIXED = -1;
+
+__device__ __forceinline__ int slot_lookup(const SlotDev* __restrict__ tab, uint32_t n,
+                                           uint32_t g, uint32_t* first) {
+    uint32_t lo = 0, hi = n - 1;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (T.s[mid].unit_end > g)
+        if (tab[mid].unit_end > g)
             hi = mid;
         else
             lo = mid + 1;
     }
-    const uint32_t first = lo ? T.s[lo - 1].unit_end : 0u;
-    const DescDev D = T.s[lo].D;
-    const Pools P = T.s[lo].P;
-    Meta* meta = T.s[lo].meta;
-    uint32_t local = g - first;
+    *first = lo ? tab[lo - 1].unit_end : 0u;
+    return (int)lo;
+}
+
+template <int MODEL>
+__device__ __forceinline__ void run_slot_unit(const DescDev& D, Meta* meta, const Pools& P,
+                                              uint32_t local, unsigned char* lds) {
     if (MODEL == M_LDA && !(lda_doc_of(D, local, &local) && lda_doc_ok(D, local))) return;
-    run_unit<MODEL>(D, meta, P, local, lds_all + w * model_lds_bytes(MODEL));
+    run_unit<MODEL>(D, meta, P, local, lds);
+}
+
+// A slot read through the constant address space, field by field: the table
+// is read-only while a kernel runs (the copy launches before it wrote it), so
+// the reads are uniform scalar loads and the fields land in scalar registers,
+// as kernel arguments would.
+typedef const SlotDev __attribute__((address_space(4))) ConstSlot;
+static_assert(sizeof(DescDev) == 128 && sizeof(Pools) == 48,
+              "load_slot copies every field of the descriptor and the pools");
+
+__device__ __forceinline__ void load_slot(ConstSlot* p, DescDev& D, Pools& P, Meta*& meta) {
+    D.model = p->D.model;
+    D.n_chains = p->D.n_chains;
+    D.unit_base = p->D.unit_base;
+    D.flags = p->D.flags;
+    D.seed = p->D.seed;
+    D.max_steps = p->D.max_steps;
+    D.n_units = p->D.n_units;
+    D.steps = p->D.steps;
+    D.perm = p->D.perm;
+    D.state = p->D.state;
+    D.trace = p->D.trace;
+    D.trace2 = p->D.trace2;
+    D.stride = p->D.stride;
+    D.offsets = p->D.offsets;
+    D.ntok = p->D.ntok;
+    D.step0 = p->D.step0;
+    D.max_rounds = p->D.max_rounds;
+    D.progress = p->D.progress;
+    D.unit_done = p->D.unit_done;
+    D.sums = p->D.sums;
+    P.u = p->P.u;
+    P.n = p->P.n;
+    P.e = p->P.e;
+    P.u64 = p->P.u64;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) P.W[k] = p->P.W[k];
+    meta = p->meta;
+}
+
+template <int MODEL>
+__device__ __forceinline__ void multi_body(const SlotDev* __restrict__ tab, uint32_t n,
+                                           uint32_t total_units, uint32_t lds_wave) {
+    extern __shared__ __align__(16) unsigned char lds_all[];
+    const uint32_t w = wave_in_block();
+    const uint32_t g = blockIdx.x * (blockDim.x >> 6) + w;
+    if (g >= total_units) return;
+    uint32_t first;
+    const int i = slot_lookup(tab, n, g, &first);
+    DescDev D;
+    Pools P;
+    Meta* meta;
+    load_slot((ConstSlot*)(tab + i), D, P, meta);
+    const uint32_t local = g - first;
+    unsigned char* lds = lds_all + w * lds_wave;
+    if constexpr (MODEL == M_MIXED) {
+        switch (D.model) {
+            case M_TRIANGLE: run_slot_unit<M_TRIANGLE>(D, meta, P, local, lds); break;
+            case M_NORMEXP: run_slot_unit<M_NORMEXP>(D, meta, P, local, lds); break;
+            case M_GAMMA: run_slot_unit<M_GAMMA>(D, meta, P, local, lds); break;
+            case M_LDA: run_slot_unit<M_LDA>(D, meta, P, local, lds); break;
+            case M_EXPCHAIN: run_slot_unit<M_EXPCHAIN>(D, meta, P, local, lds); break;
+            default: break;
+        }
+    } else {
+        run_slot_unit<MODEL>(D, meta, P, local, lds);
+    }
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(512) void k_multi(const SlotDev* __restrict__ tab, uint32_t n,
+                                               uint32_t total_units, uint32_t lds_wave) {
+    multi_body<MODEL>(tab, n, total_units, lds_wave);
+}
+
+// The mixed kernel holds every model's code, so its register count is that
+// of the largest (the normal/exponential pipeline); it is capped so that
+// three waves fit per SIMD, as the gamma and LDA kernels' LDS allows.
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3)))
+void k_mixed(const SlotDev* __restrict__ tab, uint32_t n, uint32_t total_units,
+             uint32_t lds_wave) {
+    multi_body<M_MIXED>(tab, n, total_units, lds_wave);
+}
+
+// Copy one chunk of slots into the device table (32-bit words).
+__global__ __launch_bounds__(256) void k_put_slots(SlotDev* tab, const SlotChunk c) {
+    const uint32_t words = c.n * (uint32_t)(sizeof(SlotDev) / 4);
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(c.s);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(tab + c.base);
+    for (uint32_t k = threadIdx.x; k < words; k += blockDim.x) dst[k] = src[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -765,6 +857,7 @@ struct brng_ctx {
     uint32_t n_units;
     void* pool[4];
     Meta* meta;
+    SlotDev* table;  // slots of the batched form (BRNG_BATCH_MAX entries)
     int wpb;
     int n_cu;
     // events for the next plain chain launch (brng_time_next_launch)
@@ -832,6 +925,7 @@ static void free_ctx(brng_ctx* c) {
     for (int k = 0; k < 4; ++k)
         if (c->pool[k]) (void)hipFree(c->pool[k]);
     if (c->meta) (void)hipFree(c->meta);
+    if (c->table) (void)hipFree(c->table);
     delete c;
 }
 
@@ -864,29 +958,53 @@ DescDev desc_to_device(const brng_gibbs_desc& d) {
     D.max_rounds = 0;
     D.progress = nullptr;
     D.unit_done = nullptr;
+    D.sums = d.d_sums;
     return D;
 }
 
-brng_status launch_slots(int model, const SlotTable& T, hipStream_t stream, int wpb) {
-    if (T.n == 0 || T.total_units == 0) return BRNG_OK;
-    while (wpb > 1 && (size_t)wpb * model_lds_bytes(model) > 65536) wpb >>= 1;
-    const dim3 grid((T.total_units + wpb - 1) / wpb), block(64 * wpb);
-    const size_t lds = (size_t)wpb * model_lds_bytes(model);
+brng_status launch_slots(SlotDev* slots, uint32_t n, SlotDev* tab, hipStream_t stream, int wpb) {
+    if (n == 0) return BRNG_OK;
+    uint32_t total = 0;
+    int model = slots[0].D.model;
+    int lds_wave = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        total += slots[i].D.n_units;
+        slots[i].unit_end = total;
+        slots[i].pad = 0;
+        if (slots[i].D.model != model) model = M_MIXED;
+        lds_wave = std::max(lds_wave, model_lds_bytes(slots[i].D.model));
+    }
+    if (total == 0) return BRNG_OK;
+    for (uint32_t b = 0; b < n; b += PUT_CHUNK) {
+        SlotChunk c;
+        std::memset(&c, 0, sizeof(c));
+        c.base = b;
+        c.n = std::min<uint32_t>(PUT_CHUNK, n - b);
+        std::memcpy(c.s, slots + b, sizeof(SlotDev) * c.n);
+        hipLaunchKernelGGL(k_put_slots, dim3(1), dim3(256), 0, stream, tab, c);
+    }
+    while (wpb > 1 && (size_t)wpb * lds_wave > 65536) wpb >>= 1;
+    const dim3 grid((total + wpb - 1) / wpb), block(64 * wpb);
+    const size_t lds = (size_t)wpb * lds_wave;
+    const uint32_t lw = (uint32_t)lds_wave;
     switch (model) {
         case M_TRIANGLE:
-            hipLaunchKernelGGL(k_multi<M_TRIANGLE>, grid, block, lds, stream, T);
+            hipLaunchKernelGGL(k_multi<M_TRIANGLE>, grid, block, lds, stream, tab, n, total, lw);
             break;
         case M_NORMEXP:
-            hipLaunchKernelGGL(k_multi<M_NORMEXP>, grid, block, lds, stream, T);
+            hipLaunchKernelGGL(k_multi<M_NORMEXP>, grid, block, lds, stream, tab, n, total, lw);
             break;
         case M_GAMMA:
-            hipLaunchKernelGGL(k_multi<M_GAMMA>, grid, block, lds, stream, T);
+            hipLaunchKernelGGL(k_multi<M_GAMMA>, grid, block, lds, stream, tab, n, total, lw);
             break;
         case M_LDA:
-            hipLaunchKernelGGL(k_multi<M_LDA>, grid, block, lds, stream, T);
+            hipLaunchKernelGGL(k_multi<M_LDA>, grid, block, lds, stream, tab, n, total, lw);
+            break;
+        case M_EXPCHAIN:
+            hipLaunchKernelGGL(k_multi<M_EXPCHAIN>, grid, block, lds, stream, tab, n, total, lw);
             break;
         default:
-            hipLaunchKernelGGL(k_multi<M_EXPCHAIN>, grid, block, lds, stream, T);
+            hipLaunchKernelGGL(k_mixed, grid, block, lds, stream, tab, n, total, lw);
             break;
     }
     HIPCHK(hipGetLastError());
@@ -942,7 +1060,8 @@ brng_status brng_create(const brng_config* cfg, brng_ctx** out) {
             return BRNG_E_NOMEM;
         }
     }
-    if (hipMalloc((void**)&c->meta, sizeof(Meta) * (size_t)c->n_units) != hipSuccess) {
+    if (hipMalloc((void**)&c->meta, sizeof(Meta) * (size_t)c->n_units) != hipSuccess ||
+        hipMalloc((void**)&c->table, sizeof(SlotDev) * BRNG_BATCH_MAX) != hipSuccess) {
         free_ctx(c);
         return BRNG_E_NOMEM;
     }
@@ -1243,38 +1362,21 @@ static brng_status launch_plain(brng_ctx* c, const DescDev& D) {
 }
 
 
-// Batched form: requests grouped by model, MULTI_MAX per launch, in the
-// order given within each model.
+// Batched form: all requests in one launch, in the order given (the mixed
+// kernel when their models differ).
 static brng_status launch_batched(brng_ctx* c, const brng_gibbs_desc* descs, uint32_t n_desc) {
     const Pools P = make_pools(c);
-    for (int model = 0; model < BRNG_NMODELS; ++model) {
-        SlotTable T;
-        T.n = 0;
-        T.total_units = 0;
-        for (uint32_t i = 0; i <= n_desc; ++i) {
-            const bool flush = (i == n_desc) || T.n == (uint32_t)MULTI_MAX;
-            if (flush && T.n) {
-                brng_status s = launch_slots(model, T, c->stream, c->wpb);
-                if (s != BRNG_OK) return s;
-                T.n = 0;
-                T.total_units = 0;
-            }
-            if (i == n_desc) break;
-            if (descs[i].model != model) continue;
-            SlotDev& S = T.s[T.n++];
-            S.D = desc_to_device(descs[i]);
-            S.meta = c->meta;
-            S.P = P;
-            T.total_units += S.D.n_units;
-            S.unit_end = T.total_units;
-            S.pad = 0;
-        }
+    std::vector<SlotDev> S(n_desc);
+    for (uint32_t i = 0; i < n_desc; ++i) {
+        S[i].D = desc_to_device(descs[i]);
+        S[i].meta = c->meta;
+        S[i].P = P;
     }
-    return BRNG_OK;
+    return launch_slots(S.data(), n_desc, c->table, c->stream, c->wpb);
 }
 
 brng_status brng_run_gibbs(brng_ctx* c, const brng_gibbs_desc* descs, uint32_t n_desc) {
-    if (!c || !descs || n_desc == 0) return BRNG_E_ARG;
+    if (!c || !descs || n_desc == 0 || n_desc > BRNG_BATCH_MAX) return BRNG_E_ARG;
     for (uint32_t i = 0; i < n_desc; ++i) {
         brng_status s = check_desc(c, descs[i]);
         if (s != BRNG_OK) return s;

@@ -37,6 +37,12 @@ struct DescDev {
     int32_t max_rounds;
     int32_t* progress;
     uint8_t* unit_done;
+    // Per-chain (LDA: per-component) sums of each output and of its square
+    // over this launch's steps, added to what the array holds, or null:
+    // [output][2][chains or components], fp64, one add per output per step
+    // in step order (so a run sliced over several launches gives the same
+    // sums as one launch).
+    double* sums;
 };
 
 enum : int32_t { M_TRIANGLE = 0, M_NORMEXP = 1, M_GAMMA = 2, M_LDA = 3, M_EXPCHAIN = 4 };
@@ -82,6 +88,13 @@ __device__ __forceinline__ void store_key(Meta* mp, const Meta& m) {
     }
 }
 
+// q + x * x with the product rounded before the sum (never one fused
+// multiply-add), as the sums of squares are defined.
+__device__ __forceinline__ double add_square(double q, double x) {
+#pragma clang fp contract(off)
+    return q + x * x;
+}
+
 // ---------------------------------------------------------------------------
 // Triangle (Eq. 1, Fig. 1) in fp64: x <- (1 - y) u then y <- (1 - x) u',
 // u, u' from the U64 pool.  The products and differences are rounded one at
@@ -108,6 +121,14 @@ __device__ void unit_triangle(const DescDev& D, Meta* mp, const Pools& P, uint32
     }
     double* tx = reinterpret_cast<double*>(D.trace);
     double* ty = reinterpret_cast<double*>(D.trace2);
+    const size_t n = D.n_chains;
+    double sx = 0.0, sxx = 0.0, sy = 0.0, syy = 0.0;
+    if (D.sums && in) {
+        sx = D.sums[chain];
+        sxx = D.sums[n + chain];
+        sy = D.sums[2 * n + chain];
+        syy = D.sums[3 * n + chain];
+    }
     const int32_t smax = D.max_steps;
     for (int32_t t = 0; t < smax; ++t) {
         const bool act = in && t < L;
@@ -119,11 +140,23 @@ __device__ void unit_triangle(const DescDev& D, Meta* mp, const Pools& P, uint32
         if (act) {
             if (tx) tx[(size_t)t * D.stride + slot] = x;
             if (ty) ty[(size_t)t * D.stride + slot] = y;
+            if (D.sums) {
+                sx += x;
+                sxx = add_square(sxx, x);
+                sy += y;
+                syy = add_square(syy, y);
+            }
         }
     }
     if (in) {
         st[chain] = x;
         st[(size_t)D.n_chains + chain] = y;
+        if (D.sums) {
+            D.sums[chain] = sx;
+            D.sums[n + chain] = sxx;
+            D.sums[2 * n + chain] = sy;
+            D.sums[3 * n + chain] = syy;
+        }
     }
     ru.close(*mp);
     store_key(mp, m);
@@ -150,6 +183,25 @@ __device__ __forceinline__ void store4(float* ob, float* trace, int64_t stride, 
     *reinterpret_cast<float4*>(dst) = v;
 }
 
+// Running sum and sum of squares of one fp32 output in fp64: v and v * v are
+// exact in fp64, so each step rounds once per sum.
+struct Sum2 {
+    double s = 0.0, q = 0.0;
+    __device__ __forceinline__ void add(float v) {
+        const double d = (double)v;
+        s += d;
+        q = add_square(q, d);
+    }
+    __device__ __forceinline__ void load(const double* p, size_t n, size_t i) {
+        s = p[i];
+        q = p[n + i];
+    }
+    __device__ __forceinline__ void store(double* p, size_t n, size_t i) const {
+        p[i] = s;
+        p[n + i] = q;
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Normal/exponential chain: s' = 0.9 s + (0.5 + |s|) z, e = E / (1 + s'^2).
 // Fresh chains draw s_0 as their first Gaussian.
@@ -174,9 +226,16 @@ __device__ void unit_normexp(const DescDev& D, Meta* mp, const Pools& P, uint32_
     float* ts = reinterpret_cast<float*>(D.trace);
     float* te = reinterpret_cast<float*>(D.trace2);
     const int32_t smax = D.max_steps;
-    const bool full = smax > 0 && P.W[KIND_N] >= LanePipe<KIND_N>::MIN_WINDOW &&
+    // the pipelined path serves runs without sums; sums take the staged one
+    const bool full = smax > 0 && !D.sums && P.W[KIND_N] >= LanePipe<KIND_N>::MIN_WINDOW &&
                       P.W[KIND_E] >= LanePipe<KIND_E>::MIN_WINDOW &&
                       (wave_ballot(in && L >= smax) == ~0ull);
+    const size_t n = D.n_chains;
+    Sum2 ss, se;  // sums of s' and e (outputs 0 and 1)
+    if (D.sums && in) {
+        ss.load(D.sums, n, chain);
+        se.load(D.sums + 2 * n, n, chain);
+    }
     float s;
     if (full) {
         if (fresh) {  // s_0: one call on the Gaussian pool
@@ -285,14 +344,23 @@ __device__ void unit_normexp(const DescDev& D, Meta* mp, const Pools& P, uint32_
             const float sp = fmaf(0.5f + fabsf(s), z, 0.9f * s);
             const float e = re.take(act);
             if (act) {
+                const float ev = e / fmaf(sp, sp, 1.0f);
                 if (ts) ts[(size_t)t * D.stride + slot] = sp;
-                if (te) te[(size_t)t * D.stride + slot] = e / fmaf(sp, sp, 1.0f);
+                if (te) te[(size_t)t * D.stride + slot] = ev;
+                if (D.sums) {
+                    ss.add(sp);
+                    se.add(ev);
+                }
                 s = sp;
             }
         }
         if (in) st[chain] = s;
         rn.close(*mp);
         re.close(*mp);
+    }
+    if (D.sums && in) {
+        ss.store(D.sums, n, chain);
+        se.store(D.sums + 2 * n, n, chain);
     }
     store_key(mp, m);
 }
@@ -319,8 +387,11 @@ __device__ void unit_expchain(const DescDev& D, Meta* mp, const Pools& P, uint32
     float* st = reinterpret_cast<float*>(D.state);
     float* tr = reinterpret_cast<float*>(D.trace);
     const int32_t smax = D.max_steps;
-    const bool full = smax > 0 && P.W[KIND_E] >= LanePipe<KIND_E>::MIN_WINDOW &&
+    const bool full = smax > 0 && !D.sums && P.W[KIND_E] >= LanePipe<KIND_E>::MIN_WINDOW &&
                       (wave_ballot(in && L >= smax) == ~0ull);
+    const size_t n = D.n_chains;
+    Sum2 sv;  // sums of e'
+    if (D.sums && in) sv.load(D.sums, n, chain);
     float v;
     if (full) {
         if (fresh) {
@@ -406,11 +477,13 @@ __device__ void unit_expchain(const DescDev& D, Meta* mp, const Pools& P, uint32
             if (act) {
                 v = e / fmaf(v, v, 1.0f);
                 if (tr) tr[(size_t)t * D.stride + slot] = v;
+                if (D.sums) sv.add(v);
             }
         }
         if (in) st[chain] = v;
         re.close(*mp);
     }
+    if (D.sums && in) sv.store(D.sums, n, chain);
     store_key(mp, m);
 }
 
@@ -455,9 +528,19 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
     src.col = src.trace ? reinterpret_cast<float*>(D.trace) + slot : nullptr;
     src.stride = D.stride;
     src.ring = reinterpret_cast<float*>(lds + GammaRN::LDS_BYTES + GammaRE::LDS_BYTES) + lane;
+    src.sums = D.sums != nullptr;
+    src.s1 = src.s2 = 0.0;
+    if (src.sums && in) {
+        src.s1 = D.sums[chain];
+        src.s2 = D.sums[(size_t)D.n_chains + chain];
+    }
     const uint32_t smax = (uint32_t)min(D.max_steps, 1 << 24);
     gamma_rounds<true>(rn, re, src, D.max_rounds > 0 ? (uint32_t)D.max_rounds : 4096u + 64u * smax);
     if (in) st[chain] = src.alpha;
+    if (src.sums && in) {
+        D.sums[chain] = src.s1;
+        D.sums[(size_t)D.n_chains + chain] = src.s2;
+    }
     if (D.progress && in) D.progress[slot] = src.t;
     if (D.unit_done) {
         const bool all = wave_ballot(src.holding()) == 0;
@@ -490,7 +573,7 @@ constexpr int LDA_LDS_BYTES = LDA_RINGS_BYTES + AUX_BYTES;
 // exists.  K passes through an empty asm so the comparison is made where it
 // is used instead of being kept, one lane mask per block, across the sweep.
 __device__ __forceinline__ bool comp_in(int K, int b, uint32_t lane) {
-    int Kx = K;
+    int Kx = __builtin_amdgcn_readfirstlane(K);
     asm volatile("" : "+s"(Kx));
     return b * 64 + (int)lane < Kx;
 }
@@ -533,6 +616,18 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
         const int k = b * 64 + (int)lane;
         if (comp_in(K, b, lane)) cnt[k] = counts[k];
         else Cs[k] = 0x7fffffff;
+    }
+    // sums of theta and theta^2 per component: [2][total components]
+    const size_t tot = D.sums ? (size_t)D.offsets[D.n_units] : 0;
+    double* sp = D.sums ? D.sums + off + lane : nullptr;
+    double s1[4] = {0.0, 0.0, 0.0, 0.0}, s2[4] = {0.0, 0.0, 0.0, 0.0};
+    if (sp) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if (comp_in(K, b, lane)) {
+                s1[b] = sp[b * 64];
+                s2[b] = sp[tot + b * 64];
+            }
     }
     for (int32_t sw = 0; sw < D.max_steps; ++sw) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -588,6 +683,14 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
             const int k = b * 64 + (int)lane;
             if (b * 64 < K && comp_in(K, b, lane)) cnt[k] = 0;
         }
+        if (sp) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const double t = (double)th[b];
+                s1[b] += t;
+                s2[b] = add_square(s2[b], t);
+            }
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -641,7 +744,13 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int k = b * 64 + (int)lane;
-        if (b * 64 < K && comp_in(K, b, lane)) counts[k] = cnt[k];
+        if (b * 64 < K && comp_in(K, b, lane)) {
+            counts[k] = cnt[k];
+            if (sp) {
+                sp[b * 64] = s1[b];
+                sp[tot + b * 64] = s2[b];
+            }
+        }
     }
     rn.close(*mp);
     re.close(*mp);

@@ -33,7 +33,11 @@ struct Key {
 template <bool KEYS_AT_USE = false>
 __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                           uint32_t k0, uint32_t k1) {
-    if (KEYS_AT_USE) asm volatile("" : "+s"(k0), "+s"(k1));
+    if (KEYS_AT_USE) {
+        k0 = __builtin_amdgcn_readfirstlane(k0);
+        k1 = __builtin_amdgcn_readfirstlane(k1);
+        asm volatile("" : "+s"(k0), "+s"(k1));
+    }
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
@@ -56,7 +60,11 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
 template <bool KEYS_AT_USE = false>
 __device__ __forceinline__ void philox10x2(uint32_t (&a)[4], uint32_t (&b)[4], uint32_t k0,
                                            uint32_t k1) {
-    if (KEYS_AT_USE) asm volatile("" : "+s"(k0), "+s"(k1));
+    if (KEYS_AT_USE) {
+        k0 = __builtin_amdgcn_readfirstlane(k0);
+        k1 = __builtin_amdgcn_readfirstlane(k1);
+        asm volatile("" : "+s"(k0), "+s"(k1));
+    }
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa0 = (uint64_t)a[0] * 0xD2511F53u;

@@ -297,6 +297,8 @@ struct ChainSrc {
     int64_t stride;  // trace elements between steps
     float* ring;     // LDS, TRACE_ROWS x 64 values; this lane's column
     int32_t f;       // wave-uniform: rows below f have been stored
+    bool sums;       // wave-uniform: keep the sum and sum of squares
+    double s1, s2;   // of this lane's draws, in step order
     __device__ __forceinline__ float first() {
         t0 = t;
         f = wave_minmax<false>(t < L ? t : INT32_MAX);
@@ -316,6 +318,11 @@ struct ChainSrc {
         } else {
             if (!behind) ring[(t & (TRACE_ROWS - 1)) * 64] = gv;
             if (behind && done && trace) col[(int64_t)t * stride] = gv;
+        }
+        if (sums && done) {
+            const double d = (double)gv;
+            s1 += d;
+            s2 = fma(d, d, s2);  // d * d is exact: the same as a rounded product
         }
         alpha = done ? 0.1f + gv : alpha;
         t += done ? 1 : 0;

@@ -4,9 +4,9 @@
 // when they run out, and names an asynchronous refill service as future work
 // (Sec. 3).  Here every admitted request owns unit tables and pools carved
 // out of one device arena (admission by footprint), stays resident between
-// ticks, and advances by a time slice per tick; all admitted requests of a
-// model share one multi-request launch per tick (up to MULTI_MAX per
-// launch).  Requests are independent (their streams are keyed by their own
+// ticks, and advances by a time slice per tick; all admitted requests share
+// one multi-request launch per tick (each wave runs its request's model).
+// Requests are independent (their streams are keyed by their own
 // seed and request-local unit ids), and a time slice is a resume of the
 // same kernel, so a served request's results equal a plain run's.
 //
@@ -138,6 +138,7 @@ struct brng_server {
     hipStream_t stream;
     char* base;
     Arena arena;
+    SlotDev* table;   // slots of one tick (max_active entries)
     uint8_t* status;  // host-visible unit_done bytes of gamma requests
     Arena status_arena;
     uint64_t in_use, peak;
@@ -244,49 +245,71 @@ brng_status retire(brng_server* s) {
     return BRNG_OK;
 }
 
+// Place r in the arena (and its status bytes); false when it does not fit.
+bool place(brng_server* s, Req* r) {
+    uint64_t off, soff = 0;
+    if (!s->arena.alloc(r->bytes, &off)) return false;
+    if (round_sliced(r->d.model) && !s->status_arena.alloc(r->n_units, &soff)) {
+        s->arena.release(off, r->bytes);
+        return false;
+    }
+    r->off = off;
+    carve(s, r);
+    if (r->progress) {
+        r->status_off = soff;
+        r->unit_done = s->status + soff;
+        std::memset(r->unit_done, 0, r->n_units);
+        (void)hipMemsetAsync(r->progress, 0, (size_t)r->n_units * 64 * sizeof(int32_t),
+                             s->stream);
+    }
+    r->t_admit = now_ns();
+    s->in_use += r->bytes;
+    s->peak = std::max(s->peak, s->in_use);
+    s->active.push_back(r);
+    return true;
+}
+
+// Admission by footprint, in submission order, except that while the oldest
+// waiting request does not fit, later ones that fit are admitted past it
+// (looking at most SCAN_AHEAD requests ahead) until it has waited
+// max_bypass_ms since its arrival; after that nothing passes it, so memory
+// freed by finishing requests goes to it and it cannot starve.
+constexpr int SCAN_AHEAD = 64;
+
 void admit(brng_server* s) {
-    while (!s->waiting.empty() && s->active.size() < s->cfg.max_active) {
-        Req* r = s->waiting.front();
-        uint64_t off, soff = 0;
-        if (!s->arena.alloc(r->bytes, &off)) break;  // in order: the head waits for memory
-        if (round_sliced(r->d.model) && !s->status_arena.alloc(r->n_units, &soff)) {
-            s->arena.release(off, r->bytes);
-            break;
+    const uint64_t bypass_ns = (uint64_t)s->cfg.max_bypass_ms * 1000000ull;
+    const uint64_t now = now_ns();
+    int scanned = 0;
+    auto it = s->waiting.begin();
+    while (it != s->waiting.end() && s->active.size() < s->cfg.max_active &&
+           scanned < SCAN_AHEAD) {
+        Req* r = *it;
+        if (place(s, r)) {
+            it = s->waiting.erase(it);
+            continue;
         }
-        r->off = off;
-        carve(s, r);
-        if (r->progress) {
-            r->status_off = soff;
-            r->unit_done = s->status + soff;
-            std::memset(r->unit_done, 0, r->n_units);
-            (void)hipMemsetAsync(r->progress, 0, (size_t)r->n_units * 64 * sizeof(int32_t),
-                                 s->stream);
+        if (it == s->waiting.begin()) {
+            const bool aged = now >= r->t_arrive && now - r->t_arrive >= bypass_ns;
+            if (bypass_ns == 0 || aged) break;  // the head waits; nothing passes it
         }
-        r->t_admit = now_ns();
-        s->in_use += r->bytes;
-        s->peak = std::max(s->peak, s->in_use);
-        s->active.push_back(r);
-        s->waiting.pop_front();
+        ++it;
+        ++scanned;
     }
 }
 
-// One tick: every admitted request advances by its model's slice.
+// One tick: every admitted request advances by its model's slice, all in one
+// launch.
 brng_status launch_tick(brng_server* s) {
     Tick t;
     t.id = s->n_ticks + 1;
     brng_status st = get_event(s, &t.ev);
     if (st != BRNG_OK) return st;
-    SlotTable T[BRNG_NMODELS];
-    for (int m = 0; m < BRNG_NMODELS; ++m) T[m].n = T[m].total_units = 0;
+    std::vector<SlotDev> slots;
+    slots.reserve(s->active.size());
     std::vector<Req*> still;
     still.reserve(s->active.size());
     for (Req* r : s->active) {
         const int m = r->d.model;
-        if (T[m].n == (uint32_t)MULTI_MAX) {
-            st = launch_slots(m, T[m], s->stream, 4);
-            if (st != BRNG_OK) return st;
-            T[m].n = T[m].total_units = 0;
-        }
         DescDev D = desc_to_device(r->d);
         D.unit_base = 0;
         D.flags = r->last_tick ? FLAG_RESUME : 0u;
@@ -309,13 +332,12 @@ brng_status launch_tick(brng_server* s) {
             r->done += steps;
             last = r->done >= r->d.max_steps;
         }
-        SlotDev& S = T[m].s[T[m].n++];
+        SlotDev S;
+        std::memset(&S, 0, sizeof(S));
         S.D = D;
         S.meta = r->meta;
         S.P = r->P;
-        T[m].total_units += r->n_units;
-        S.unit_end = T[m].total_units;
-        S.pad = 0;
+        slots.push_back(S);
         r->last_tick = t.id;
         t.reqs.push_back(r);
         if (last)
@@ -323,11 +345,8 @@ brng_status launch_tick(brng_server* s) {
         else
             still.push_back(r);
     }
-    for (int m = 0; m < BRNG_NMODELS; ++m) {
-        if (!T[m].n) continue;
-        st = launch_slots(m, T[m], s->stream, 4);
-        if (st != BRNG_OK) return st;
-    }
+    st = launch_slots(slots.data(), (uint32_t)slots.size(), s->table, s->stream, 4);
+    if (st != BRNG_OK) return st;
     if (hipEventRecord(t.ev, s->stream) != hipSuccess) return BRNG_E_HIP;
     s->active.swap(still);
     s->ticks.push_back(std::move(t));
@@ -379,11 +398,19 @@ brng_status brng_serve_open(const brng_serve_config* cfg, brng_server** out) {
         return BRNG_E_NOMEM;
     }
     s->arena.init(bytes);
+    s->table = nullptr;
+    if (hipMalloc((void**)&s->table, sizeof(SlotDev) * cfg->max_active) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(s->base);
+        delete s;
+        return BRNG_E_NOMEM;
+    }
     // unit_done bytes: a gamma unit's footprint is well above 2 KiB
     const uint64_t sbytes = bytes / 2048 + 4096;
     s->status = nullptr;
     if (hipHostMalloc((void**)&s->status, sbytes, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
+        (void)hipFree(s->table);
         (void)hipFree(s->base);
         delete s;
         return BRNG_E_NOMEM;
@@ -482,6 +509,7 @@ brng_status brng_serve_close(brng_server* s) {
     for (Req* r : left) delete r;
     for (hipEvent_t e : s->spare) (void)hipEventDestroy(e);
     (void)hipHostFree(s->status);
+    (void)hipFree(s->table);
     (void)hipFree(s->base);
     delete s;
     return st;

@@ -1,9 +1,11 @@
-// Multi-request launches: one kernel of a model over the units of up to
-// MULTI_MAX requests, each with its own descriptor, unit tables and pools.
-// The table travels as a kernel argument (no device copy, so the launch can
-// be captured in a graph and needs no allocation).  Used by the batched form
-// of brng_run_gibbs (requests sharing a context) and by the served form's
-// ticks (requests with their own memory).
+// Multi-request launches: one kernel over the units of several requests,
+// each with its own descriptor, unit tables and pools, of one model or of
+// several (the wave then picks its model's code).  The requests' slots sit
+// in a device table written by small copy launches whose kernel arguments
+// carry the slots (no host-to-device copy and no allocation, so the whole
+// sequence can be captured in a graph and replayed).  Used by the batched
+// form of brng_run_gibbs (requests sharing a context) and by the served
+// form's ticks (requests with their own memory).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -11,8 +13,6 @@
 #include "models.hpp"
 
 namespace brng {
-
-constexpr int MULTI_MAX = 16;
 
 struct SlotDev {
     DescDev D;
@@ -22,12 +22,15 @@ struct SlotDev {
     uint32_t pad;
 };
 
-struct SlotTable {
-    SlotDev s[MULTI_MAX];
-    uint32_t n;            // slots in use, 1..MULTI_MAX
-    uint32_t total_units;  // s[n - 1].unit_end
+// Slots per copy launch (its kernel argument stays under 4 KiB).
+constexpr int PUT_CHUNK = 16;
+struct SlotChunk {
+    SlotDev s[PUT_CHUNK];
+    uint32_t base;  // first table entry written
+    uint32_t n;     // slots in use
 };
-static_assert(sizeof(SlotTable) <= 4000, "kernel argument size");
+static_assert(sizeof(SlotChunk) <= 4000, "kernel argument size");
+static_assert(sizeof(SlotDev) % 4 == 0, "slots are copied as 32-bit words");
 
 // Bytes of LDS one wave of `model` uses.
 int model_lds_bytes_host(int model);
@@ -37,8 +40,11 @@ int model_lds_bytes_host(int model);
 uint32_t desc_unit_count(const brng_gibbs_desc& d);
 DescDev desc_to_device(const brng_gibbs_desc& d);
 
-// Launch the model's multi-request kernel over T on `stream`, with at most
-// `wpb` waves per workgroup.  Returns BRNG_OK or BRNG_E_HIP.
-brng_status launch_slots(int model, const SlotTable& T, hipStream_t stream, int wpb);
+// Write slots[0..n) (unit_end filled in here) to the device table `tab`
+// (at least n entries) and launch one kernel over all their units on
+// `stream`, with at most `wpb` waves per workgroup: the model's own kernel
+// when every slot has the same model, else the kernel that dispatches per
+// wave.  Returns BRNG_OK or BRNG_E_HIP.
+brng_status launch_slots(SlotDev* slots, uint32_t n, SlotDev* tab, hipStream_t stream, int wpb);
 
 }  // namespace brng

@@ -22,7 +22,7 @@ class Request:
     """Device arrays and descriptor of one served request.  The state is
     reset to its initial value by reset()."""
 
-    def __init__(self, torch, q: dict, dev):
+    def __init__(self, torch, q: dict, dev, sums: bool = False):
         self.q = q
         self.model = MODEL_OF[q["kind"]]
         n, s = q["chains"], q["steps"]
@@ -52,6 +52,14 @@ class Request:
             from . import order
             self.perm = torch.from_numpy(order.doc_order(q["offsets"], q["ntok"])).to(dev)
             kw = dict(offsets=self.offsets, ntok=self.ntok, perm=self.perm)
+        # per-chain sums of every output (LDA: per component), the request's
+        # summary besides its final state
+        self.sums = None
+        if sums:
+            nout = 4 if q["kind"] in ("uniform", "normal") else 2
+            width = int(q["offsets"][-1]) if q["kind"] == "dirichlet" else n
+            self.sums = torch.zeros((nout, width), dtype=torch.float64, device=dev)
+            kw["sums"] = self.sums
         self.desc = b.gibbs_desc(self.model, n, self.state, max_steps=s, seed=q["seed"], **kw)
         self.units = n if self.model == b.BRNG_MODEL_LDA else (n + 63) // 64
 
@@ -60,6 +68,8 @@ class Request:
             self.state.zero_()
         else:
             self.state.copy_(self.init)
+        if self.sums is not None:
+            self.sums.zero_()
 
 
 def run_plain(torch, reqs, window, stream=None):
@@ -85,13 +95,13 @@ def run_plain(torch, reqs, window, stream=None):
 
 
 def run_served(torch, reqs, arrivals_s, *, budget, window, max_active=64, tick_steps=256,
-               tick_sweeps=4, stream=None, on_done=None):
+               tick_sweeps=4, max_bypass_ms=0, stream=None, on_done=None):
     """Serve `reqs`, request i arriving arrivals_s[i] seconds after the start
     (all at 0 for a saturated run).  Returns (latency_s per request, makespan
     seconds from the first arrival to the last completion, server stats).
     on_done(count), if given, is called after each completed request."""
     srv = b.brng_serve_open(budget, window, max_active=max_active, tick_steps=tick_steps,
-                            tick_sweeps=tick_sweeps,
+                            tick_sweeps=tick_sweeps, max_bypass_ms=max_bypass_ms,
                             stream=stream or torch.cuda.current_stream())
     n = len(reqs)
     lat = np.zeros(n)

@@ -35,15 +35,23 @@ def _np(t):
     return t.cpu().numpy()
 
 
-def _requests(dev):
+N_SUMS = {0: 4, 1: 4, 2: 2, 3: 2, 4: 2}  # outputs x (sum, square) per model
+
+
+def _requests(dev, sums=False):
     """A mix of every model with traces, uneven lengths and several sizes.
     Returns (descs, arrays-to-check) per request; the arrays are the state and
-    traces the request writes."""
+    traces the request writes (and its sums array when sums=True)."""
     import torch
     b = _b()
     reqs = []
 
-    def add(desc, arrays, keep):
+    def add(desc, arrays, keep, width=None):
+        if sums:
+            w = width if width is not None else desc.n_chains
+            sm = torch.zeros((N_SUMS[desc.model], w), dtype=torch.float64, device=dev)
+            desc.d_sums = sm.data_ptr()
+            arrays = arrays + [sm]
         reqs.append((desc, arrays, keep))
 
     # triangle, fp64, with both traces
@@ -83,7 +91,8 @@ def _requests(dev):
     ct = torch.zeros((7, tot), dtype=torch.int32, device=dev)
     keep = (_t(wl["offsets"], dev), _t(wl["ntok"], dev))
     add(b.gibbs_desc(b.BRNG_MODEL_LDA, 20, cnt, max_steps=7, seed=15, trace=th, trace2=ct,
-                     trace_stride=tot, offsets=keep[0], ntok=keep[1]), [cnt, th, ct], keep)
+                     trace_stride=tot, offsets=keep[0], ntok=keep[1]), [cnt, th, ct], keep,
+        width=tot)
     # a second, larger gamma request (several units)
     w2 = workloads.gamma_chain(n_chains=700, lmin=30, lmax=60, seed=8)
     st2 = _t(w2["alpha0"], dev)
@@ -108,14 +117,15 @@ def _alone(dev, desc, arrays, keep):
         b.brng_destroy(ctx)
 
 
-def test_served_equals_alone(dev):
+@pytest.mark.parametrize("sums", [False, True], ids=["plain", "sums"])
+def test_served_equals_alone(dev, sums):
     import torch
     b = _b()
-    _say("serve alone-vs-mix: 6 requests, 5 models")
+    _say("serve alone-vs-mix: 6 requests, 5 models, sums", sums)
     alone = []
-    for desc, arrays, keep in _requests(dev):
+    for desc, arrays, keep in _requests(dev, sums):
         alone.append(_alone(dev, desc, arrays, keep))
-    mix = _requests(dev)
+    mix = _requests(dev, sums)
     budget = 3 * 1024 * 1024  # room for a few requests at a time
     srv = b.brng_serve_open(budget, W_SERVE, max_active=3, tick_steps=16, tick_sweeps=2,
                             stream=torch.cuda.current_stream())
@@ -297,3 +307,193 @@ def test_launch_shape_invariance_and_graph_replay(dev):
             torch.cuda.synchronize()
     finally:
         b.brng_destroy(ctx)
+
+
+def _sums_from_trace(model, n, tr, tr2, steps=None, perm=None):
+    """Per-chain sums of the outputs recomputed from the traces in step
+    order (fp64, one rounding per add; v * v is exact for fp32 v and rounded
+    once for fp64 v, as the kernels compute it).  Gamma traces are
+    [step][slot] with slot -> chain by perm and steps per chain."""
+    outs = [tr] if tr2 is None else [tr, tr2]
+    res = []
+    for o in outs:
+        o = o.astype(np.float64)
+        T = o.shape[0]
+        s1 = np.zeros(o.shape[1])
+        s2 = np.zeros(o.shape[1])
+        for t in range(T):
+            v = o[t]
+            if steps is not None:
+                ok = t < steps
+                v = np.where(ok, v, 0.0)
+            s1 = s1 + v
+            s2 = s2 + v * v
+        res += [s1, s2]
+    out = np.stack(res)
+    if perm is not None:  # slot order -> chain order
+        u = np.empty_like(out)
+        u[:, perm] = out
+        out = u
+    return out
+
+
+def test_sums_equal_trace_recomputation(dev):
+    """Every model's sums equal the same sums recomputed from its trace bit
+    for bit, and a run split in two launches gives the sums of one."""
+    import torch
+    b = _b()
+    _say("sums against traces, every model")
+    for desc, arrays, keep in _requests(dev, sums=True):
+        model = desc.model
+        layout = 1 if model == b.BRNG_MODEL_LDA else 0
+        ctx = b.brng_create(desc.seed, desc.n_chains, W_SERVE, layout=layout,
+                            stream=torch.cuda.current_stream())
+        try:
+            b.brng_run_gibbs(ctx, desc)
+            got = [_np(a) for a in arrays]
+        finally:
+            b.brng_destroy(ctx)
+        sm = got[-1]
+        if model == b.BRNG_MODEL_TRIANGLE_F64:
+            ref = _sums_from_trace(model, desc.n_chains, got[1], got[2])
+        elif model == b.BRNG_MODEL_NORMEXP:
+            ref = _sums_from_trace(model, desc.n_chains, got[1], got[2])
+        elif model == b.BRNG_MODEL_EXP_CHAIN:
+            ref = _sums_from_trace(model, desc.n_chains, got[1], None)
+        elif model == b.BRNG_MODEL_LDA:
+            th = got[1]
+            ref = _sums_from_trace(model, th.shape[1], th, None)
+        else:
+            if len(got) < 3:  # the gamma request without a trace
+                continue
+            stp = keep[0].cpu().numpy()
+            perm = keep[1].cpu().numpy()
+            ref = _sums_from_trace(model, desc.n_chains, got[1], None, steps=stp[perm], perm=perm)
+        assert np.array_equal(sm.view(np.uint64), ref.view(np.uint64)), model
+    # split: normal/exponential 40 + 60 steps (resumed) = 100 steps at once
+    n = 130
+    outs = []
+    for split in (False, True):
+        ctx = b.brng_create(5, n, [0, 512, 512, 0], stream=torch.cuda.current_stream())
+        try:
+            st = torch.zeros(n, dtype=torch.float32, device=dev)
+            sm = torch.zeros((4, n), dtype=torch.float64, device=dev)
+            if split:
+                b.brng_run_gibbs(ctx, b.gibbs_desc(b.BRNG_MODEL_NORMEXP, n, st, max_steps=40,
+                                                   seed=5, sums=sm))
+                b.brng_run_gibbs(ctx, b.gibbs_desc(b.BRNG_MODEL_NORMEXP, n, st, max_steps=60,
+                                                   seed=5, sums=sm, flags=b.BRNG_FLAG_RESUME))
+            else:
+                b.brng_run_gibbs(ctx, b.gibbs_desc(b.BRNG_MODEL_NORMEXP, n, st, max_steps=100,
+                                                   seed=5, sums=sm))
+            outs.append((_np(st), _np(sm)))
+        finally:
+            b.brng_destroy(ctx)
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1].view(np.uint64), outs[1][1].view(np.uint64))
+
+
+def test_batched_mixed_models_one_call(dev):
+    """120 requests of all five models (some with sums) in one
+    brng_run_gibbs call: one launch over all their units, each wave running
+    its request's model; every request equals its plain run bit for bit."""
+    import torch
+    b = _b()
+    _say("batched: 120 mixed requests in one call")
+    rng = np.random.default_rng(77)
+    specs = []
+    for i in range(120):
+        model = i % 5
+        specs.append((model, int(rng.integers(1, 200)), int(rng.integers(3, 30)), 900 + i,
+                      bool(i % 3 == 0)))
+
+    def build(model, n, s, seed, with_sums, unit_base):
+        if model == b.BRNG_MODEL_TRIANGLE_F64:
+            st = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+            tr = torch.zeros((s, n), dtype=torch.float64, device=dev)
+            d = b.gibbs_desc(model, n, st, max_steps=s, seed=seed, trace=tr, trace_stride=n,
+                             unit_base=unit_base)
+            arrs, keep, units, width = [st, tr], None, (n + 63) // 64, n
+        elif model in (b.BRNG_MODEL_NORMEXP, b.BRNG_MODEL_EXP_CHAIN):
+            st = torch.zeros(n, dtype=torch.float32, device=dev)
+            tr = torch.zeros((s, n), dtype=torch.float32, device=dev)
+            d = b.gibbs_desc(model, n, st, max_steps=s, seed=seed, trace=tr, trace_stride=n,
+                             unit_base=unit_base)
+            arrs, keep, units, width = [st, tr], None, (n + 63) // 64, n
+        elif model == b.BRNG_MODEL_GAMMA_CHAIN:
+            w = workloads.gamma_chain(n_chains=n, lmin=1, lmax=s, seed=seed)
+            st = _t(w["alpha0"], dev)
+            stp = _t(w["steps"], dev)
+            tr = torch.full((s, n), float("nan"), dtype=torch.float32, device=dev)
+            d = b.gibbs_desc(model, n, st, max_steps=s, seed=seed, trace=tr, trace_stride=n,
+                             steps=stp, unit_base=unit_base)
+            arrs, keep, units, width = [st, tr], stp, (n + 63) // 64, n
+        else:
+            nd = max(1, n // 20)
+            wl = workloads.lda(n_docs=nd, sweeps=s, seed=seed)
+            tot = int(wl["offsets"][-1])
+            cnt = torch.zeros(tot, dtype=torch.int32, device=dev)
+            th = torch.zeros((s, tot), dtype=torch.float32, device=dev)
+            keep = (_t(wl["offsets"], dev), _t(wl["ntok"], dev))
+            d = b.gibbs_desc(model, nd, cnt, max_steps=s, seed=seed, trace=th, trace_stride=tot,
+                             offsets=keep[0], ntok=keep[1], unit_base=unit_base)
+            arrs, units, width = [cnt, th], nd, tot
+        if with_sums:
+            sm = torch.zeros((N_SUMS[model], width), dtype=torch.float64, device=dev)
+            d.d_sums = sm.data_ptr()
+            arrs = arrs + [sm]
+        return d, arrs, keep, units
+
+    refs = []
+    for model, n, s, seed, ws in specs:
+        d, arrs, keep, _ = build(model, n, s, seed, ws, 0)
+        refs.append(_alone(dev, d, arrs, keep))
+    descs, outs, keeps, base = [], [], [], 0
+    for model, n, s, seed, ws in specs:
+        d, arrs, keep, units = build(model, n, s, seed, ws, base)
+        descs.append(d)
+        outs.append(arrs)
+        keeps.append(keep)
+        base += units
+    ctx = b.brng_create(3, base, W_PLAIN, layout=1, stream=torch.cuda.current_stream())
+    try:
+        b.brng_run_gibbs(ctx, descs)
+        for i, (arrs, ref) in enumerate(zip(outs, refs)):
+            for j, (a, r) in enumerate(zip(arrs, ref)):
+                got = _np(a)
+                assert np.array_equal(got.view(np.uint8), r.view(np.uint8)), (i, specs[i], j)
+    finally:
+        b.brng_destroy(ctx)
+
+
+def test_admission_passes_a_blocked_head(dev):
+    """With a bypass bound, a small request that fits is admitted while an
+    older large one waits for memory; with none, it waits behind it."""
+    import torch
+    b = _b()
+    _say("serve admission past a blocked head")
+    n_big = 150 * 64  # 150 units x (2 x 512 floats + 96 B) ~ 0.6 MiB
+    for bypass in (0, 60000):
+        srv = b.brng_serve_open(1 << 20, W_SERVE, max_active=8, tick_steps=8, tick_sweeps=1,
+                                max_bypass_ms=bypass, stream=torch.cuda.current_stream())
+        try:
+            sts = [torch.ones(n_big, dtype=torch.float32, device=dev) for _ in range(2)]
+            small = torch.ones(64, dtype=torch.float32, device=dev)
+            t = [b.brng_serve_submit(srv, b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, n_big, sts[i],
+                                                       max_steps=400, seed=200 + i))
+                 for i in range(2)]
+            t.append(b.brng_serve_submit(srv, b.gibbs_desc(b.BRNG_MODEL_GAMMA_CHAIN, 64, small,
+                                                           max_steps=5, seed=300)))
+            done = {}
+            while len(done) < 3:
+                b.brng_serve_progress(srv, wait=True)
+                for d in b.brng_serve_poll(srv):
+                    assert d["status"] == 0
+                    done[d["ticket"]] = d
+            admit = [done[k]["t_admit_ns"] for k in t]
+            if bypass:
+                assert admit[2] < admit[1], admit  # the small one went first
+            else:
+                assert admit[0] <= admit[1] <= admit[2], admit
+        finally:
+            b.brng_serve_close(srv)
