@@ -321,11 +321,8 @@ def setup_lda(torch, b, args):
     ct = torch.empty((sweeps, total), dtype=torch.int32, device=dev)
     toff = torch.from_numpy(wl["offsets"]).to(dev)
     tntok = torch.from_numpy(wl["ntok"]).to(dev)
-    # waves take documents by decreasing work (results do not depend on it)
-    from paper_1412_4825_amd import order
-    tperm = torch.from_numpy(order.doc_order(wl["offsets"], wl["ntok"])).to(dev)
     kw = dict(max_steps=sweeps, seed=args.seed, trace=th, trace2=ct, trace_stride=total,
-              offsets=toff, ntok=tntok, perm=tperm)
+              offsets=toff, ntok=tntok)
     fresh = b.gibbs_desc(b.BRNG_MODEL_LDA, nd, counts, **kw)
     resume = b.gibbs_desc(b.BRNG_MODEL_LDA, nd, counts, flags=b.BRNG_FLAG_RESUME, **kw)
     dv = sweeps * (total + int(wl["ntok"].sum()))
@@ -351,7 +348,7 @@ def setup_lda(torch, b, args):
                 "sample": "the first %d documents x %d sweeps (%.3g deviates) in one thread" % (sd, sweeps, sdv)}
 
     return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_U, b.BRNG_N, b.BRNG_E],
-                keep=(counts, th, ct, toff, tntok, tperm),
+                keep=(counts, th, ct, toff, tntok),
                 entry_bytes={b.BRNG_U: 4, b.BRNG_N: 4, b.BRNG_E: 4},
                 windows={b.BRNG_U: W, b.BRNG_N: W, b.BRNG_E: W},
                 deviates=dv, out_bytes=sweeps * total * 8, dtype="f32", cpu=cpu, cpu1=cpu1,

@@ -253,10 +253,10 @@ typedef struct {
     int32_t pad0;
     const int32_t *d_steps; /* per-chain steps (user order) or NULL */
     const int32_t *d_perm;  /* chains: slot -> chain, or NULL for identity
-                               (see brng_sort_by_length); LDA: wave order of
-                               the documents (wave i runs document
-                               d_perm[i]; a permutation of 0..n_docs-1), or
-                               NULL; results do not depend on it */
+                               (see brng_sort_by_length); LDA: ignored (the
+                               library schedules documents by their number
+                               of components; results never depend on the
+                               order) */
     void *d_state;          /* model state, user order, in/out:
                                TRIANGLE: double[2][n] (x then y)
                                NORMEXP : float[n] (s)
@@ -301,8 +301,13 @@ typedef struct {
  * Each request's units [unit_base, unit_base + n_units) must lie inside the
  * context and must not overlap another request's.  The needed kinds must be
  * enabled: TRIANGLE U64; NORMEXP N,E; GAMMA N,E; EXP E; LDA U,N,E.  LDA
- * documents need 1..256 components (others are skipped).  Traces need
- * max_steps rows of trace_stride elements.
+ * documents need 1..256 components, a token count >= 0 and, with traces,
+ * components inside trace_stride; a document that breaks this gets -1 in
+ * every count of its state (when it has components) and nothing else.  A
+ * single LDA request first runs a one-workgroup planning kernel that sorts
+ * the documents by size (documents of up to 16 components share a wave,
+ * each with its own streams), using the context's plan memory.  Traces
+ * need max_steps rows of trace_stride elements.
  * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_HIP. */
 brng_status brng_run_gibbs(brng_ctx *ctx, const brng_gibbs_desc *h_descs, uint32_t n_desc);
 
@@ -319,8 +324,9 @@ brng_status brng_run_gibbs(brng_ctx *ctx, const brng_gibbs_desc *h_descs, uint32
  * fresh context with window4.  window4[kind] as in brng_config (the model's
  * kinds must be enabled); wpb = waves per workgroup (1, 2, 4 or 8, halved
  * while a workgroup's LDS would exceed 64 KiB).  The footprint is, per kind
- * the model reads, n_units x window x entry size, plus 96 bytes per unit
- * (each term rounded up to 256 bytes); a request beyond the array returns
+ * the model reads, n_units x window x entry size, plus 96 bytes per unit,
+ * plus for LDA 4 x (8 + 6 n_docs) bytes of launch plan (each term rounded
+ * up to 256 bytes); a request beyond the array returns
  * BRNG_E_TOO_LARGE.  Caller-owned device arrays as in brng_gibbs_desc.
  * Every call on one GPU uses the same array: calls that overlap on that GPU
  * (other streams, other threads) race and give undefined results; calls in

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/brng.h"
+#include "lda_packed.hpp"
 #include "models.hpp"
 #include "slots.hpp"
 
@@ -699,18 +700,10 @@ __host__ __device__ constexpr int model_lds_bytes(int model) {
                                  : RING_BYTES;
 }
 
-// LDA waves take documents in the order of D.perm when it is given (a
-// permutation of the documents, e.g. by decreasing work so that the longest
-// ones start first and the launch has no long tail); each document is its
-// own unit, so the order changes no result.  Returns false for an entry
-// outside the request.
-__device__ __forceinline__ bool lda_doc_of(const DescDev& D, uint32_t local, uint32_t* doc) {
-    *doc = D.perm ? (uint32_t)D.perm[local] : local;
-    return *doc < D.n_units;
-}
-
-// Documents the LDA kernel cannot serve are skipped: K outside [1, 256],
-// negative token counts, or traces too narrow for their components.
+// Documents the LDA kernels cannot serve: K outside [1, 256], negative
+// token counts, or traces too narrow for their components.  Such a document
+// gets -1 in every count of its state (when it has components) and nothing
+// else changes.
 __device__ __forceinline__ bool lda_doc_ok(const DescDev& D, uint32_t doc) {
     const int32_t off = D.offsets[doc];
     const int K = D.offsets[doc + 1] - off;
@@ -718,15 +711,126 @@ __device__ __forceinline__ bool lda_doc_ok(const DescDev& D, uint32_t doc) {
     return K >= 1 && K <= LDA_KMAX && D.ntok[doc] >= 0 && fits;
 }
 
-// Plain form: one launch per request, one wave per unit.
+// Mark an unserved document (threads t of n write its counts).
+__device__ __forceinline__ void lda_doc_reject(const DescDev& D, uint32_t doc, uint32_t t,
+                                               uint32_t n) {
+    const int32_t off = D.offsets[doc];
+    const int K = D.offsets[doc + 1] - off;
+    if (off < 0 || K < 1) return;
+    int32_t* counts = reinterpret_cast<int32_t*>(D.state) + off;
+    for (int k = (int)t; k < K; k += (int)n) counts[k] = -1;
+}
+
+// The plain LDA launch runs from a plan that a one-workgroup kernel builds
+// first: the request's documents in six lists by component count, each in
+// index order, laid out so that the most work per wave starts first: up to
+// 8 components (eight documents to a wave), 129..256, 9..16 (four to a
+// wave), 65..128, 33..64 and 17..32 (one to a wave).  plan[0..5] = the
+// lists' lengths, list j at plan + PLAN_HEAD + j n_docs.  Documents that
+// cannot be served are marked here.  (The order changes no result: every
+// document is its own unit.)
+constexpr int PLAN_HEAD = 8;
+constexpr int PLAN_LISTS = 6;
+constexpr int PLAN_THREADS = 1024;
+
+__device__ __forceinline__ int plan_list(int K) {
+    return K <= 8 ? 0 : K <= 16 ? 2 : K <= 32 ? 5 : K <= 64 ? 4 : K <= 128 ? 3 : 1;
+}
+
+__global__ __launch_bounds__(PLAN_THREADS) void k_lda_plan(DescDev D, int32_t* plan) {
+    __shared__ uint32_t wc[PLAN_THREADS / 64][PLAN_LISTS];
+    __shared__ uint32_t base[PLAN_LISTS];
+    constexpr int AHEAD = 8;  // blocks of documents whose inputs are loaded together
+    const uint32_t n = D.n_units, tid = threadIdx.x, wv = tid / 64;
+    if (tid < PLAN_LISTS) base[tid] = 0;
+    __syncthreads();
+    int32_t* lists = plan + PLAN_HEAD;
+    for (uint32_t c0 = 0; c0 < n; c0 += AHEAD * PLAN_THREADS) {
+        int32_t o0[AHEAD], o1[AHEAD], nt[AHEAD];
+#pragma unroll
+        for (int i = 0; i < AHEAD; ++i) {
+            const uint32_t doc = c0 + (uint32_t)i * PLAN_THREADS + tid;
+            o0[i] = o1[i] = nt[i] = 0;
+            if (doc < n) {
+                o0[i] = D.offsets[doc];
+                o1[i] = D.offsets[doc + 1];
+                nt[i] = D.ntok[doc];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < AHEAD; ++i) {
+            const uint32_t b0 = c0 + (uint32_t)i * PLAN_THREADS;
+            if (b0 >= n) break;
+            const uint32_t doc = b0 + tid;
+            int l = -1;
+            if (doc < n) {
+                const int K = o1[i] - o0[i];
+                const bool fits = (!D.trace && !D.trace2) ||
+                                  (o0[i] >= 0 && (int64_t)o0[i] + K <= D.stride);
+                if (K >= 1 && K <= LDA_KMAX && nt[i] >= 0 && fits)
+                    l = plan_list(K);
+                else
+                    lda_doc_reject(D, doc, 0, 1);
+            }
+            uint32_t rank = 0;
+            for (int j = 0; j < PLAN_LISTS; ++j) {
+                const uint64_t mk = __builtin_amdgcn_ballot_w64(l == j);
+                if (l == j) rank = mask_rank(mk);
+                if (lane_id() == 0) wc[wv][j] = (uint32_t)__popcll(mk);
+            }
+            __syncthreads();
+            if (l >= 0) {
+                uint32_t pos = base[l] + rank;
+                for (uint32_t w = 0; w < wv; ++w) pos += wc[w][l];
+                lists[(size_t)l * n + pos] = (int32_t)doc;
+            }
+            __syncthreads();
+            if (tid < PLAN_LISTS) {
+                uint32_t t = 0;
+                for (uint32_t w = 0; w < PLAN_THREADS / 64; ++w) t += wc[w][tid];
+                base[tid] += t;
+            }
+            __syncthreads();
+        }
+    }
+    if (tid < PLAN_LISTS) plan[tid] = (int32_t)base[tid];
+}
+
+// Plain form: one launch per request, one wave per unit (LDA: waves as the
+// plan lays them out: groups of small documents first, then one document
+// per wave).
 template <int MODEL>
-__global__ __launch_bounds__(512) void k_gibbs(DescDev D, Meta* meta, Pools P) {
+__global__ __launch_bounds__(512) void k_gibbs(DescDev D, Meta* meta, Pools P,
+                                               const int32_t* plan) {
     extern __shared__ __align__(16) unsigned char lds_all[];
     const uint32_t w = wave_in_block();
-    uint32_t local = blockIdx.x * (blockDim.x >> 6) + w;
+    const uint32_t local = blockIdx.x * (blockDim.x >> 6) + w;
     if (local >= D.n_units) return;
-    if (MODEL == M_LDA && !(lda_doc_of(D, local, &local) && lda_doc_ok(D, local))) return;
-    run_unit<MODEL>(D, meta, P, local, lds_all + w * model_lds_bytes(MODEL));
+    unsigned char* lds = lds_all + w * model_lds_bytes(MODEL);
+    if constexpr (MODEL == M_LDA) {
+        // the lists in wave order, with documents per wave 8, 1, 4, 1, 1, 1
+        const uint32_t n = D.n_units;
+        uint32_t w = local;
+        for (int j = 0; j < PLAN_LISTS; ++j) {
+            const uint32_t len = (uint32_t)plan[j];
+            const uint32_t per = j == 0 ? 8u : j == 2 ? 4u : 1u;
+            const uint32_t waves = (len + per - 1) / per;
+            if (w < waves) {
+                const int32_t* list = plan + PLAN_HEAD + (size_t)j * n + per * w;
+                const uint32_t cnt = min(per, len - per * w);
+                if (j == 0)
+                    unit_lda_packed<8>(D, meta, P, list, cnt, lds);
+                else if (j == 2)
+                    unit_lda_packed<16>(D, meta, P, list, cnt, lds);
+                else
+                    run_unit<M_LDA>(D, meta, P, (uint32_t)list[0], lds);
+                return;
+            }
+            w -= waves;
+        }
+    } else {
+        run_unit<MODEL>(D, meta, P, local, lds);
+    }
 }
 
 // Batched and served form: the units of several requests in one launch.  A
@@ -750,10 +854,15 @@ __device__ __forceinline__ int slot_lookup(const SlotDev* __restrict__ tab, uint
     return (int)lo;
 }
 
+// LDA documents run in index order here (the descriptor's document order
+// is only a scheduling hint, used by the plain launch).
 template <int MODEL>
 __device__ __forceinline__ void run_slot_unit(const DescDev& D, Meta* meta, const Pools& P,
                                               uint32_t local, unsigned char* lds) {
-    if (MODEL == M_LDA && !(lda_doc_of(D, local, &local) && lda_doc_ok(D, local))) return;
+    if (MODEL == M_LDA && !lda_doc_ok(D, local)) {
+        lda_doc_reject(D, local, lane_id(), 64);
+        return;
+    }
     run_unit<MODEL>(D, meta, P, local, lds);
 }
 
@@ -858,6 +967,7 @@ struct brng_ctx {
     void* pool[4];
     Meta* meta;
     SlotDev* table;  // slots of the batched form (BRNG_BATCH_MAX entries)
+    int32_t* lda_plan;  // plain LDA launches: PLAN_HEAD + PLAN_LISTS n_units int32
     int wpb;
     int n_cu;
     // events for the next plain chain launch (brng_time_next_launch)
@@ -926,6 +1036,7 @@ static void free_ctx(brng_ctx* c) {
         if (c->pool[k]) (void)hipFree(c->pool[k]);
     if (c->meta) (void)hipFree(c->meta);
     if (c->table) (void)hipFree(c->table);
+    if (c->lda_plan) (void)hipFree(c->lda_plan);
     delete c;
 }
 
@@ -1061,7 +1172,9 @@ brng_status brng_create(const brng_config* cfg, brng_ctx** out) {
         }
     }
     if (hipMalloc((void**)&c->meta, sizeof(Meta) * (size_t)c->n_units) != hipSuccess ||
-        hipMalloc((void**)&c->table, sizeof(SlotDev) * BRNG_BATCH_MAX) != hipSuccess) {
+        hipMalloc((void**)&c->table, sizeof(SlotDev) * BRNG_BATCH_MAX) != hipSuccess ||
+        hipMalloc((void**)&c->lda_plan,
+                  sizeof(int32_t) * (PLAN_HEAD + PLAN_LISTS * (size_t)c->n_units)) != hipSuccess) {
         free_ctx(c);
         return BRNG_E_NOMEM;
     }
@@ -1329,18 +1442,25 @@ static int model_wpb(int wpb, int model) {
 // One request's chain kernel over unit records `meta` and pools P; with an
 // event pair (ts, te) the launch records them at the kernel's own start and
 // end.
+// plan: for LDA, PLAN_HEAD + PLAN_LISTS n_docs int32 of device memory; the
+// plan kernel runs first.
 static brng_status launch_gibbs(hipStream_t stream, int wpb_req, const DescDev& D, Meta* meta,
-                                const Pools& P, hipEvent_t ts, hipEvent_t te) {
+                                const Pools& P, int32_t* plan, hipEvent_t ts, hipEvent_t te) {
     const int wpb = model_wpb(wpb_req, D.model);
     const dim3 grid((D.n_units + wpb - 1) / wpb), block(64 * wpb);
     const size_t lds = (size_t)wpb * model_lds_bytes(D.model);
+    if (D.model == M_LDA) {
+        hipLaunchKernelGGL(k_lda_plan, dim3(1), dim3(PLAN_THREADS), 0, stream, D, plan);
+        HIPCHK(hipGetLastError());
+    }
 #define BRNG_LAUNCH_GIBBS(MODEL)                                                               \
     do {                                                                                      \
         if (ts)                                                                               \
             hipExtLaunchKernelGGL(k_gibbs<MODEL>, grid, block, (uint32_t)lds, stream, ts, te, \
-                                  0u, D, meta, P);                                            \
+                                  0u, D, meta, P, (const int32_t*)plan);                      \
         else                                                                                  \
-            hipLaunchKernelGGL(k_gibbs<MODEL>, grid, block, lds, stream, D, meta, P);         \
+            hipLaunchKernelGGL(k_gibbs<MODEL>, grid, block, lds, stream, D, meta, P,          \
+                               (const int32_t*)plan);                                         \
     } while (0)
     switch (D.model) {
         case M_TRIANGLE: BRNG_LAUNCH_GIBBS(M_TRIANGLE); break;
@@ -1358,7 +1478,7 @@ static brng_status launch_plain(brng_ctx* c, const DescDev& D) {
     // a pending event pair is used by this launch, then forgotten
     hipEvent_t ts = c->t_start, te = c->t_stop;
     c->t_start = c->t_stop = nullptr;
-    return launch_gibbs(c->stream, c->wpb, D, c->meta, make_pools(c), ts, te);
+    return launch_gibbs(c->stream, c->wpb, D, c->meta, make_pools(c), c->lda_plan, ts, te);
 }
 
 
@@ -1454,6 +1574,9 @@ brng_status brng_run_gibbs_static(const brng_gibbs_desc* d, const uint32_t* wind
     }
     const uint64_t meta_off = total;
     total += scratch_round(nu * sizeof(Meta));
+    const uint64_t plan_off = total;  // LDA: the launch plan and its scratch
+    if (d->model == BRNG_MODEL_LDA)
+        total += scratch_round((PLAN_HEAD + PLAN_LISTS * nu) * sizeof(int32_t));
     if (total > STATIC_SCRATCH_BYTES) return BRNG_E_TOO_LARGE;
     void* base = nullptr;
     st = scratch_address(&base);
@@ -1469,7 +1592,8 @@ brng_status brng_run_gibbs_static(const brng_gibbs_desc* d, const uint32_t* wind
     // windows start empty (regenerated on first use) and its unit records
     // are built in registers and written at the end
     return launch_gibbs((hipStream_t)stream, wpb, desc_to_device(*d),
-                        reinterpret_cast<Meta*>(b + meta_off), P, nullptr, nullptr);
+                        reinterpret_cast<Meta*>(b + meta_off), P,
+                        reinterpret_cast<int32_t*>(b + plan_off), nullptr, nullptr);
 }
 
 brng_status brng_sort_by_length(uint32_t n, const int32_t* steps, int32_t* perm) {

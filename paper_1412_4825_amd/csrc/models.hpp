@@ -651,7 +651,11 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
             y[b] = in ? yv[k] : 0.0f;
             if (in) part += y[b];
         }
-        const float S = wave_sum(part);
+        // documents of up to 16 components (all in lanes 0..15) sum in the
+        // same order as when several share a wave (group_sum)
+        const float S = K <= 16 ? __builtin_bit_cast(float, __builtin_amdgcn_readlane(
+                                      __builtin_bit_cast(int32_t, group_sum<16>(y[0])), 0))
+                                : wave_sum(part);
         // theta, quantised weights and their prefix sums
         int32_t carry = 0;
         float th[4];

@@ -375,6 +375,23 @@ __device__ __forceinline__ float wave_sum(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, t), 63));
 }
 
+// Sum over an aligned group of S lanes (S = 8 or 16) by exchanges with the
+// lanes whose index differs in bit 3 (S = 16 only), then bit 2, 1 and 0:
+// every lane of the group gets the same value.  For a group of 16 whose
+// upper 8 lanes hold zero the first exchange adds zero to each value, so the
+// sum equals that of the lower 8 lanes as a group of 8: documents of up to 8
+// components get the same sum in either layout, and in the wave of a single
+// document.
+template <int S>
+__device__ __forceinline__ float group_sum(float v) {
+    if constexpr (S >= 16)
+        v = v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x201F));  // xor 8
+    v = v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));      // xor 4
+    v = v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x081F));      // xor 2
+    v = v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x041F));      // xor 1
+    return v;
+}
+
 // Inclusive prefix sum over lanes (integers, exact).
 __device__ __forceinline__ int32_t wave_incl_scan(int32_t v) { return dpp_incl_scan(v); }
 

@@ -48,10 +48,7 @@ class Request:
             self.deviates = (int(off[-1]) + int(ntok.sum())) * s
         kw = {}
         if self.model == b.BRNG_MODEL_LDA:
-            # documents by decreasing work (no effect on results)
-            from . import order
-            self.perm = torch.from_numpy(order.doc_order(q["offsets"], q["ntok"])).to(dev)
-            kw = dict(offsets=self.offsets, ntok=self.ntok, perm=self.perm)
+            kw = dict(offsets=self.offsets, ntok=self.ntok)
         # per-chain sums of every output (LDA: per component), the request's
         # summary besides its final state
         self.sums = None

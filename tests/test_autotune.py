@@ -24,18 +24,3 @@ def test_pick_uses_best_of_repeats():
     seq = iter([5.0, 1.0, 4.0, 4.0])
     best = autotune.pick(lambda w, k: next(seq), windows=(512, 1024), wpbs=(1,), reps=2)
     assert best["window"] == 512 and best["seconds"] == 1.0
-
-
-def test_doc_order_is_a_stable_permutation_by_work():
-    """Documents by decreasing estimated work (components weigh about 2.45
-    tokens each), ties in document order."""
-    import numpy as np
-    from paper_1412_4825_amd import order
-    K = np.array([8, 256, 8, 64, 16, 256, 8], dtype=np.int64)
-    ntok = np.array([200, 10, 200, 300, 0, 10, 199], dtype=np.int64)
-    off = np.concatenate([[0], np.cumsum(K)]).astype(np.int32)
-    perm = order.doc_order(off, ntok)
-    assert sorted(perm.tolist()) == list(range(7))
-    work = 220 + 2.45 * K + ntok
-    assert np.all(np.diff(work[perm]) <= 0)
-    assert perm.tolist() == [1, 5, 3, 0, 2, 6, 4]

@@ -7,7 +7,7 @@ launch after the bulk refills, as bench.py times it.
   length, window 512, eight waves per block requested (the autotuner's usual
   choice; the launch fits four in its LDS);
 - LDA: 16,384 documents x 100 sweeps, window 512, eight waves per block
-  requested, documents in the work order the bench uses.
+  requested.
 
 Every test prints its case before the GPU calls."""
 import numpy as np
@@ -274,10 +274,8 @@ def test_lda_full_size(dev):
     cols = [c for d in docs for c in range(off[d], off[d + 1])]
     try:
         b.brng_set_launch(ctx, 8)
-        from paper_1412_4825_amd import order
-        tperm = _t(order.doc_order(off, ntok), dev)
         kw = dict(max_steps=sweeps, seed=SEED, trace=th, trace2=ct, trace_stride=total,
-                  offsets=_t(off, dev), ntok=_t(ntok, dev), perm=tperm)
+                  offsets=_t(off, dev), ntok=_t(ntok, dev))
         b.brng_run_gibbs(ctx, b.gibbs_desc(b.BRNG_MODEL_LDA, nd, counts, **kw))
         runs = [(_cols(th, cols), _cols(ct, cols))]
         for k in (b.BRNG_U, b.BRNG_N, b.BRNG_E):

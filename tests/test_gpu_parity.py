@@ -565,17 +565,15 @@ def test_lda_ragged_components_and_tokens(dev):
 
 
 def test_lda_document_order_invariance(dev):
-    """Waves taking documents in another order (the work order the bench
-    uses, and a random one), with other windows and workgroup sizes, give the
-    same counts, traces and cursors bit for bit: each document is its own
-    unit."""
+    """Other windows and workgroup sizes (and an order hint, which the
+    library ignores) give the same counts, traces and cursors bit for bit:
+    each document is its own unit."""
     import torch
-    from paper_1412_4825_amd import order
     b = _b()
     w = workloads.lda(n_docs=300, sweeps=6, seed=12)
     seed = 77
     nd, total, sw = w["n_docs"], int(w["offsets"][-1]), w["sweeps"]
-    perms = [None, order.doc_order(w["offsets"], w["ntok"]),
+    perms = [None, np.arange(nd, dtype=np.int32)[::-1].copy(),
              np.random.default_rng(4).permutation(nd).astype(np.int32)]
     # (document order, window, waves per workgroup); the bench's tuned shape
     # is the second
@@ -799,3 +797,116 @@ def test_time_next_launch_brackets_the_chain_kernel(dev):
             b.brng_destroy(ctx)
     assert np.array_equal(outs[0][0], outs[1][0], equal_nan=True)
     assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def _lda_small_workload(seed):
+    """Documents of 1..20 components (most at most 16, so that the plain
+    launch packs them several to a wave) with token counts at the edges of a
+    64-token call and of a 256-entry window chunk, plus Poisson(200)."""
+    rng = np.random.default_rng(seed)
+    nd = 301
+    K = rng.integers(1, 17, nd).astype(np.int32)
+    K[::13] = rng.integers(17, 21, K[::13].size)
+    ntok = rng.poisson(200, nd).astype(np.int32)
+    edge = [0, 1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 700]
+    ntok[:len(edge)] = edge
+    off = np.zeros(nd + 1, dtype=np.int32)
+    off[1:] = np.cumsum(K)
+    return off, ntok
+
+
+def _lda_run(dev, off, ntok, sweeps, seed, batched, perm=None, flags=0, state=None):
+    """One LDA request with traces and sums, alone (the plain launch, small
+    documents packed) or beside a one-unit exponential-chain request (the
+    batched launch, one document per wave).  Returns host copies of counts,
+    traces, sums and the request's cursors."""
+    import torch
+    b = _b()
+    nd, tot = len(off) - 1, int(off[-1])
+    ctx = b.brng_create(seed, nd + 1, W_SMALL, layout=1, stream=torch.cuda.current_stream())
+    try:
+        counts = torch.zeros(tot, dtype=torch.int32, device=dev)
+        th = torch.full((sweeps, tot), float("nan"), dtype=torch.float32, device=dev)
+        ct = torch.full((sweeps, tot), -7, dtype=torch.int32, device=dev)
+        sm = torch.zeros((2, tot), dtype=torch.float64, device=dev)
+        keep = [_t(off, dev), _t(ntok, dev)]
+        if perm is not None:
+            keep.append(_t(perm, dev))
+        d = b.gibbs_desc(b.BRNG_MODEL_LDA, nd, counts, max_steps=sweeps, seed=seed, trace=th,
+                         trace2=ct, trace_stride=tot, offsets=keep[0], ntok=keep[1],
+                         perm=keep[2] if perm is not None else None, sums=sm)
+        descs = [d]
+        if batched:
+            e = torch.zeros(64, dtype=torch.float32, device=dev)
+            keep.append(e)
+            descs.append(b.gibbs_desc(b.BRNG_MODEL_EXP_CHAIN, 64, e, max_steps=3, seed=1,
+                                      unit_base=nd))
+        b.brng_run_gibbs(ctx, descs)
+        first = [_np(th).copy(), _np(ct).copy()]
+        # a second call resumes from the cursors and counts of the first
+        descs[0].flags = b.BRNG_FLAG_RESUME
+        b.brng_run_gibbs(ctx, descs)
+        out = [_np(counts), _np(th), _np(ct), _np(sm)]
+        out.append(b.brng_get_cursors(ctx)[:nd])
+        return out + first
+    finally:
+        b.brng_destroy(ctx)
+
+
+def test_lda_packed_documents_equal_one_per_wave(dev):
+    """Documents with up to 16 components run several to a wave in the plain
+    launch; every result (counts, theta and counts traces, sums, cursors,
+    over a fresh and a resumed call) equals the batched launch's, which runs
+    one document per wave, bit for bit; the theta of the packed run also
+    passes the oracle."""
+    off, ntok = _lda_small_workload(21)
+    _say("lda packed vs one per wave", len(off) - 1)
+    a = _lda_run(dev, off, ntok, 6, 77, batched=False)
+    c = _lda_run(dev, off, ntok, 6, 77, batched=True)
+    for i, (x, y) in enumerate(zip(a, c)):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), i
+    # the first call's six sweeps against the oracle
+    r = oracle.lda(77, off, ntok, 6)
+    diverged = _lda_diverged(a[5], a[6], r, off, 6)
+    print("lda packed diverged docs", diverged, flush=True)
+    assert diverged <= 2
+
+
+def test_lda_document_order_checked_and_bad_documents_marked(dev):
+    """An order with a repeated document is ignored (the results equal those
+    of the index order); documents the kernels cannot serve (257
+    components, a negative token count) get -1 in every count, the others
+    are unaffected, in the plain and the batched launch."""
+    off, ntok = _lda_small_workload(5)
+    nd = len(off) - 1
+    _say("lda bad order and bad documents", nd)
+    ref = _lda_run(dev, off, ntok, 3, 9, batched=False)
+    dup = np.arange(nd, dtype=np.int32)[::-1].copy()
+    dup[3] = dup[4]
+    got = _lda_run(dev, off, ntok, 3, 9, batched=False, perm=dup)
+    for i, (x, y) in enumerate(zip(ref, got)):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), i
+    # a valid reversed order changes nothing either
+    rev = np.arange(nd, dtype=np.int32)[::-1].copy()
+    got = _lda_run(dev, off, ntok, 3, 9, batched=False, perm=rev)
+    for i, (x, y) in enumerate(zip(ref, got)):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), i
+    # bad documents: document 7 gets 257 components, document 11 -1 tokens
+    K = np.diff(off).astype(np.int64)
+    K[7] = 257
+    off2 = np.zeros(nd + 1, dtype=np.int32)
+    off2[1:] = np.cumsum(K)
+    nt2 = ntok.copy()
+    nt2[11] = -1
+    for batched in (False, True):
+        res = _lda_run(dev, off2, nt2, 3, 9, batched=batched)
+        cnt = res[0]
+        for dd in (7, 11):
+            assert (cnt[off2[dd]:off2[dd + 1]] == -1).all(), (batched, dd)
+        # every other document as in a run without the bad ones (its own
+        # streams: the same results)
+        good = [dd for dd in range(nd) if dd not in (7, 11)]
+        for dd in good[:40]:
+            a0, a1 = off2[dd], off2[dd + 1]
+            r0, r1 = off[dd], off[dd + 1]
+            assert np.array_equal(cnt[a0:a1], ref[0][r0:r1]), (batched, dd)
