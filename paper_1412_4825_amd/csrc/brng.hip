@@ -687,7 +687,12 @@ __device__ __forceinline__ void run_unit(const DescDev& D, Meta* meta, const Poo
     Meta* mp = meta + D.unit_base + local;
     if constexpr (MODEL == M_TRIANGLE) unit_triangle(D, mp, P, local, lds);
     if constexpr (MODEL == M_NORMEXP) unit_normexp(D, mp, P, local, lds);
-    if constexpr (MODEL == M_GAMMA) unit_gamma(D, mp, P, local, lds);
+    if constexpr (MODEL == M_GAMMA) {
+        if (D.sums)  // the sums path, kept out of the rounds of runs without
+            unit_gamma<true>(D, mp, P, local, lds);
+        else
+            unit_gamma<false>(D, mp, P, local, lds);
+    }
     if constexpr (MODEL == M_LDA) unit_lda(D, mp, P, local, lds);
     if constexpr (MODEL == M_EXPCHAIN) unit_expchain(D, mp, P, local, lds);
 }

@@ -501,6 +501,7 @@ constexpr int GAMMA_LDS_BYTES = GammaRN::LDS_BYTES + GammaRE::LDS_BYTES + GAMMA_
 static_assert(GammaRN::CH >= 64 * EPOCH_ROUNDS && GammaRE::CH >= 128 * EPOCH_ROUNDS,
               "gamma rings must cover an epoch");
 
+template <bool SUMS>
 __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t local,
                            unsigned char* lds) {
     const uint32_t lane = lane_id();
@@ -517,7 +518,7 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
     re.open(m, P.e + (size_t)gu * P.W[KIND_E], P.W[KIND_E],
             reinterpret_cast<float*>(lds + GammaRN::LDS_BYTES));
     float* st = reinterpret_cast<float*>(D.state);
-    ChainSrc src;
+    ChainSrc<SUMS> src;
     // steps already done by this slot (round-sliced runs continue a chain
     // mid-way; the round sequence is the same as in one straight run)
     const int32_t t0 = (D.progress && in) ? D.progress[slot] : 0;
@@ -528,16 +529,15 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
     src.col = src.trace ? reinterpret_cast<float*>(D.trace) + slot : nullptr;
     src.stride = D.stride;
     src.ring = reinterpret_cast<float*>(lds + GammaRN::LDS_BYTES + GammaRE::LDS_BYTES) + lane;
-    src.sums = D.sums != nullptr;
     src.s1 = src.s2 = 0.0;
-    if (src.sums && in) {
+    if (SUMS && in) {
         src.s1 = D.sums[chain];
         src.s2 = D.sums[(size_t)D.n_chains + chain];
     }
     const uint32_t smax = (uint32_t)min(D.max_steps, 1 << 24);
     gamma_rounds<true>(rn, re, src, D.max_rounds > 0 ? (uint32_t)D.max_rounds : 4096u + 64u * smax);
     if (in) st[chain] = src.alpha;
-    if (src.sums && in) {
+    if (SUMS && in) {
         D.sums[chain] = src.s1;
         D.sums[(size_t)D.n_chains + chain] = src.s2;
     }
@@ -656,7 +656,9 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
         const float S = K <= 16 ? __builtin_bit_cast(float, __builtin_amdgcn_readlane(
                                       __builtin_bit_cast(int32_t, group_sum<16>(y[0])), 0))
                                 : wave_sum(part);
-        // theta, quantised weights and their prefix sums
+        // theta (each gamma times the correctly rounded 1 / S), quantised
+        // weights and their prefix sums
+        const float inv = 1.0f / S;
         int32_t carry = 0;
         float th[4];
 #pragma unroll
@@ -664,7 +666,7 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
             const int k = b * 64 + (int)lane;
             if (b * 64 < K) {
                 const bool in = comp_in(K, b, lane);
-                th[b] = (in && S > 0.0f) ? y[b] / S : 0.0f;
+                th[b] = (in && S > 0.0f) ? y[b] * inv : 0.0f;
                 const int32_t q = in ? (int32_t)rintf(th[b] * 16777216.0f) : 0;
                 const int32_t inc = wave_incl_scan(q) + carry;
                 if (in) Cs[k] = inc;

@@ -228,16 +228,22 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // it.  The caller therefore stages all its readers together at fixed points
 // ("epochs", every few rounds of its loop) and issues its own global stores
 // right after them: each wait then covers only operations issued one epoch
-// earlier.  A chunk is CHV 16-byte loads per lane (CH entries); the LDS ring
-// holds two chunks and the next chunk waits in registers.  A chunk is
-// prefetched only when it lies inside the current window; otherwise the
-// window is regenerated (the blocking refill) when that chunk is staged.
-// If a call needs more than the ring holds, it stages at once (correct,
-// only slower); sized so that an epoch's worst case fits, that never happens.
+// earlier.  A chunk is CHV 16-byte blocks per lane (CH entries); the LDS ring
+// holds two chunks and the next chunk waits in registers.  A chunk inside
+// the unit's window (the bulk fill's, in HBM) is loaded from it one epoch
+// ahead; a chunk past the window is the buffer's refill, and the wave
+// generates it in registers when it is staged: the entries are the same
+// pure function of their index that a regenerated window would hold, and
+// nothing is written back (a window written to HBM only to be read back
+// once cost a quarter of the LDA kernel's time, the stores holding up the
+// next loads on the shared counter).  If a call needs more than the ring
+// holds, it stages at once (correct, only slower); sized so that an epoch's
+// worst case fits, that never happens.
 // ---------------------------------------------------------------------------
-// PAIRED: a regenerating lane computes its blocks two at a time under one key
-// schedule (fewer scalar instructions, more code and registers; it pays off
-// for a kernel with two readers, not with three).
+// PAIRED: a lane computes its blocks two at a time under one key schedule
+// (fewer scalar instructions, more code and registers; it pays off for a
+// kernel with two readers, not with three); with one block per lane per
+// chunk the second block is the next chunk's, which then waits in registers.
 template <uint32_t KIND, int CHV, bool PAIRED = false>
 struct EpochReader {
     static_assert(CHV == 1 || CHV == 2, "a chunk is one or two blocks per lane");
@@ -256,6 +262,7 @@ struct EpochReader {
     int32_t avail;  // staged - cursor (the cursor itself is staged - avail)
     uint32_t pos;   // cursor mod R: the ring index of the next entry
     bool inflight;  // pf holds chunk `staged`
+    bool ahead;     // pf holds chunk `staged`, generated with the previous one
     u32x4 pf[CHV];
 
     __device__ __forceinline__ bool in_window(uint64_t f) const {
@@ -268,8 +275,8 @@ struct EpochReader {
     }
     // Whether the ring has room for the waiting chunk.
     __device__ __forceinline__ bool room() const { return avail <= (int32_t)(R - CH); }
-    // Move chunk `staged` into the ring (needs room()).  Without a prefetched
-    // copy the window is regenerated first and the chunk read at once.
+    // Move chunk `staged` into the ring (needs room()).  Without a waiting
+    // copy the chunk is generated here.
     __device__ __forceinline__ void put() {
         const uint32_t off = (uint32_t)staged & (R - 1);
         u32x4* dst = reinterpret_cast<u32x4*>(ring + off) + lane_id();
@@ -279,48 +286,26 @@ struct EpochReader {
             for (int j = 0; j < CHV; ++j) dst[j * 64] = pf[j];
             head = pf[0];
         } else {
-            // Regenerate the window from `staged`.  The chunk's own blocks
-            // are the first CHV blocks each lane generates, so they go to the
-            // ring straight from registers.  Later loads of the window are
-            // issued after these stores by the same wave, which sees them (one
-            // vector L1 per CU, operations performed in order); the fence only
-            // keeps the compiler from moving memory operations across.
             const uint32_t lane = lane_id();
             const uint64_t b0 = staged / EPB;
-            uint4* wd = reinterpret_cast<uint4*>(win);
             u32x4 tmp[CHV];
             if constexpr (PAIRED) {
-                // blocks two at a time; a window has a whole number of
-                // 64-block groups, at least two
-                const uint32_t ng = W / EPB / 64;
                 uint4 va, vb;
                 gen_block2<KIND, true>(key, b0 + lane, b0 + 64 + lane, va, vb);
-                wd[lane] = va;
-                wd[64 + lane] = vb;
                 tmp[0] = u32x4{va.x, va.y, va.z, va.w};
-                if constexpr (CHV == 2) tmp[1] = u32x4{vb.x, vb.y, vb.z, vb.w};
-                uint32_t g = 2;
-                for (; g + 1 < ng; g += 2) {
-                    gen_block2<KIND, true>(key, b0 + g * 64 + lane, b0 + (g + 1) * 64 + lane, va,
-                                           vb);
-                    wd[g * 64 + lane] = va;
-                    wd[(g + 1) * 64 + lane] = vb;
+                if constexpr (CHV == 2) {
+                    tmp[1] = u32x4{vb.x, vb.y, vb.z, vb.w};
+                } else {
+                    pf[0] = u32x4{vb.x, vb.y, vb.z, vb.w};  // the next chunk
+                    ahead = true;
                 }
-                if (g < ng) wd[g * 64 + lane] = gen_block<KIND, true>(key, b0 + g * 64 + lane);
             } else {
-                const uint32_t nblk = W / EPB;
 #pragma unroll
                 for (int j = 0; j < CHV; ++j) {
                     const uint4 v = gen_block<KIND, true>(key, b0 + (uint32_t)(j * 64) + lane);
-                    wd[j * 64 + lane] = v;
                     tmp[j] = u32x4{v.x, v.y, v.z, v.w};
                 }
-                for (uint32_t b = (uint32_t)(CHV * 64) + lane; b < nblk; b += 64)
-                    wd[b] = gen_block<KIND, true>(key, b0 + b);
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            wbase = staged;
-            wlen = W;
 #pragma unroll
             for (int j = 0; j < CHV; ++j) dst[j * 64] = tmp[j];
             head = tmp[0];
@@ -331,12 +316,16 @@ struct EpochReader {
         staged += CH;
         avail += (int32_t)CH;
     }
-    // Prefetch chunk `staged`.  The load is issued unconditionally (outside
-    // the window it reads the window's first chunk, a value never used), so
-    // its registers are the ones put() writes out, with no copy in between.
+    // Prefetch chunk `staged` when it lies inside the window (or keep the
+    // one generated ahead).
     __device__ __forceinline__ void prefetch() {
+        if (ahead) {
+            ahead = false;
+            inflight = true;
+            return;
+        }
         inflight = in_window(staged);
-        load(inflight ? staged : wbase);
+        if (inflight) load(staged);
     }
     __device__ __forceinline__ void stage() {
         put();
@@ -356,6 +345,7 @@ struct EpochReader {
         staged = cur & ~(uint64_t)(CH - 1);
         avail = -(int32_t)(cur - staged);
         pos = (uint32_t)cur & (R - 1);
+        ahead = false;
         prefetch();
         stage();
     }

@@ -63,8 +63,11 @@ __device__ __forceinline__ MtStat mt_stat(float d, float y, float v0, float e) {
     const float y2 = y * y;
     const float y3 = y2 * y;
     const float q = (3.0f * l - 3.0f * y) + (1.5f * y2 - y3);
-    const float mag = e + d * (3.0f * fabsf(l) + 3.0f * fabsf(y) + 1.5f * y2 + fabsf(y3) +
-                               3.0f * y2 * y2 * __builtin_amdgcn_rcpf(v0));
+    // magnitudes of the terms: 3|l| + 3|y| + 1.5 y^2 + |y|^3 (Horner in |y|)
+    // and the effect of y's own rounding, 3 y^4 / v0
+    const float ay = fabsf(y);
+    const float poly = fmaf(ay, fmaf(ay, ay + 1.5f, 3.0f), 3.0f * fabsf(l));
+    const float mag = e + d * fmaf(3.0f * y2, y2 * __builtin_amdgcn_rcpf(v0), poly);
     return MtStat{e + d * q, 2e-6f * mag};
 }
 
@@ -288,6 +291,7 @@ __device__ __forceinline__ int32_t wave_minmax(int32_t v) {
 // the lowest rows are stored partially (the lanes that have written them) and
 // a lane that later completes such a row stores its value directly.
 constexpr int32_t TRACE_ROWS = 16;
+template <bool SUMS>
 struct ChainSrc {
     int32_t t, L;
     int32_t t0;      // the lane's first step in this launch
@@ -297,8 +301,8 @@ struct ChainSrc {
     int64_t stride;  // trace elements between steps
     float* ring;     // LDS, TRACE_ROWS x 64 values; this lane's column
     int32_t f;       // wave-uniform: rows below f have been stored
-    bool sums;       // wave-uniform: keep the sum and sum of squares
-    double s1, s2;   // of this lane's draws, in step order
+    double s1, s2;   // SUMS: the sum and sum of squares of this lane's
+                     // draws, in step order
     __device__ __forceinline__ float first() {
         t0 = t;
         f = wave_minmax<false>(t < L ? t : INT32_MAX);
@@ -319,10 +323,12 @@ struct ChainSrc {
             if (!behind) ring[(t & (TRACE_ROWS - 1)) * 64] = gv;
             if (behind && done && trace) col[(int64_t)t * stride] = gv;
         }
-        if (sums && done) {
-            const double d = (double)gv;
-            s1 += d;
-            s2 = fma(d, d, s2);  // d * d is exact: the same as a rounded product
+        if constexpr (SUMS) {
+            if (done) {
+                const double d = (double)gv;
+                s1 += d;
+                s2 = fma(d, d, s2);  // d * d is exact: the same as a rounded product
+            }
         }
         alpha = done ? 0.1f + gv : alpha;
         t += done ? 1 : 0;
