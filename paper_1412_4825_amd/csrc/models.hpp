@@ -554,8 +554,7 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
 constexpr int LDA_KMAX = 256;
 using LdaRN = EpochReader<KIND_N, 1>;
 using LdaRE = EpochReader<KIND_E, 1>;
-using LdaRU = EpochReader<KIND_U, 1>;
-constexpr int LDA_RINGS_BYTES = LdaRN::LDS_BYTES + LdaRE::LDS_BYTES + LdaRU::LDS_BYTES;
+constexpr int LDA_RINGS_BYTES = LdaRN::LDS_BYTES + LdaRE::LDS_BYTES;
 // Epoch points every two rounds keep the one-chunk rings covered.
 constexpr uint32_t LDA_EPOCH = 2;
 static_assert(LdaRN::CH >= 64 * LDA_EPOCH && LdaRE::CH >= 128 * LDA_EPOCH,
@@ -593,12 +592,11 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
     const int kexp = K > 1 ? 31 - (int)__builtin_clz((uint32_t)(K - 1)) : -1;
     LdaRN rn;
     LdaRE re;
-    LdaRU ru;
+
     rn.open(m, P.n + (size_t)gu * P.W[KIND_N], P.W[KIND_N], reinterpret_cast<float*>(lds));
     re.open(m, P.e + (size_t)gu * P.W[KIND_E], P.W[KIND_E],
             reinterpret_cast<float*>(lds + LdaRN::LDS_BYTES));
-    ru.open(m, P.u + (size_t)gu * P.W[KIND_U], P.W[KIND_U],
-            reinterpret_cast<float*>(lds + LdaRN::LDS_BYTES + LdaRE::LDS_BYTES));
+    uint64_t ucur = m.cur[KIND_U];  // the U stream's cursor (entries come from registers)
     int32_t* Cs = reinterpret_cast<int32_t*>(lds + LDA_RINGS_BYTES);  // 256 bin ends
     int32_t* cnt = Cs + LDA_KMAX;                                      // 256 counts
     float* yv = reinterpret_cast<float*>(cnt + LDA_KMAX);              // 256 gammas
@@ -700,38 +698,47 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // Token u -> t = (j Q) >> 23 with j = (u 2^24 - 1) / 2, then the
-        // first k with t < C_k, i.e. the number of k with C_k <= t (the C_k
-        // do not decrease and C_{K-1} = Q > t): binary lifting over the
-        // power-of-two steps 2^e, e = kexp .. 0, the same count of steps in
-        // every lane.  The steps are unrolled from the largest possible one
-        // (2^7; K <= 256) and those above kstep skipped as a wave, so each
-        // probe is an LDS read at a fixed offset from the position reached
-        // (at most 2 kstep - 2 <= 254).  Calls are taken two at a time (in
-        // call order) so that the two searches' LDS reads overlap.
-        for (int i0 = 0; i0 < ntok; i0 += 128) {
-            const bool act0 = i0 + (int)lane < ntok;
-            const bool act1 = i0 + 64 + (int)lane < ntok;
-            const float u0 = ru.take(act0);
-            const float u1 = ru.take(act1);
-            const uint32_t t0 =
-                (uint32_t)(((uint64_t)((((uint32_t)(u0 * 16777216.0f)) - 1u) >> 1) * (uint32_t)Q) >> 23);
-            const uint32_t t1 =
-                (uint32_t)(((uint64_t)((((uint32_t)(u1 * 16777216.0f)) - 1u) >> 1) * (uint32_t)Q) >> 23);
-            int32_t* p0 = Cs;  // bin end of the position reached
-            int32_t* p1 = Cs;
-            static_for<0, 8>([&](auto jc) {
-                constexpr int e = 7 - decltype(jc)::value;
-                if (e <= kexp) {
-                    const uint32_t c0 = (uint32_t)p0[(1 << e) - 1];
-                    const uint32_t c1 = (uint32_t)p1[(1 << e) - 1];
-                    p0 += c0 <= t0 ? (1 << e) : 0;
-                    p1 += c1 <= t1 ? (1 << e) : 0;
+        // The sweep's uniforms are the document's entries [cu, cu + ntok) of
+        // its U stream; lane l generates Philox blocks blo + l, blo + l + 64,
+        // ... in registers (the buffer's refill; the bulk-filled window is
+        // not read) and bins each block's four entries that fall in the
+        // range.  Entry u = (2 (w >> 9) + 1) 2^-24 gives j = (u 2^24 - 1) / 2
+        // = w >> 9 and t = (j Q) >> 23; its bin is the number of k with
+        // C_k <= t (the C_k do not decrease and C_{K-1} = Q > t), found by
+        // binary lifting over the power-of-two steps 2^e, e = kexp .. 0, the
+        // same count of steps in every lane.  The steps are unrolled from the
+        // largest possible one (2^7; K <= 256) and those above kstep skipped
+        // as a wave, so each probe is an LDS read at a fixed offset from the
+        // position reached (at most 2 kstep - 2 <= 254); a lane's four
+        // searches are independent, so their LDS reads overlap.
+        {
+            const uint64_t cu = ucur;
+            const uint64_t blo = cu / 4, bhi = (cu + (uint32_t)max(ntok, 0) + 3) / 4;
+            const Key ku = meta_key(m);
+            for (uint64_t r0 = blo; r0 < bhi; r0 += 64) {
+                const uint64_t b = r0 + lane;
+                const uint4 w = block_words<true>(ku, KIND_U, b);
+                const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+                int32_t* p[4] = {Cs, Cs, Cs, Cs};  // bin end of the position reached
+                uint32_t t[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) t[i] = (uint32_t)(((uint64_t)(wv[i] >> 9) * (uint32_t)Q) >> 23);
+                static_for<0, 8>([&](auto jc) {
+                    constexpr int e = 7 - decltype(jc)::value;
+                    if (e <= kexp) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            p[i] += (uint32_t)p[i][(1 << e) - 1] <= t[i] ? (1 << e) : 0;
+                    }
+                });
+                // the counts sit LDA_KMAX entries past the bin ends
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint64_t e = 4 * b + (uint64_t)i;
+                    if (b < bhi && e >= cu && e < cu + (uint32_t)ntok) atomicAdd(p[i] + LDA_KMAX, 1);
                 }
-            });
-            // the counts sit LDA_KMAX entries past the bin ends
-            if (act0) atomicAdd(p0 + LDA_KMAX, 1);
-            if (act1) atomicAdd(p1 + LDA_KMAX, 1);
+            }
+            ucur = cu + (uint32_t)max(ntok, 0);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -760,7 +767,11 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
     }
     rn.close(*mp);
     re.close(*mp);
-    ru.close(*mp);
+    if (lane == 0) {  // the U window record stays as it was opened
+        mp->cur[KIND_U] = ucur;
+        mp->wbase[KIND_U] = m.wbase[KIND_U];
+        mp->wlen[KIND_U] = m.wlen[KIND_U];
+    }
     store_key(mp, m);
 }
 
