@@ -20,6 +20,10 @@
 
 #include "../../include/brng.h"
 #include "lda_packed.hpp"
+
+#ifndef LDA_WAVES_PER_EU
+#define LDA_WAVES_PER_EU 5
+#endif
 #include "models.hpp"
 #include "slots.hpp"
 
@@ -805,8 +809,8 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_lda_plan(DescDev D, int32_t* p
 // plan lays them out: groups of small documents first, then one document
 // per wave).
 template <int MODEL>
-__global__ __launch_bounds__(512) void k_gibbs(DescDev D, Meta* meta, Pools P,
-                                               const int32_t* plan) {
+__device__ __forceinline__ void gibbs_body(const DescDev& D, Meta* meta, const Pools& P,
+                                           const int32_t* plan) {
     extern __shared__ __align__(16) unsigned char lds_all[];
     const uint32_t w = wave_in_block();
     const uint32_t local = blockIdx.x * (blockDim.x >> 6) + w;
@@ -836,6 +840,20 @@ __global__ __launch_bounds__(512) void k_gibbs(DescDev D, Meta* meta, Pools P,
     } else {
         run_unit<MODEL>(D, meta, P, local, lds);
     }
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(512) void k_gibbs(DescDev D, Meta* meta, Pools P,
+                                               const int32_t* plan) {
+    gibbs_body<MODEL>(D, meta, P, plan);
+}
+
+// The LDA kernel is held to five waves per SIMD (at most 102 registers):
+// its LDS allows that many, and its rounds gain from the extra latency
+// hiding more than they lose to the tighter register budget.
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(LDA_WAVES_PER_EU)))
+void k_gibbs_lda(DescDev D, Meta* meta, Pools P, const int32_t* plan) {
+    gibbs_body<M_LDA>(D, meta, P, plan);
 }
 
 // Batched and served form: the units of several requests in one launch.  A
@@ -1471,7 +1489,14 @@ static brng_status launch_gibbs(hipStream_t stream, int wpb_req, const DescDev& 
         case M_TRIANGLE: BRNG_LAUNCH_GIBBS(M_TRIANGLE); break;
         case M_NORMEXP: BRNG_LAUNCH_GIBBS(M_NORMEXP); break;
         case M_GAMMA: BRNG_LAUNCH_GIBBS(M_GAMMA); break;
-        case M_LDA: BRNG_LAUNCH_GIBBS(M_LDA); break;
+        case M_LDA:
+            if (ts)
+                hipExtLaunchKernelGGL(k_gibbs_lda, grid, block, (uint32_t)lds, stream, ts, te, 0u,
+                                      D, meta, P, (const int32_t*)plan);
+            else
+                hipLaunchKernelGGL(k_gibbs_lda, grid, block, lds, stream, D, meta, P,
+                                   (const int32_t*)plan);
+            break;
         default: BRNG_LAUNCH_GIBBS(M_EXPCHAIN); break;
     }
 #undef BRNG_LAUNCH_GIBBS
