@@ -380,7 +380,7 @@ def setup_lda_full(torch, b, args):
     per token.  A step is one call of `sweeps_per_step` sweeps."""
     from paper_1412_4825_amd import workloads
     nd = args.chains or 16384
-    K, V = 64, 4096
+    K, V = 64, args.lda_vocab
     sweeps = args.chain_steps or 5
     alpha, beta = 0.1, 0.05
     c = workloads.lda_corpus(n_docs=nd, n_topics=K, n_vocab=V, seed=args.seed)
@@ -883,6 +883,8 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--cpu-units", type=int, default=0)
     ap.add_argument("--oaat-steps", type=int, default=100)
+    ap.add_argument("--lda-vocab", type=int, default=4096,
+                    help="lda_full: vocabulary size (64 topics)")
     ap.add_argument("--no-oaat", action="store_true",
                     help="skip the one-launch-per-step comparison (gamma)")
     ap.add_argument("--served-requests", type=int, default=1000)

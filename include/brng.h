@@ -202,8 +202,12 @@ brng_status brng_step_dirichlet(brng_ctx *ctx, const int32_t *d_offsets,
  * [d_doc_offsets[d], d_doc_offsets[d+1]) clamped to [0, n_tokens); a word
  * id outside [0, n_vocab) gets z = -1, no count, and still takes its
  * uniform.  All arrays are caller-owned device memory.
- * Limits: 1 <= n_topics <= 64, 1 <= n_vocab <= 4096, alpha, beta > 0.
+ * Limits: 1 <= n_topics <= 64 (the token step holds one topic per lane),
+ * 1 <= n_vocab <= BRNG_LDAF_VMAX, alpha, beta > 0.  A topic's Dirichlet over
+ * the vocabulary is drawn by one wave (n_vocab / 64 gamma rounds per sweep),
+ * beside the documents' Dirichlets.
  * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_UNSUPPORTED, BRNG_E_HIP. */
+#define BRNG_LDAF_VMAX (1 << 20)
 typedef struct {
     uint32_t n_docs;
     uint32_t n_topics;

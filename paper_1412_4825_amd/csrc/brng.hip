@@ -1370,7 +1370,8 @@ brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
     if (c->cfg.layout != BRNG_LAYOUT_ITEMS) return BRNG_E_ARG;
     if (c->cfg.prec != BRNG_F32) return BRNG_E_UNSUPPORTED;
     const uint32_t D = d->n_docs, K = d->n_topics, V = d->n_vocab;
-    if (D == 0 || K < 1 || K > 64 || V < 1 || V > 4096 || d->n_tokens < 0) return BRNG_E_ARG;
+    if (D == 0 || K < 1 || K > 64 || V < 1 || V > BRNG_LDAF_VMAX || d->n_tokens < 0)
+        return BRNG_E_ARG;
     if ((uint64_t)K + D > c->n_units) return BRNG_E_ARG;
     if (!(d->alpha > 0.0f) || !(d->beta > 0.0f) || !std::isfinite(d->alpha) ||
         !std::isfinite(d->beta))

@@ -12,6 +12,7 @@ sweep replayed by the oracle from the device's own state:
 
 Cases: ragged documents (empty ones, up to a few hundred tokens) with a few
 word ids outside the vocabulary, topic counts 1, 13 and 64 (the limit), a
+vocabulary of 30,000 words, a
 launch of all sweeps at once equal to the sweep-by-sweep calls, and window
 length and workgroup size changing nothing."""
 import numpy as np
@@ -63,7 +64,7 @@ def _bufs(dev, D, K, V, words, z0):
 
 
 @pytest.mark.parametrize("K,V,D,mean_len", [(13, 300, 40, 60.0), (64, 512, 24, 120.0),
-                                            (1, 50, 10, 30.0)])
+                                            (1, 50, 10, 30.0), (64, 30000, 60, 150.0)])
 def test_lda_full_sweep_replay(dev, K, V, D, mean_len):
     import torch
     b = _b()
@@ -157,7 +158,7 @@ def test_lda_full_rejects_bad_arguments(dev):
                         stream=torch.cuda.current_stream())
     buf = _bufs(dev, D, K, V, words, z0)
     try:
-        for k, v, a in ((65, V, 0.1), (K, 4097, 0.1), (K, V, 0.0), (K + 1, V, 0.1)):
+        for k, v, a in ((65, V, 0.1), (K, (1 << 20) + 1, 0.1), (K, V, 0.0), (K + 1, V, 0.1)):
             # K + 1 topics with D documents need more units than the context has
             with pytest.raises(b.BrngError):
                 b.brng_run_lda_full(ctx, k, v, 1, a, 0.05, _t(off, dev), buf["words"], buf["z"],
