@@ -369,8 +369,8 @@ def _cpu_lda_full(a):
     seed, K, V, off, words, z0, alpha, beta, docs = a
     import oracle
     t = time.perf_counter()
-    oracle.lda_full_sweep(seed, oracle.new_cursors(K + off.size - 1), K, V, alpha, beta, off,
-                          words, z0, docs=docs)
+    cur = oracle.new_cursors(oracle.lda_full_units(K, V, off.size - 1))
+    oracle.lda_full_sweep(seed, cur, K, V, alpha, beta, off, words, z0, docs=docs)
     return time.perf_counter() - t
 
 

@@ -88,6 +88,8 @@ def _declare(L):
     L.or_step_multinomial.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p, _i32p, _i32p,
                                       _dp, _i32p, _dp]
     L.or_step_dirichlet.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _u64p, _i32p, _dp, _dp, _dp, _dp]
+    L.or_dirichlet_blocks.argtypes = [C.c_uint64, C.c_uint32, C.c_int32, C.c_int32, _u64p, _dp, _dp, _dp,
+                                      _dp]
     L.or_multinomial.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _u64p, _i32p, _i32p, _dp, _i32p]
     L.or_triangle.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _dp, _dp, _u64p, _dp, _dp, _dp, _dp]
     L.or_normexp.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, _dp, _u64p, _dp, _dp, _dp, _dp]
@@ -275,6 +277,20 @@ def step_dirichlet(seed, cursors, offsets, alpha, unit0=0):
     m = np.zeros(n_items)
     lib().or_step_dirichlet(seed, unit0, n_items, _p(cursors, _u64p), _p(offsets, _i32p), _p(alpha, _dp),
                             _p(out, _dp), _p(t, _dp), _p(m, _dp))
+    return out, t, m
+
+
+def dirichlet_blocks(seed, cursors, alpha, tb, unit0=0):
+    """One Dirichlet(alpha) whose components are drawn in blocks of tb, block
+    j from unit unit0 + j (cursors[j], advanced in place), normalised by the
+    sum of all gammas.  Returns (theta, tol, margin per block)."""
+    alpha = _d(alpha)
+    K = alpha.size
+    nb = -(-K // tb)
+    assert cursors.shape[0] >= nb
+    out, t, m = np.zeros(K), np.zeros(K), np.zeros(nb)
+    lib().or_dirichlet_blocks(seed, unit0, K, tb, _p(cursors, _u64p), _p(alpha, _dp), _p(out, _dp),
+                              _p(t, _dp), _p(m, _dp))
     return out, t, m
 
 
@@ -514,40 +530,55 @@ def lda_full_token_topic(theta_d, phi, w, u):
     return int(np.searchsorted(c, t, side="right"))
 
 
+LDA_FULL_VBLOCK = 4096  # words per topic block: one unit, one gamma stream
+
+
+def lda_full_units(K, V, D, vblock=LDA_FULL_VBLOCK):
+    """Units of a full LDA corpus: topic k's word block j is unit k nb + j
+    (nb = ceil(V / vblock) blocks per topic), document d is unit K nb + d."""
+    return K * (-(-V // vblock)) + D
+
+
 def lda_full_sweep(seed, cursors, K, V, alpha, beta, doc_offsets, words, z_in,
-                   theta32=None, phi32=None, docs=None):
+                   theta32=None, phi32=None, docs=None, vblock=LDA_FULL_VBLOCK):
     """One sweep from assignment z_in.  Topic k draws phi_k ~ Dir(beta + n_k.)
-    from its pools, document d draws theta_d ~ Dir(alpha + n_d.) from its
-    pools, then takes one uniform per token in token order and draws the
-    token's topic by lda_full_token_topic.  The shapes beta + n and alpha + n
-    are formed in fp32, as the sampler receives them.  The token step uses
-    theta32 / phi32 when given (the device's fp32 values, for replay), else
-    this sweep's own values rounded to fp32.  cursors ([K + D][4], uint64)
-    advance in place.  Returns the fp64 phi and theta with their tolerances
-    and decision margins, the new assignment and its counts.  With `docs`
-    (document indices) only those documents draw (every topic still does):
-    the other documents' theta rows are NaN, their tokens keep z_in, and no
-    counts are returned."""
+    with the gammas of words [j vblock, (j + 1) vblock) from unit k nb + j
+    (dirichlet_blocks), document d draws theta_d ~ Dir(alpha + n_d.) from
+    unit K nb + d, then takes one uniform per token in token order and draws
+    the token's topic by lda_full_token_topic.  The shapes beta + n and
+    alpha + n are formed in fp32, as the sampler receives them.  The token
+    step uses theta32 / phi32 when given (the device's fp32 values, for
+    replay), else this sweep's own values rounded to fp32.  cursors
+    ([lda_full_units][4], uint64) advance in place.  Returns the fp64 phi and
+    theta with their tolerances and decision margins (phi_margin per topic:
+    the smallest of its blocks'), the new assignment and its counts.  With
+    `docs` (document indices) only those documents draw (every topic still
+    does): the other documents' theta rows are NaN, their tokens keep z_in,
+    and no counts are returned."""
     doc_offsets = np.ascontiguousarray(doc_offsets, dtype=np.int32)
     words = np.asarray(words, dtype=np.int64)
     D = doc_offsets.size - 1
+    nb = -(-V // vblock)
     ndk, nkw = lda_full_counts(K, V, doc_offsets, words, z_in)
-    a_phi = (np.float32(beta) + nkw.astype(np.float32)).astype(np.float32).ravel()
+    a_phi = (np.float32(beta) + nkw.astype(np.float32)).astype(np.float32)
     a_th = (np.float32(alpha) + ndk.astype(np.float32)).astype(np.float32).ravel()
-    off_phi = (np.arange(K + 1, dtype=np.int32) * V).astype(np.int32)
     off_th = (np.arange(D + 1, dtype=np.int32) * K).astype(np.int32)
-    ct = cursors[:K]
-    cd = cursors[K:]
-    phi, phi_t, phi_m = step_dirichlet(seed, ct, off_phi, a_phi, unit0=0)
+    phi, phi_t, phi_m = np.zeros((K, V)), np.zeros((K, V)), np.zeros(K)
+    for k in range(K):
+        ck = cursors[k * nb:(k + 1) * nb]  # a view: advanced in place
+        phi[k], phi_t[k], mb = dirichlet_blocks(seed, ck, a_phi[k], vblock, unit0=k * nb)
+        phi_m[k] = mb.min()
+    cd = cursors[K * nb:]
+    du = K * nb  # unit of document 0
     if docs is None:
-        th, th_t, th_m = step_dirichlet(seed, cd, off_th, a_th, unit0=K)
+        th, th_t, th_m = step_dirichlet(seed, cd, off_th, a_th, unit0=du)
         todo = range(D)
     else:
         th, th_t, th_m = np.full(D * K, np.nan), np.full(D * K, np.nan), np.full(D, np.nan)
         for d in docs:
             c1 = cd[d:d + 1]  # this document's cursors, advanced in place
             o1 = np.array([0, K], dtype=np.int32)
-            r1 = step_dirichlet(seed, c1, o1, a_th[d * K:(d + 1) * K], unit0=K + int(d))
+            r1 = step_dirichlet(seed, c1, o1, a_th[d * K:(d + 1) * K], unit0=du + int(d))
             th[d * K:(d + 1) * K], th_t[d * K:(d + 1) * K], th_m[d] = r1[0], r1[1], r1[2][0]
         todo = docs
     phi_f = (phi.astype(np.float32) if phi32 is None else np.asarray(phi32, np.float32)).reshape(K, V)
@@ -558,7 +589,7 @@ def lda_full_sweep(seed, cursors, K, V, alpha, beta, doc_offsets, words, z_in,
         a, b = int(doc_offsets[d]), int(doc_offsets[d + 1])
         if b == a:
             continue
-        u = entries(seed, K + d, KIND_U, int(cd[d, KIND_U]), b - a)
+        u = entries(seed, du + d, KIND_U, int(cd[d, KIND_U]), b - a)
         cd[d, KIND_U] += np.uint64(b - a)
         for i in range(a, b):
             z[i] = lda_full_token_topic(th_f[d], phi_f, int(words[i]), u[i - a])

@@ -600,10 +600,9 @@ static void comps_done(gsrc_t *g, int k, const gdraw_t *r)
         c->mmin = r->margin;
 }
 
-/* Draw theta for one item; y/ytol are scratch of length K. Returns the
- * smallest decision margin. tol: bound on |gpu theta - oracle theta|. */
-static double dirichlet_item(stream_t *s, int K, const double *alpha,
-                             double *theta, double *tol, double *y, double *ytol)
+/* The K gammas y_k ~ Gamma(alpha_k, 1) of one unit, with their tolerances;
+ * returns the smallest decision margin. */
+static double gamma_comps(stream_t *s, int K, const double *alpha, double *y, double *ytol)
 {
     comps_t cs;
     cs.K = K;
@@ -614,7 +613,14 @@ static double dirichlet_item(stream_t *s, int K, const double *alpha,
     cs.mmin = INFINITY;
     gsrc_t src = {comps_next, comps_done, &cs};
     or_gamma_rounds(s, OR_BATCH, &src);
-    double mmin = cs.mmin;
+    return cs.mmin;
+}
+
+/* theta_k = y_k / sum y, with tol (when non-NULL) a bound on |gpu theta -
+ * oracle theta| for fp32 gammas summed in fp32. */
+static void dirichlet_normalize(int K, const double *y, const double *ytol, double *theta,
+                                double *tol)
+{
     double S = 0.0, St = 0.0;
     for (int k = 0; k < K; k++) {
         S += y[k];
@@ -632,6 +638,15 @@ static double dirichlet_item(stream_t *s, int K, const double *alpha,
                 tol[k] = dmax(tol[k], 0x1p-126 / (S > 0.0 ? S : 1.0));
         }
     }
+}
+
+/* Draw theta for one item; y/ytol are scratch of length K. Returns the
+ * smallest decision margin. tol: bound on |gpu theta - oracle theta|. */
+static double dirichlet_item(stream_t *s, int K, const double *alpha,
+                             double *theta, double *tol, double *y, double *ytol)
+{
+    const double mmin = gamma_comps(s, K, alpha, y, ytol);
+    dirichlet_normalize(K, y, ytol, theta, tol);
     return mmin;
 }
 
@@ -1116,6 +1131,30 @@ void or_step_dirichlet(uint64_t seed, uint32_t unit0, uint32_t n_items, uint64_t
         if (margin)
             margin[i] = m;
     }
+    free(y);
+    free(yt);
+}
+
+/* One Dirichlet(alpha_0 .. alpha_{K-1}) whose gammas come from several units:
+ * components [j tb, min(K, (j+1) tb)) are block j, drawn from unit unit0 + j
+ * (cursors + 4 j) exactly as a K = tb item of that unit would draw them, and
+ * theta_k = y_k / (sum of all K gammas).  A gamma's law does not depend on
+ * which stream feeds it, so this is the same distribution as one item's
+ * draw; with tb >= K it is that draw.  margin[j]: block j's smallest margin. */
+void or_dirichlet_blocks(uint64_t seed, uint32_t unit0, int32_t K, int32_t tb, uint64_t *cursors,
+                         const double *alpha, double *out, double *tol, double *margin)
+{
+    double *y = (double *)malloc(sizeof(double) * (size_t)(K + 1));
+    double *yt = (double *)malloc(sizeof(double) * (size_t)(K + 1));
+    const int32_t nb = (K + tb - 1) / tb;
+    for (int32_t j = 0; j < nb; j++) {
+        const int32_t lo = j * tb, kb = (K - lo < tb) ? K - lo : tb;
+        stream_t s = {seed, unit0 + (uint32_t)j, cursors + 4 * (size_t)j};
+        const double m = gamma_comps(&s, kb, alpha + lo, y + lo, yt + lo);
+        if (margin)
+            margin[j] = m;
+    }
+    dirichlet_normalize(K, y, yt, out, tol);
     free(y);
     free(yt);
 }

@@ -124,21 +124,24 @@ def test_counts_and_cursors():
     assert np.allclose(r["theta"].sum(axis=1), 1.0)
 
 
-def test_dirichlet_shapes_are_prior_plus_counts():
+@pytest.mark.parametrize("vblock", [oracle.LDA_FULL_VBLOCK, 4])
+def test_dirichlet_shapes_are_prior_plus_counts(vblock):
+    """With vblock 4 each topic's six words are two blocks of two units: the
+    means still follow the whole topic's counts."""
     rng = np.random.default_rng(4)
     K, V, D = 3, 6, 4
     alpha, beta = 0.3, 0.2
     off, words = _corpus(rng, D, V, 15, 25)
     z0 = rng.integers(0, K, size=words.size).astype(np.int32)
     ndk, nkw = oracle.lda_full_counts(K, V, off, words, z0)
-    cur = oracle.new_cursors(K + D)
+    cur = oracle.new_cursors(oracle.lda_full_units(K, V, D, vblock))
     n = 3000
     phis = np.zeros((n, K, V))
     ths = np.zeros((n, D, K))
     for s in range(n):
         # the assignment is reset each time: the shapes stay beta + n_kw and
         # alpha + n_dk while the cursors move on
-        r = oracle.lda_full_sweep(17, cur, K, V, alpha, beta, off, words, z0)
+        r = oracle.lda_full_sweep(17, cur, K, V, alpha, beta, off, words, z0, vblock=vblock)
         phis[s], ths[s] = r["phi"], r["theta"]
     m_phi = (beta + nkw) / (V * beta + nkw.sum(axis=1, keepdims=True))
     m_th = (alpha + ndk) / (K * alpha + ndk.sum(axis=1, keepdims=True))
@@ -169,3 +172,42 @@ def test_document_subset_equals_full_sweep_on_those_documents():
     others = [d for d in range(D) if d not in docs]
     assert np.isnan(sub["theta"][others]).all()
     assert (cur[[K + d for d in others]] == 0).all()
+
+
+def test_vocabulary_blocks_units_and_cursors():
+    """Topics over a vocabulary of several blocks: topic k's block j is unit
+    k nb + j and document d unit K nb + d; topic blocks take no uniforms and
+    each draws its own N and E."""
+    rng = np.random.default_rng(12)
+    K, V, D, vb = 4, 23, 7, 5
+    nb = -(-V // vb)
+    assert oracle.lda_full_units(K, V, D, vb) == K * nb + D
+    off, words = _corpus(rng, D, V, 5, 30)
+    z0 = rng.integers(0, K, size=words.size).astype(np.int32)
+    cur = oracle.new_cursors(K * nb + D)
+    r = oracle.lda_full_sweep(31, cur, K, V, 0.1, 0.05, off, words, z0, vblock=vb)
+    assert (cur[:K * nb, oracle.KIND_U] == 0).all()
+    assert (cur[:, oracle.KIND_N] > 0).all() and (cur[:, oracle.KIND_E] > 0).all()
+    assert np.allclose(r["phi"].sum(axis=1), 1.0)
+    assert np.array_equal(cur[K * nb:, oracle.KIND_U], np.diff(off).astype(np.uint64))
+    # document 3 is unit K nb + 3: its theta is that unit's Dirichlet over
+    # alpha + n_3., and its tokens' topics take that unit's uniforms
+    ndk0, _ = oracle.lda_full_counts(K, V, off, words, z0)
+    d, du = 3, K * nb + 3
+    sh = (np.float32(0.1) + ndk0[d].astype(np.float32)).astype(np.float32)
+    x, _, _ = oracle.step_dirichlet(31, oracle.new_cursors(1), np.array([0, K], np.int32), sh,
+                                    unit0=du)
+    assert np.array_equal(r["theta"][d], x)
+    a, b = int(off[d]), int(off[d + 1])
+    u = oracle.entries(31, du, oracle.KIND_U, 0, b - a)
+    phi32, th32 = r["phi"].astype(np.float32), r["theta"][d].astype(np.float32)
+    zt = [oracle.lda_full_token_topic(th32, phi32, int(words[i]), u[i - a]) for i in range(a, b)]
+    assert b > a and np.array_equal(r["z"][a:b], zt)
+    # topic 2's block 1 (words 5..9) is unit 2 nb + 1: within the block the
+    # ratios of phi are that unit's Dirichlet over beta + n_kw of those words
+    _, nkw0 = oracle.lda_full_counts(K, V, off, words, z0)
+    shapes = (np.float32(0.05) + nkw0[2, vb:2 * vb].astype(np.float32)).astype(np.float32)
+    x, _, _ = oracle.step_dirichlet(31, oracle.new_cursors(1), np.array([0, vb], np.int32),
+                                    shapes, unit0=2 * nb + 1)
+    blk = r["phi"][2, vb:2 * vb]
+    np.testing.assert_allclose(blk / blk.sum(), x, rtol=1e-12)

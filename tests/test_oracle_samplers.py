@@ -228,3 +228,50 @@ def test_multinomial_counts():
     tot = counts.sum(axis=0)
     chi2, pv = stats.chisquare(tot, f_exp=p * tot.sum())
     assert pv > 1e-3
+
+
+def test_blocked_dirichlet_marginals_span_the_blocks():
+    """A Dirichlet drawn in blocks of 3 components (each block from its own
+    unit) is still Dirichlet(alpha) over all 8: the components sum to one and
+    each follows Beta(alpha_k, A - alpha_k) with A the sum over every block
+    (a normalisation within a block would put A_block there)."""
+    av = np.array([0.3, 1.0, 2.5, 7.0, 0.1, 4.0, 0.7, 1.5])
+    K, tb, draws = av.size, 3, 3000
+    nb = -(-K // tb)
+    cur = oracle.new_cursors(nb)
+    th = np.zeros((draws, K))
+    for i in range(draws):  # successive draws continue the blocks' streams
+        th[i], _, _ = oracle.dirichlet_blocks(21, cur, av, tb, unit0=5)
+    assert np.all(np.abs(th.sum(axis=1) - 1.0) < 1e-12)
+    a0 = av.sum()
+    for k in range(K):
+        assert stats.kstest(th[:, k], "beta", args=(av[k], a0 - av[k])).pvalue > 1e-3, k
+
+
+def test_blocked_dirichlet_block_streams():
+    """Block j's gammas are those a single item of unit unit0 + j draws over
+    that block's shapes: within a block the ratios of components equal the
+    ratios of that item's draw, and each block's cursors move as that item's
+    do.  With one block the draw is the single item's."""
+    av = np.array([0.5, 2.0, 1.0, 3.0, 0.2, 6.0, 1.1])
+    K, tb, unit0 = av.size, 3, 9
+    nb = -(-K // tb)
+    cur = oracle.new_cursors(nb)
+    th, tol, m = oracle.dirichlet_blocks(4, cur, av, tb, unit0=unit0)
+    assert m.shape == (nb,)
+    for j in range(nb):
+        lo, hi = j * tb, min(K, (j + 1) * tb)
+        c1 = oracle.new_cursors(1)
+        x, _, _ = oracle.step_dirichlet(4, c1, np.array([0, hi - lo], np.int32), av[lo:hi],
+                                        unit0=unit0 + j)
+        np.testing.assert_allclose(th[lo:hi] / th[lo:hi].sum(), x, rtol=1e-12)
+        assert np.array_equal(cur[j], c1[0])
+    # another unit's block would give other values
+    c2 = oracle.new_cursors(1)
+    x2, _, _ = oracle.step_dirichlet(4, c2, np.array([0, tb], np.int32), av[:tb], unit0=unit0 + 1)
+    assert not np.allclose(th[:tb] / th[:tb].sum(), x2)
+    # one block: the item's draw, with the same tolerances
+    c3, c4 = oracle.new_cursors(1), oracle.new_cursors(1)
+    a, ta, _ = oracle.dirichlet_blocks(4, c3, av, 64, unit0=unit0)
+    b, tbb, _ = oracle.step_dirichlet(4, c4, np.array([0, K], np.int32), av, unit0=unit0)
+    assert np.array_equal(a, b) and np.array_equal(ta, tbb) and np.array_equal(c3, c4)
