@@ -387,7 +387,9 @@ def setup_lda_full(torch, b, args):
     T = int(c["offsets"][-1])
     W = args.window or 512
     dev = torch.device("cuda:0")
-    ctx = b.brng_create(args.seed, K + nd, [W, W, W, 0], layout=b.BRNG_LAYOUT_ITEMS,
+    n_units = b.brng_lda_full_units(K, V, nd)
+    du = n_units - nd  # topic-block units first, then one unit per document
+    ctx = b.brng_create(args.seed, n_units, [W, W, W, 0], layout=b.BRNG_LAYOUT_ITEMS,
                         stream=torch.cuda.current_stream())
     toff = torch.from_numpy(c["offsets"]).to(dev)
     tw = torch.from_numpy(c["words"]).to(dev)
@@ -412,9 +414,9 @@ def setup_lda_full(torch, b, args):
 
     def kernel_bytes(delta):
         # the document kernel of one sweep: its units' consumed entries (the
-        # document units K..), written once and read once, plus theta, z,
+        # document units), written once and read once, plus theta, z,
         # n_d., the n_kw increments and the words it reads
-        ent = delta[K:, [b.BRNG_U, b.BRNG_N, b.BRNG_E]].sum() / sweeps
+        ent = delta[du:, [b.BRNG_U, b.BRNG_N, b.BRNG_E]].sum() / sweeps
         return 8.0 * ent + 4.0 * (2 * nd * K + 3 * T)
 
     def cpu(workers):

@@ -189,8 +189,13 @@ brng_status brng_step_dirichlet(brng_ctx *ctx, const int32_t *d_offsets,
  * f in [1/2, 1) (all 1 when max p = 0), and takes
  * the first k with t < q_0 + ... + q_k, t = (j Q) >> 23, Q the sum of the
  * q_k, j = (u 2^24 - 1) / 2.  Context: layout ITEMS, F32, kinds U, N, E
- * enabled, at least n_topics + n_docs items; topic k is unit k, document d
- * unit n_topics + d, and every call continues those units' streams.
+ * enabled, at least brng_lda_full_units(n_topics, n_vocab, n_docs) items.
+ * A topic's vocabulary is cut into nb = ceil(n_vocab / BRNG_LDAF_VBLOCK)
+ * blocks: the gammas of topic k's words [j BRNG_LDAF_VBLOCK,
+ * (j + 1) BRNG_LDAF_VBLOCK) come from unit k nb + j, and phi_k divides them
+ * by their sum over all blocks (the same Dirichlet: a gamma's law does not
+ * depend on the stream that feeds it); document d is unit n_topics nb + d.
+ * Every call continues those units' streams.
  * The state is the assignment d_z (int32 per token, in/out): a call first
  * recounts n_dk and n_kw from it (skipped with flags BRNG_LDAF_COUNTS_VALID,
  * when d_ndk and d_nkw already hold the counts of d_z, as a previous call
@@ -203,11 +208,17 @@ brng_status brng_step_dirichlet(brng_ctx *ctx, const int32_t *d_offsets,
  * id outside [0, n_vocab) gets z = -1, no count, and still takes its
  * uniform.  All arrays are caller-owned device memory.
  * Limits: 1 <= n_topics <= 64 (the token step holds one topic per lane),
- * 1 <= n_vocab <= BRNG_LDAF_VMAX, alpha, beta > 0.  A topic's Dirichlet over
- * the vocabulary is drawn by one wave (n_vocab / 64 gamma rounds per sweep),
- * beside the documents' Dirichlets.
- * Errors: BRNG_E_ARG, BRNG_E_KIND_DISABLED, BRNG_E_UNSUPPORTED, BRNG_E_HIP. */
+ * 1 <= n_vocab <= BRNG_LDAF_VMAX, alpha, beta > 0.  Each topic block is
+ * drawn by one wave (BRNG_LDAF_VBLOCK / 64 gamma rounds per sweep), beside
+ * the documents' Dirichlets; with more than one block per topic a second
+ * small kernel normalises phi.
+ * Errors: BRNG_E_ARG (also for too few items), BRNG_E_KIND_DISABLED,
+ * BRNG_E_UNSUPPORTED, BRNG_E_HIP. */
 #define BRNG_LDAF_VMAX (1 << 20)
+#define BRNG_LDAF_VBLOCK 4096
+/* Items a full-LDA corpus uses: n_topics ceil(n_vocab / BRNG_LDAF_VBLOCK)
+ * + n_docs (0 when n_vocab is 0). */
+uint64_t brng_lda_full_units(uint32_t n_topics, uint32_t n_vocab, uint32_t n_docs);
 typedef struct {
     uint32_t n_docs;
     uint32_t n_topics;

@@ -34,6 +34,7 @@ EXPORTS = [
     "brng_step_exp", "brng_step_gamma", "brng_step_laplace", "brng_step_weibull", "brng_step_poisson",
     "brng_step_binomial", "brng_step_multinomial",
     "brng_step_dirichlet", "brng_run_gibbs", "brng_run_gibbs_static", "brng_run_lda_full",
+    "brng_lda_full_units",
     "brng_sort_by_length", "brng_get_cursors", "brng_set_cursors", "brng_get_window",
     "brng_get_info", "brng_set_launch", "brng_time_next_launch", "brng_status_string",
     "brng_last_hip_error",
@@ -171,6 +172,8 @@ def _load():
     L.brng_run_gibbs.argtypes = [vp, C.POINTER(brng_gibbs_desc), C.c_uint32]
     L.brng_run_gibbs_static.argtypes = [C.POINTER(brng_gibbs_desc), vp, C.c_int32, vp]
     L.brng_run_lda_full.argtypes = [vp, C.POINTER(brng_lda_full_desc)]
+    L.brng_lda_full_units.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
+    L.brng_lda_full_units.restype = C.c_uint64
     L.brng_sort_by_length.argtypes = [C.c_uint32, vp, vp]
     L.brng_get_cursors.argtypes = [vp, vp]
     L.brng_set_cursors.argtypes = [vp, vp]
@@ -381,6 +384,11 @@ def brng_get_window(ctx: int, kind: int, unit: int):
 
 def brng_set_launch(ctx: int, waves_per_block: int) -> None:
     _check(_lib.brng_set_launch(ctx, waves_per_block, 0), "brng_set_launch")
+
+
+def brng_lda_full_units(n_topics: int, n_vocab: int, n_docs: int) -> int:
+    """Items (units) a full-LDA corpus of this shape uses."""
+    return int(_lib.brng_lda_full_units(n_topics, n_vocab, n_docs))
 
 
 def brng_run_lda_full(ctx: int, n_topics: int, n_vocab: int, sweeps: int, alpha: float,

@@ -533,7 +533,9 @@ __global__ __launch_bounds__(512) void k_step_dirichlet(Meta* meta, Pools P, uin
 // redraws motivate the method (Sec. 1 and its footnote).  Per sweep,
 // phi_k ~ Dir(beta + n_k.) for every topic, theta_d ~ Dir(alpha + n_d.) for
 // every document, then every token's topic z ~ Cat(theta_d,k phi_k,w).
-// Topic k is unit k, document d is unit K + d.  Token indices are clamped to
+// Topic k's words [j LDAF_VBLOCK, (j + 1) LDAF_VBLOCK) are unit k nb + j
+// (nb = ceil(V / LDAF_VBLOCK) blocks per topic), document d is unit K nb + d.
+// Token indices are clamped to
 // [0, n_tokens), so malformed offsets read nothing outside the arrays.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_zero_i32(int32_t* p, uint64_t n) {
@@ -560,60 +562,93 @@ __global__ __launch_bounds__(512) void k_ldaf_recount(uint32_t D, int K, int V,
 }
 
 // The sweep's Dirichlets in one launch, one wave (and workgroup) each: the
-// first K workgroups draw phi_k ~ Dir(beta + n_k.) (topic k), the others
-// theta_d ~ Dir(alpha + n_d.) (document d = block - K), so that the few long
-// topic draws run beside the many short document ones.  A topic's pools are
-// staged through LDS by the epoch readers of the LDA kernel (its thousands of
-// components are many sequential rounds); phi is word-major ([V][K]), so
-// that a token's K weights are one contiguous row.
+// first K nb workgroups draw the topics' gammas, workgroup k nb + j those of
+// topic k over words [j LDAF_VBLOCK, (j + 1) LDAF_VBLOCK) from unit k nb + j,
+// the others theta_d ~ Dir(alpha + n_d.) (document d = block - K nb), so that
+// the long topic draws run beside the many short document ones.  A topic
+// block's pools are staged through LDS by the epoch readers of the LDA kernel
+// (its thousands of components are many sequential rounds); phi is
+// word-major ([V][K]), so that a token's K weights are one contiguous row.
+// With one block per topic the wave also normalises phi_k; with more, each
+// block leaves its gammas in phi and their fp32 sum in psum[k nb + j], and
+// k_ldaf_phi_norm divides by the topic's total.
 constexpr int LDAF_TOPIC_LDS = LdaRN::LDS_BYTES + LdaRE::LDS_BYTES;
+constexpr int LDAF_VBLOCK = BRNG_LDAF_VBLOCK;
 __global__ __launch_bounds__(64) void k_ldaf_dirichlets(Meta* meta, Pools P, uint32_t D, int K,
-                                                        int V, float alpha, float beta,
-                                                        const int32_t* ndk, const int32_t* nkw,
-                                                        float* theta, float* phi) {
+                                                        int V, uint32_t nb, float alpha,
+                                                        float beta, const int32_t* ndk,
+                                                        const int32_t* nkw, float* theta,
+                                                        float* phi, float* psum) {
     __shared__ __align__(16) unsigned char lds[LDAF_TOPIC_LDS];
     const uint32_t blk = blockIdx.x;
-    if (blk >= (uint32_t)K) {
-        const uint32_t d = blk - (uint32_t)K;
+    const uint32_t n_topic_units = (uint32_t)K * nb;
+    if (blk >= n_topic_units) {
+        const uint32_t d = blk - n_topic_units;
         if (d >= D) return;
         dirichlet_unit(meta, P, blk, K, nullptr, ndk + (size_t)d * K, alpha,
                        theta + (size_t)d * K);
         return;
     }
-    const uint32_t k = blk;
+    const uint32_t k = blk / nb, j = blk - k * nb;
+    const int c0 = (int)j * LDAF_VBLOCK;
+    const int Vb = min(LDAF_VBLOCK, V - c0);
     const uint32_t lane = lane_id();
-    Meta m = meta[k];
+    Meta m = meta[blk];
     // the key words feed the scalar key schedule: make them provably uniform
     m.key_unit = __builtin_amdgcn_readfirstlane(m.key_unit);
     m.key_seed = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(m.key_seed >> 32)) << 32) |
                  (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)m.key_seed);
     LdaRN rn;
     LdaRE re;
-    rn.open(m, P.n + (size_t)k * P.W[KIND_N], P.W[KIND_N], reinterpret_cast<float*>(lds));
-    re.open(m, P.e + (size_t)k * P.W[KIND_E], P.W[KIND_E],
+    rn.open(m, P.n + (size_t)blk * P.W[KIND_N], P.W[KIND_N], reinterpret_cast<float*>(lds));
+    re.open(m, P.e + (size_t)blk * P.W[KIND_E], P.W[KIND_E],
             reinterpret_cast<float*>(lds + LdaRN::LDS_BYTES));
-    float* out = phi + k;
+    float* out = phi + (size_t)c0 * K + k;
     CompSrc src;
-    src.K = V;
+    src.K = Vb;
     src.alpha = nullptr;
-    src.cnt = nkw + (size_t)k * V;
+    src.cnt = nkw + (size_t)k * V + c0;
     src.base = beta;
     src.y = out;
     src.ys = K;
-    gamma_rounds<true, LDA_EPOCH>(rn, re, src, 4096u + 64u * (uint32_t)V);
+    gamma_rounds<true, LDA_EPOCH>(rn, re, src, 4096u + 64u * (uint32_t)Vb);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     float part = 0.0f;
-    for (int b0 = 0; b0 < V; b0 += 64) {
+    for (int b0 = 0; b0 < Vb; b0 += 64) {
         const int c = b0 + (int)lane;
-        if (c < V) part += out[(size_t)c * K];
+        if (c < Vb) part += out[(size_t)c * K];
     }
     const float S = wave_sum(part);
-    for (int b0 = 0; b0 < V; b0 += 64) {
-        const int c = b0 + (int)lane;
-        if (c < V) out[(size_t)c * K] = S > 0.0f ? out[(size_t)c * K] / S : 0.0f;
+    if (nb == 1) {
+        for (int b0 = 0; b0 < Vb; b0 += 64) {
+            const int c = b0 + (int)lane;
+            if (c < Vb) out[(size_t)c * K] = S > 0.0f ? out[(size_t)c * K] / S : 0.0f;
+        }
+    } else if (lane == 0) {
+        psum[blk] = S;
     }
-    rn.close(meta[k]);
-    re.close(meta[k]);
+    rn.close(meta[blk]);
+    re.close(meta[blk]);
+}
+
+// phi[w][k] /= sum over topic k's blocks of psum (in block order, fp32):
+// every workgroup first forms the K totals in LDS, then divides a
+// grid-strided share of the [V][K] array.
+__global__ __launch_bounds__(256) void k_ldaf_phi_norm(int K, int V, uint32_t nb,
+                                                       const float* psum, float* phi) {
+    __shared__ float tot[64];
+    const uint32_t t = threadIdx.x;
+    if (t < (uint32_t)K) {
+        float S = 0.0f;
+        for (uint32_t j = 0; j < nb; ++j) S += psum[t * nb + j];
+        tot[t] = S;
+    }
+    __syncthreads();
+    const uint32_t n = (uint32_t)V * (uint32_t)K;  // at most 2^26
+    for (uint32_t i = blockIdx.x * blockDim.x + t; i < n; i += gridDim.x * blockDim.x) {
+        const float S = tot[i % (uint32_t)K];
+        phi[i] = S > 0.0f ? phi[i] / S : 0.0f;
+    }
 }
 
 // One uniform per token of document d (token order; theta_d drawn by the
@@ -628,7 +663,8 @@ __global__ __launch_bounds__(64) void k_ldaf_dirichlets(Meta* meta, Pools P, uin
 // New n_d. in place (LDS counts), n_kw added atomically (zero on entry), both
 // once per group of 64 tokens.
 __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t D, int K, int V,
-                                                   const int32_t* doff, int32_t n_tokens,
+                                                   uint32_t nb, const int32_t* doff,
+                                                   int32_t n_tokens,
                                                    const int32_t* words, const float* phi,
                                                    const float* theta, int32_t* z, int32_t* ndk,
                                                    int32_t* nkw) {
@@ -636,7 +672,7 @@ __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t
     const uint32_t d = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
     if (d >= D) return;
     const uint32_t lane = lane_id();
-    const uint32_t unit = (uint32_t)K + d;
+    const uint32_t unit = (uint32_t)K * nb + d;
     const bool topic = (int)lane < K;
     int32_t* cnt = ldaf_cnt + 64 * wave_in_block();  // tokens per topic
     const float* th_row = theta + (size_t)d * K;
@@ -991,6 +1027,7 @@ struct brng_ctx {
     Meta* meta;
     SlotDev* table;  // slots of the batched form (BRNG_BATCH_MAX entries)
     int32_t* lda_plan;  // plain LDA launches: PLAN_HEAD + PLAN_LISTS n_units int32
+                        // (full LDA: the topic blocks' gamma sums)
     int wpb;
     int n_cu;
     // events for the next plain chain launch (brng_time_next_launch)
@@ -1365,6 +1402,11 @@ brng_status brng_step_dirichlet(brng_ctx* c, const int32_t* offsets, const float
 }
 
 
+uint64_t brng_lda_full_units(uint32_t n_topics, uint32_t n_vocab, uint32_t n_docs) {
+    if (n_vocab == 0) return 0;
+    return (uint64_t)n_topics * ((n_vocab + LDAF_VBLOCK - 1) / LDAF_VBLOCK) + n_docs;
+}
+
 brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
     if (!c || !d) return BRNG_E_ARG;
     if (c->cfg.layout != BRNG_LAYOUT_ITEMS) return BRNG_E_ARG;
@@ -1372,7 +1414,8 @@ brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
     const uint32_t D = d->n_docs, K = d->n_topics, V = d->n_vocab;
     if (D == 0 || K < 1 || K > 64 || V < 1 || V > BRNG_LDAF_VMAX || d->n_tokens < 0)
         return BRNG_E_ARG;
-    if ((uint64_t)K + D > c->n_units) return BRNG_E_ARG;
+    const uint32_t nb = (V + LDAF_VBLOCK - 1) / LDAF_VBLOCK;
+    if ((uint64_t)K * nb + D > c->n_units) return BRNG_E_ARG;
     if (!(d->alpha > 0.0f) || !(d->beta > 0.0f) || !std::isfinite(d->alpha) ||
         !std::isfinite(d->beta))
         return BRNG_E_ARG;
@@ -1383,6 +1426,9 @@ brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
     const Pools P = make_pools(c);
     const int wpb = c->wpb;
     const dim3 blk(64 * wpb);
+    // the topic blocks' gamma sums borrow the LDA planning buffer (at least
+    // PLAN_LISTS n_units >= K nb words; both uses are stream-ordered)
+    float* psum = reinterpret_cast<float*>(c->lda_plan);
     auto zero = [&](int32_t* p, uint64_t n) {
         const uint64_t g = std::min<uint64_t>((n + 255) / 256, 4096);
         if (g) hipLaunchKernelGGL(k_zero_i32, dim3((uint32_t)g), dim3(256), 0, c->stream, p, n);
@@ -1401,20 +1447,25 @@ brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
     hipEvent_t ts = c->t_start, te = c->t_stop;
     if (d->sweeps) c->t_start = c->t_stop = nullptr;
     for (uint32_t s = 0; s < d->sweeps; ++s) {
-        hipLaunchKernelGGL(k_ldaf_dirichlets, dim3(K + D), dim3(64), 0, c->stream, c->meta, P, D,
-                           (int)K, (int)V, d->alpha, d->beta, (const int32_t*)d->d_ndk,
-                           (const int32_t*)d->d_nkw, d->d_theta, d->d_phi);
+        hipLaunchKernelGGL(k_ldaf_dirichlets, dim3(K * nb + D), dim3(64), 0, c->stream, c->meta,
+                           P, D, (int)K, (int)V, nb, d->alpha, d->beta, (const int32_t*)d->d_ndk,
+                           (const int32_t*)d->d_nkw, d->d_theta, d->d_phi, psum);
+        if (nb > 1) {
+            const uint32_t g = std::min<uint32_t>(((uint32_t)K * V + 255) / 256, 2048u);
+            hipLaunchKernelGGL(k_ldaf_phi_norm, dim3(g), dim3(256), 0, c->stream, (int)K, (int)V,
+                               nb, (const float*)psum, d->d_phi);
+        }
         zero(d->d_nkw, (uint64_t)K * V);
         const dim3 grid((D + wpb - 1) / wpb);
         const size_t lds = (size_t)wpb * 64 * sizeof(int32_t);
         if (ts && s + 1 == d->sweeps)
             hipExtLaunchKernelGGL(k_ldaf_docs, grid, blk, (uint32_t)lds, c->stream, ts, te, 0u,
-                                  c->meta, P, D, (int)K, (int)V, d->d_doc_offsets, d->n_tokens,
+                                  c->meta, P, D, (int)K, (int)V, nb, d->d_doc_offsets, d->n_tokens,
                                   d->d_words, (const float*)d->d_phi, (const float*)d->d_theta,
                                   d->d_z, d->d_ndk, d->d_nkw);
         else
             hipLaunchKernelGGL(k_ldaf_docs, grid, blk, lds, c->stream, c->meta, P, D, (int)K,
-                               (int)V, d->d_doc_offsets, d->n_tokens, d->d_words,
+                               (int)V, nb, d->d_doc_offsets, d->n_tokens, d->d_words,
                                (const float*)d->d_phi, (const float*)d->d_theta, d->d_z, d->d_ndk,
                                d->d_nkw);
         HIPCHK(hipGetLastError());

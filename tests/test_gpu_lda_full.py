@@ -11,8 +11,9 @@ sweep replayed by the oracle from the device's own state:
 - cursors equal for every unit without such a decision.
 
 Cases: ragged documents (empty ones, up to a few hundred tokens) with a few
-word ids outside the vocabulary, topic counts 1, 13 and 64 (the limit), a
-vocabulary of 30,000 words, a
+word ids outside the vocabulary, topic counts 1, 13 and 64 (the limit),
+vocabularies of 4,097, 8,192 and 30,000 words (two, two and eight blocks of
+4,096 words per topic, each block its own unit), a
 launch of all sweeps at once equal to the sweep-by-sweep calls, and window
 length and workgroup size changing nothing."""
 import numpy as np
@@ -64,18 +65,22 @@ def _bufs(dev, D, K, V, words, z0):
 
 
 @pytest.mark.parametrize("K,V,D,mean_len", [(13, 300, 40, 60.0), (64, 512, 24, 120.0),
-                                            (1, 50, 10, 30.0), (64, 30000, 60, 150.0)])
+                                            (1, 50, 10, 30.0), (64, 30000, 60, 150.0),
+                                            (5, 4097, 20, 40.0), (3, 8192, 12, 50.0)])
 def test_lda_full_sweep_replay(dev, K, V, D, mean_len):
     import torch
     b = _b()
     seed, alpha, beta, sweeps = 777 + K, 0.1, 0.05, 4
     off, words, z0 = _corpus(D, K, V, mean_len, seed=K)
-    _say("lda_full replay", K, V, D, int(off[-1]))
-    ctx = b.brng_create(seed, K + D, [512, 512, 512, 0], layout=b.BRNG_LAYOUT_ITEMS,
+    U = b.brng_lda_full_units(K, V, D)
+    nb = (U - D) // K  # vocabulary blocks per topic
+    assert U == oracle.lda_full_units(K, V, D)
+    _say("lda_full replay", K, V, D, int(off[-1]), "blocks", nb)
+    ctx = b.brng_create(seed, U, [512, 512, 512, 0], layout=b.BRNG_LAYOUT_ITEMS,
                         stream=torch.cuda.current_stream())
     buf = _bufs(dev, D, K, V, words, z0)
     toff = _t(off, dev)
-    cur = oracle.new_cursors(K + D)
+    cur = oracle.new_cursors(U)
     z_in = z0.copy()
     flips = 0
     try:
@@ -85,7 +90,7 @@ def test_lda_full_sweep_replay(dev, K, V, D, mean_len):
             gz, gth = _np(buf["z"]), _np(buf["theta"])
             gphi = np.ascontiguousarray(_np(buf["phi"]).reshape(V, K).T)  # word-major on device
             gndk, gnkw = _np(buf["ndk"]), _np(buf["nkw"])
-            gcur = b.brng_get_cursors(ctx)[:K + D]
+            gcur = b.brng_get_cursors(ctx)[:U]
             r = oracle.lda_full_sweep(seed, cur, K, V, alpha, beta, off, words, z_in,
                                       theta32=gth, phi32=gphi.ravel())
             flipped = set()
@@ -93,12 +98,12 @@ def test_lda_full_sweep_replay(dev, K, V, D, mean_len):
             for k in range(K):
                 if not okp[k].all():
                     assert r["phi_margin"][k] <= 1.0, ("phi", s, k)
-                    flipped.add(k)
+                    flipped.update(range(k * nb, (k + 1) * nb))  # the topic's blocks
             okt = within(gth.reshape(D, K), r["theta"], r["theta_tol"])
             for d in range(D):
                 if not okt[d].all():
                     assert r["theta_margin"][d] <= 1.0, ("theta", s, d)
-                    flipped.add(K + d)
+                    flipped.add(K * nb + d)
             flips += len(flipped)
             bad = np.nonzero(gz != r["z"])[0]
             if bad.size:
@@ -107,12 +112,12 @@ def test_lda_full_sweep_replay(dev, K, V, D, mean_len):
             assert bad.size == 0, s
             assert np.array_equal(gndk.reshape(D, K), r["ndk"]), s
             assert np.array_equal(gnkw.reshape(K, V), r["nkw"]), s
-            keep = np.array([u not in flipped for u in range(K + D)])
+            keep = np.array([u not in flipped for u in range(U)])
             assert np.array_equal(gcur[keep], cur[keep]), s
             cur[:] = gcur  # replay: follow the device from here
             z_in = gz
         print("lda_full flips", flips, flush=True)
-        assert flips <= 2
+        assert flips <= 2 * nb
     finally:
         b.brng_destroy(ctx)
 
@@ -158,8 +163,10 @@ def test_lda_full_rejects_bad_arguments(dev):
                         stream=torch.cuda.current_stream())
     buf = _bufs(dev, D, K, V, words, z0)
     try:
-        for k, v, a in ((65, V, 0.1), (K, (1 << 20) + 1, 0.1), (K, V, 0.0), (K + 1, V, 0.1)):
-            # K + 1 topics with D documents need more units than the context has
+        for k, v, a in ((65, V, 0.1), (K, (1 << 20) + 1, 0.1), (K, V, 0.0), (K + 1, V, 0.1),
+                        (K, 4097, 0.1)):
+            # K + 1 topics with D documents, or two vocabulary blocks per
+            # topic, need more units than the context has
             with pytest.raises(b.BrngError):
                 b.brng_run_lda_full(ctx, k, v, 1, a, 0.05, _t(off, dev), buf["words"], buf["z"],
                                     buf["ndk"], buf["nkw"], buf["theta"], buf["phi"])
@@ -167,18 +174,20 @@ def test_lda_full_rejects_bad_arguments(dev):
         b.brng_destroy(ctx)
 
 
-def test_lda_full_window_and_launch_shape_invariance(dev):
+@pytest.mark.parametrize("K,V,D", [(24, 700, 50), (8, 9000, 40)])
+def test_lda_full_window_and_launch_shape_invariance(dev, K, V, D):
     """Window length and waves per workgroup are speed knobs only: three
     configurations give the same topics, counts, draws and cursors bit for
-    bit over three sweeps."""
+    bit over three sweeps (also with three vocabulary blocks per topic)."""
     import torch
     b = _b()
-    K, V, D, seed = 24, 700, 50, 99
+    seed = 99
     off, words, z0 = _corpus(D, K, V, 90.0, seed=7)
     _say("lda_full window/launch invariance", K, V, D)
     res = []
     for win, wpb in ((512, 4), (4096, 1), (1024, 8)):
-        ctx = b.brng_create(seed, K + D, [win, win, win, 0], layout=b.BRNG_LAYOUT_ITEMS,
+        ctx = b.brng_create(seed, b.brng_lda_full_units(K, V, D), [win, win, win, 0],
+                            layout=b.BRNG_LAYOUT_ITEMS,
                             stream=torch.cuda.current_stream())
         buf = _bufs(dev, D, K, V, words, z0)
         try:
