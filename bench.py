@@ -190,7 +190,7 @@ def setup_normexp(torch, b, args):
     return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_N, b.BRNG_E], keep=(st, ts, te),
                 entry_bytes={b.BRNG_N: 4, b.BRNG_E: 4}, windows={b.BRNG_N: W, b.BRNG_E: W},
                 deviates=2 * n * steps, out_bytes=2 * n * steps * 4, dtype="f32", cpu=cpu,
-                cpu1=cpu1, kernel="k_gibbs<NORMEXP>",
+                cpu1=cpu1, kernel="k_gibbs<1>",
                 config={"workload": "normal/exponential chains: s'~N(0.9s,0.5+|s|), e~Exp(1+s'^2)",
                         "chains": n, "steps": steps, "window_per_unit_per_kind": W,
                         "unit_chains": 64, "precision": "fp32", "generator": "Philox4x32-10"})
@@ -227,7 +227,7 @@ def setup_triangle(torch, b, args):
     return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_U64], keep=(st, tx, ty),
                 entry_bytes={b.BRNG_U64: 8}, windows={b.BRNG_U64: W},
                 deviates=2 * n * iters, out_bytes=2 * n * iters * 8, dtype="f64", cpu=cpu, cpu1=cpu1,
-                kernel="k_gibbs<TRIANGLE>",
+                kernel="k_gibbs<0>",
                 config={"workload": "triangle Gibbs sampler of Eq. 1 / Fig. 1: x~U(0,1-y), y~U(0,1-x)",
                         "chains": n, "iterations": iters, "window_per_unit": W,
                         "precision": "fp64", "generator": "Philox4x32-10"})
@@ -298,7 +298,7 @@ def setup_gamma(torch, b, args):
                 keep=(st, tg, tsteps, tperm),
                 entry_bytes={b.BRNG_N: 4, b.BRNG_E: 4}, windows={b.BRNG_N: W, b.BRNG_E: W},
                 deviates=draws, out_bytes=draws * 4, dtype="f32", cpu=cpu, cpu1=cpu1, oaat=oaat,
-                kernel="k_gibbs<GAMMA_CHAIN>",
+                kernel="k_gibbs<2>",
                 config={"workload": "varying-shape gamma chains: g~Gamma(alpha,1), alpha'=0.1+g, "
                                     "Marsaglia-Tsang with the alpha<1 boost",
                         "chains": n, "steps": "U{50..1000}", "draws_per_step": draws,
@@ -356,7 +356,7 @@ def setup_lda(torch, b, args):
                 entry_bytes={b.BRNG_U: 4, b.BRNG_N: 4, b.BRNG_E: 4},
                 windows={b.BRNG_U: W, b.BRNG_N: W, b.BRNG_E: W},
                 deviates=dv, out_bytes=sweeps * total * 8, dtype="f32", cpu=cpu, cpu1=cpu1,
-                kernel="k_gibbs<LDA>",
+                kernel="k_gibbs_lda",
                 config={"workload": "LDA-style Dirichlet resampling: theta~Dir(0.1+counts), "
                                     "counts~Mult(n_d, theta)",
                         "documents": nd, "sweeps": sweeps, "K": "{8,16,64,256}",
