@@ -484,7 +484,8 @@ def lda(seed, offsets, ntok, sweeps, counts0=None, cursors=None, unit0=0):
 # (the motivating application of Sec. 1 and its footnote, run as the
 # uncollapsed Gibbs sampler of the LDA model: phi_k | z ~ Dir(beta + n_k.),
 # theta_d | z ~ Dir(alpha + n_d.), z_di | theta, phi ~ Cat(theta_dk phi_k,w)).
-# Units: topic k is unit k, document d is unit K + d.
+# Units: topic k's vocabulary block j is unit k nb + j (nb blocks of
+# LDA_FULL_VBLOCK words per topic), document d is unit K nb + d.
 # --------------------------------------------------------------------------
 
 def lda_full_counts(K, V, doc_offsets, words, z):
