@@ -794,6 +794,11 @@ def measure(torch, b, args, workload):
     ev.pairs.clear()
     cur0 = b.brng_get_cursors(ctx)
     torch.cuda.synchronize()
+    # no garbage collection inside the timed region: the steps are queued
+    # by this thread, and a long collection would leave the GPU waiting
+    import gc
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -803,6 +808,7 @@ def measure(torch, b, args, workload):
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gc.enable()
     cur1 = b.brng_get_cursors(ctx)
     ms_step = start.elapsed_time(stop) / args.steps
     value = Wk["deviates"] / (ms_step / 1e3)
@@ -845,21 +851,37 @@ def measure(torch, b, args, workload):
                                              for t in tuned["table"]}}
     if "oaat" in Wk and not args.no_oaat:
         out["one_launch_per_step"] = Wk["oaat"](ev)
-    if not args.no_cpu:
-        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
-        cb = Wk["cpu"](workers)
-        # one core: the same oracle in this process on a smaller sample, and
-        # its cycles per deviate at the host's nominal clock (the unit of the
-        # paper's results table)
-        one = Wk["cpu1"]()
-        ghz = args.host["nominal_ghz"]
-        if ghz:
-            one["cycles_per_deviate_at_nominal"] = round(ghz * 1e9 / one["value"], 1)
-        cb["one_core"] = one
-        cb.update({k: v for k, v in args.host.items()})
-        out["cpu_baseline"] = cb
     b.brng_destroy(ctx)
+    if not args.no_cpu:
+        # the oracle legs run after every GPU measurement of the run (see
+        # run_cpu_legs), so that a pool of host processes never overlaps a
+        # timed region
+        out["_cpu"] = lambda: cpu_leg(Wk, args)
     return out
+
+
+def cpu_leg(Wk, args):
+    """The oracle on a bounded sample over the host's processes, and on a
+    smaller sample in one thread, with the host's description."""
+    workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+    cb = Wk["cpu"](workers)
+    # one core: the same oracle in this process on a smaller sample, and its
+    # cycles per deviate at the host's nominal clock (the unit of the paper's
+    # results table)
+    one = Wk["cpu1"]()
+    ghz = args.host["nominal_ghz"]
+    if ghz:
+        one["cycles_per_deviate_at_nominal"] = round(ghz * 1e9 / one["value"], 1)
+    cb["one_core"] = one
+    cb.update({k: v for k, v in args.host.items()})
+    return cb
+
+
+def run_cpu_legs(results):
+    for r in results:
+        leg = r.pop("_cpu", None)
+        if leg is not None:
+            r["cpu_baseline"] = leg()
 
 
 HEADLINE = "lda"
@@ -973,6 +995,8 @@ def main():
         # the metric's second half: served latency and throughput against
         # per-request plain launches on a mixed request stream
         out["served"] = served_section(torch, args, args.served_requests)
+    # the CPU oracle legs, once no more GPU work is timed
+    run_cpu_legs([out] + list(out.get("workloads", {}).values()))
     print(json.dumps(out), flush=True)
 
 
