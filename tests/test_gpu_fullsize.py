@@ -316,20 +316,24 @@ def test_lda_full_size(dev):
     assert diverged <= 1
 
 
-def test_lda_full_full_size(dev):
-    """Full LDA at the bench's size (16,384 documents, 64 topics, 4,096
-    words, window 512): two calls of one sweep; every topic's phi and eight
-    sampled documents (theta, every token's topic, n_d.) against the oracle
-    replayed from the device's state, n_kw against the counts of the new
-    assignment."""
+@pytest.mark.parametrize("V", [4096, 50000])
+def test_lda_full_full_size(dev, V):
+    """Full LDA at the bench's size (16,384 documents, 64 topics, window
+    512), over the bench's default vocabulary of 4,096 words and one of
+    50,000 (13 blocks of 4,096 words per topic): two calls of one sweep;
+    every topic's phi and eight sampled documents (theta, every token's
+    topic, n_d.) against the oracle replayed from the device's state, n_kw
+    against the counts of the new assignment."""
     import torch
     b = _b()
-    K, V, D = 64, 4096, 16384
+    K, D = 64, 16384
     c = workloads.lda_corpus(n_docs=D, n_topics=K, n_vocab=V, seed=SEED)
     off, words, z0 = c["offsets"], c["words"], c["z0"]
     T = int(off[-1])
-    _say("lda_full full size", D, K, V, T)
-    ctx = b.brng_create(SEED, K + D, [512, 512, 512, 0], layout=b.BRNG_LAYOUT_ITEMS,
+    U = b.brng_lda_full_units(K, V, D)
+    du = U - D  # unit of document 0: the topic blocks come first
+    _say("lda_full full size", D, K, V, T, "units", U)
+    ctx = b.brng_create(SEED, U, [512, 512, 512, 0], layout=b.BRNG_LAYOUT_ITEMS,
                         stream=torch.cuda.current_stream())
     tz = _t(z0, dev)
     ndk = torch.zeros(D * K, dtype=torch.int32, device=dev)
@@ -337,7 +341,7 @@ def test_lda_full_full_size(dev):
     th = torch.zeros(D * K, dtype=torch.float32, device=dev)
     phi = torch.zeros(K * V, dtype=torch.float32, device=dev)
     docs = [0, 1, 777, 4096, 9000, 12345, 16000, D - 1]
-    cur = oracle.new_cursors(K + D)
+    cur = oracle.new_cursors(U)
     z_in = z0.copy()
     flips = 0
     try:
@@ -368,7 +372,7 @@ def test_lda_full_full_size(dev):
             ndk_ref, nkw_ref = oracle.lda_full_counts(K, V, off, words, gz)
             assert np.array_equal(gndk[docs], ndk_ref[docs]), call
             assert np.array_equal(gnkw, nkw_ref), call
-            units = list(range(K)) + [K + d for d in docs]
+            units = list(range(du)) + [du + d for d in docs]
             same = [u for u in units if np.array_equal(gcur[u], cur[u])]
             assert len(same) >= len(units) - 2, call
             cur[:] = gcur
