@@ -95,9 +95,11 @@ __device__ __forceinline__ uint4 block_words(const Key& key, uint32_t kind, uint
 }
 
 // U = (2 (w >> 9) + 1) 2^-24: the open midpoint grid, exact in fp32.
-// 2 (w >> 9) + 1 == (w >> 8) | 1.
+// Formed from the bits of 1 + (w >> 9) 2^-23 minus (1 - 2^-24): both
+// operands lie in [1/2, 2) within a factor of two of each other, so the
+// difference is exact (one shift, one or and one subtraction).
 __device__ __forceinline__ float u01(uint32_t w) {
-    return (float)((w >> 8) | 1u) * 0x1p-24f;
+    return __uint_as_float((w >> 9) | 0x3F800000u) - 0x1.fffffep-1f;
 }
 
 // U64 = (2k + 1) 2^-53 with k = (wa << 20) | (wb >> 12): 52 random bits.
