@@ -135,11 +135,15 @@ __device__ __forceinline__ float2 sincos_2pi(float u) {
     c = fmaf(a2, c, 4.16666667e-2f);                       // 1/4!
     c = fmaf(a2, c, -0.5f);
     c = fmaf(a2, c, 1.0f);
-    const int k = (int)kf;
+    const uint32_t k = (uint32_t)(int)kf;
     const float ss = (k & 1) ? c : s;  // sin(theta + k pi/2)
     const float cc = (k & 1) ? s : c;
-    const float sn = (k & 2) ? -ss : ss;
-    const float cs = ((k + 1) & 2) ? -cc : cc;
+    // the sign changes (bit 1 of k for the sine, of k + 1 for the cosine)
+    // applied to the sign bit directly
+    const uint32_t fs = (k << 30) & 0x80000000u;
+    const uint32_t fc = ((k + 1u) << 30) & 0x80000000u;
+    const float sn = __uint_as_float(__float_as_uint(ss) ^ fs);
+    const float cs = __uint_as_float(__float_as_uint(cc) ^ fc);
     return make_float2(sn, cs);
 }
 
