@@ -714,9 +714,12 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
         {
             const uint64_t cu = ucur;
             const uint64_t blo = cu / 4, bhi = (cu + (uint32_t)max(ntok, 0) + 3) / 4;
+            const uint32_t c0 = (uint32_t)cu & 3u;  // cu - 4 blo
+            const uint32_t nt = (uint32_t)max(ntok, 0);
             const Key ku = meta_key(m);
             for (uint64_t r0 = blo; r0 < bhi; r0 += 64) {
                 const uint64_t b = r0 + lane;
+                const uint32_t bi = (uint32_t)(r0 - blo) + lane;  // b - blo
                 const uint4 w = block_words<true>(ku, KIND_U, b);
                 const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
                 int32_t* p[4] = {Cs, Cs, Cs, Cs};  // bin end of the position reached
@@ -734,8 +737,10 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
                 // the counts sit LDA_KMAX entries past the bin ends
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const uint64_t e = 4 * b + (uint64_t)i;
-                    if (b < bhi && e >= cu && e < cu + (uint32_t)ntok) atomicAdd(p[i] + LDA_KMAX, 1);
+                    // entry 4 b + i is token tk of the sweep; entries before
+                    // the cursor wrap to large values
+                    const uint32_t tk = 4u * bi + (uint32_t)i - c0;
+                    if (tk < nt) atomicAdd(p[i] + LDA_KMAX, 1);
                 }
             }
             ucur = cu + (uint32_t)max(ntok, 0);
