@@ -729,9 +729,12 @@ __device__ void unit_lda(const DescDev& D, Meta* mp, const Pools& P, uint32_t do
                 static_for<0, 8>([&](auto jc) {
                     constexpr int e = 7 - decltype(jc)::value;
                     if (e <= kexp) {
+                        // the four probes first, then the four steps
+                        int32_t v[4];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            p[i] += (uint32_t)p[i][(1 << e) - 1] <= t[i] ? (1 << e) : 0;
+                        for (int i = 0; i < 4; ++i) v[i] = p[i][(1 << e) - 1];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) p[i] += (uint32_t)v[i] <= t[i] ? (1 << e) : 0;
                     }
                 });
                 // the counts sit LDA_KMAX entries past the bin ends
