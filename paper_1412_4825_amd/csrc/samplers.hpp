@@ -381,20 +381,23 @@ __device__ __forceinline__ float wave_sum(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, t), 63));
 }
 
-// Sum over an aligned group of S lanes (S = 8 or 16) by exchanges with the
-// lanes whose index differs in bit 3 (S = 16 only), then bit 2, 1 and 0:
-// every lane of the group gets the same value.  For a group of 16 whose
-// upper 8 lanes hold zero the first exchange adds zero to each value, so the
-// sum equals that of the lower 8 lanes as a group of 8: documents of up to 8
-// components get the same sum in either layout, and in the wave of a single
-// document.
+// Sum over an aligned group of S lanes (S = 8 or 16), identical in every
+// lane of the group, by DPP lane moves (no LDS round trip): for S = 16 each
+// lane first adds the lane 8 away in its row (a rotation by 8 within the
+// row of 16), so lanes j and j + 8 hold the same pair sum; then within each
+// half-row lane j adds lane 7 - j (half mirror), and the four distinct pair
+// sums of a quad are added by the quad exchanges (lanes differing in bit 0,
+// then bit 1).  Floating-point addition is commutative, so every lane of
+// the group forms the same sum.  For a group of 16 whose upper 8 lanes hold
+// zero the first step adds zero to each value, so the sum equals that of the
+// lower 8 lanes as a group of 8: documents of up to 8 components get the
+// same sum in either layout, and in the wave of a single document.
 template <int S>
 __device__ __forceinline__ float group_sum(float v) {
-    if constexpr (S >= 16)
-        v = v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x201F));  // xor 8
-    v = v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));      // xor 4
-    v = v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x081F));      // xor 2
-    v = v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x041F));      // xor 1
+    if constexpr (S >= 16) v = v + dpp_move<0x128, 0xF, false>(v);  // row_ror:8
+    v = v + dpp_move<0x141, 0xF, false>(v);  // row_half_mirror
+    v = v + dpp_move<0xB1, 0xF, false>(v);   // quad_perm [1,0,3,2]
+    v = v + dpp_move<0x4E, 0xF, false>(v);   // quad_perm [2,3,0,1]
     return v;
 }
 
