@@ -244,18 +244,19 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // (fewer scalar instructions, more code and registers; it pays off for a
 // kernel with two readers, not with three); with one block per lane per
 // chunk the second block is the next chunk's, which then waits in registers.
-template <uint32_t KIND, int CHV, bool PAIRED = false>
+// MIRROR: the ring is followed by a copy of its first 64 entries, so that the
+// 64 entries from any position are contiguous; without it a read wraps its
+// index (one more instruction) and the ring takes 256 bytes less LDS.
+template <uint32_t KIND, int CHV, bool PAIRED = false, bool MIRROR = true>
 struct EpochReader {
     static_assert(CHV == 1 || CHV == 2, "a chunk is one or two blocks per lane");
     using T = typename KindTraits<KIND>::T;
     static constexpr int EPB = KindTraits<KIND>::EPB;
     static constexpr uint32_t CH = 64u * EPB * CHV;
     static constexpr uint32_t R = 2 * CH;
-    // the ring, then a copy of its first 64 entries, so that the 64 entries
-    // from any position are contiguous
-    static constexpr int LDS_BYTES = (int)((R + 64) * sizeof(T));
+    static constexpr int LDS_BYTES = (int)((R + (MIRROR ? 64 : 0)) * sizeof(T));
     T* win;
-    T* ring;  // LDS, R + 64 entries
+    T* ring;  // LDS, R entries (+ 64: the mirror)
     Key key;
     uint64_t wbase, staged;  // ring holds entries [.., staged)
     uint32_t wlen, W;
@@ -312,7 +313,8 @@ struct EpochReader {
         }
         // the mirror: entries 0..63 of the ring are lanes 0 .. 64/EPB - 1 of
         // the first load of the chunk at offset 0
-        if (off == 0 && lane_id() < 64u / EPB) reinterpret_cast<u32x4*>(ring + R)[lane_id()] = head;
+        if (MIRROR && off == 0 && lane_id() < 64u / EPB)
+            reinterpret_cast<u32x4*>(ring + R)[lane_id()] = head;
         staged += CH;
         avail += (int32_t)CH;
     }
@@ -354,7 +356,9 @@ struct EpochReader {
         while ((int32_t)n > avail) stage();
     }
     // Entry cursor + r (r < 64, after reserve).
-    __device__ __forceinline__ T peek(uint32_t r) const { return ring[pos + r]; }
+    __device__ __forceinline__ T peek(uint32_t r) const {
+        return MIRROR ? ring[pos + r] : ring[(pos + r) & (R - 1)];
+    }
     __device__ __forceinline__ void advance(uint32_t n) {
         pos = (pos + n) & (R - 1);
         avail -= (int32_t)n;
