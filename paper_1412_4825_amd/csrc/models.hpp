@@ -530,6 +530,7 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
     src.trace = D.trace != nullptr;
     src.col = src.trace ? reinterpret_cast<float*>(D.trace) + slot : nullptr;
     src.stride = D.stride;
+    src.vec = src.trace && ((uintptr_t)D.trace & 15u) == 0 && (D.stride & 3) == 0;
     src.ring = reinterpret_cast<float*>(lds + GammaRN::LDS_BYTES + GammaRE::LDS_BYTES) + lane;
     src.s1 = src.s2 = 0.0;
     if (SUMS && in) {

@@ -289,7 +289,11 @@ __device__ __forceinline__ int32_t wave_minmax(int32_t v) {
 // Lanes at different steps (rejections) then no longer scatter 4-byte stores
 // over many rows.  When the lanes spread further apart than the ring holds,
 // the lowest rows are stored partially (the lanes that have written them) and
-// a lane that later completes such a row stores its value directly.
+// a lane that later completes such a row stores its value directly.  Where
+// every lane of the wave has written four consecutive rows in this launch
+// (and the trace rows are 16-byte aligned), the four rows go out in one
+// 16-byte store per lane: lane l stores chains 4 (l mod 16) .. + 3 of row
+// r + l / 16.
 constexpr int32_t TRACE_ROWS = 16;
 template <bool SUMS>
 struct ChainSrc {
@@ -297,6 +301,8 @@ struct ChainSrc {
     int32_t t0;      // the lane's first step in this launch
     float alpha;
     bool trace;      // wave-uniform: write the trace
+    bool vec;        // wave-uniform: trace rows 16-byte aligned (four-row stores)
+    int32_t t0max;   // wave-uniform: the largest t0 of the wave
     float* col;      // this lane's trace column (row 0), or null
     int64_t stride;  // trace elements between steps
     float* ring;     // LDS, TRACE_ROWS x 64 values; this lane's column
@@ -305,6 +311,7 @@ struct ChainSrc {
                      // draws, in step order
     __device__ __forceinline__ float first() {
         t0 = t;
+        t0max = wave_minmax<true>(t0);
         f = wave_minmax<false>(t < L ? t : INT32_MAX);
         return alpha;
     }
@@ -338,6 +345,17 @@ struct ChainSrc {
     __device__ __forceinline__ void store_row(int32_t r) {
         if (t0 <= r && r < t) col[(int64_t)r * stride] = ring[(r & (TRACE_ROWS - 1)) * 64];
     }
+    // Rows r .. r + 3, written by every lane in this launch: lane l moves
+    // chains 4 (l mod 16) .. 4 (l mod 16) + 3 of row r + l / 16 (16 bytes
+    // from the ring, 16 bytes to the trace).
+    __device__ __forceinline__ void store_rows4(int32_t r) {
+        const uint32_t lane = lane_id();
+        const int32_t rr = r + (int32_t)(lane >> 4);
+        const uint32_t cc = 4u * (lane & 15u);
+        const float4 v = *reinterpret_cast<const float4*>(
+            ring - lane + (uint32_t)(rr & (TRACE_ROWS - 1)) * 64u + cc);
+        *reinterpret_cast<float4*>(col - lane + (int64_t)rr * stride + cc) = v;
+    }
     // Epoch point (final: the end of the launch, when every written row goes
     // out).  Keeps room in the ring for the next EPOCH_ROUNDS steps.
     __device__ __forceinline__ void flush(bool final = false) {
@@ -345,7 +363,13 @@ struct ChainSrc {
         const int32_t hi = wave_minmax<true>(t);
         if (trace) {
             const int32_t end = final ? hi : min(lo, hi);
-            for (int32_t r = f; r < end; ++r) store_row(r);
+            int32_t r = f;
+            if (vec && r + 4 <= end && r >= t0max) {
+                // every lane has written rows below the smallest t of the wave
+                const int32_t tmin = wave_minmax<false>(t);
+                for (; r + 4 <= min(end, tmin); r += 4) store_rows4(r);
+            }
+            for (; r < end; ++r) store_row(r);
             f = max(f, end);
             for (; f < hi + (int32_t)EPOCH_ROUNDS - TRACE_ROWS; ++f) store_row(f);
         } else {
