@@ -487,6 +487,37 @@ def test_gamma_chains(dev):
     assert len(flips) <= 2
 
 
+def test_gamma_trace_store_paths_bitwise_equal(dev):
+    """Gamma-chain traces are the same bits whether rows go out one by one
+    (a trace stride that is not a multiple of four) or four rows per 16-byte
+    store (a stride that is), over a fresh launch of at most 37 steps per
+    chain and a resumed launch of every chain's full length."""
+    import torch
+    b = _b()
+    w = workloads.gamma_chain(n_chains=4096 + 17, lmin=20, lmax=300, seed=91)
+    n, seed = w["n_chains"], 57
+    perm = b.brng_sort_by_length(w["steps"])
+    smax = int(w["steps"].max())
+    outs = []
+    for stride in (n, n + 3):  # n = 4,113: rows one by one; n + 3: four-row stores
+        _say("gamma trace paths", n, stride)
+        ctx = _ctx(seed, n, W_SMALL)
+        st = _t(w["alpha0"], dev)
+        tg = torch.full((smax, stride), float("nan"), dtype=torch.float32, device=dev)
+        kw = dict(trace=tg, trace_stride=stride, perm=_t(perm, dev))
+        try:
+            _gibbs(ctx, b.BRNG_MODEL_GAMMA_CHAIN, n, st, 37, seed, dev, tg, None, stride,
+                   steps=_t(np.minimum(w["steps"], 37).astype(np.int32), dev), perm=_t(perm, dev))
+            _gibbs(ctx, b.BRNG_MODEL_GAMMA_CHAIN, n, st, smax, seed, dev, tg, None, stride,
+                   steps=_t(w["steps"], dev), perm=_t(perm, dev), flags=b.BRNG_FLAG_RESUME)
+            outs.append((_np(tg)[:, :n], _np(st), b.brng_get_cursors(ctx)))
+        finally:
+            b.brng_destroy(ctx)
+    assert (n + 3) % 4 == 0 and n % 4 != 0
+    for x, y in zip(outs[0], outs[1]):
+        assert np.array_equal(x, y, equal_nan=True)
+
+
 def test_lda(dev):
     import torch
     b = _b()
