@@ -126,7 +126,10 @@ __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t 
         // and consumes nothing); below 1 the boost applies
         const uint64_t mv = wave_ballot(al > 0.0f) & wave_ballot(al < 0x1p64f);
         const uint64_t mboost = mv & wave_ballot(al < 1.0f);
-        const float a = lane_in(mv) ? (lane_in(mboost) ? al + 1.0f : al) : 1.0f;
+        // selects, not a branch: al + 1 where the boost applies, al + 0 = al
+        // elsewhere (al > 0 wherever the sum is used)
+        const float ab = al + (lane_in(mboost) ? 1.0f : 0.0f);
+        const float a = lane_in(mv) ? ab : 1.0f;
         const float d = a - (1.0f / 3.0f);
         const float c = __builtin_amdgcn_rsqf(9.0f * d);  // 1 / sqrt(9 d)
         const uint64_t mp = mh & mv;
@@ -320,14 +323,14 @@ struct ChainSrc {
     // without a trace: the ring is there either way); only lanes whose draw
     // completed move on, so a slot written by a lane that did not is
     // rewritten before its row is stored.  A lane behind the stored rows
-    // stores a completed value itself.
+    // stores a completed value itself; its ring write is harmless: the slot's
+    // earlier row has gone out, and its next row is stored for this lane only
+    // after the lane has passed it, i.e. rewritten the slot.
     __device__ __forceinline__ float complete(uint64_t md, float gv, float) {
         const bool done = lane_in(md);
         const bool behind = t < f;
-        if (wave_ballot(behind) == 0) {
-            ring[(t & (TRACE_ROWS - 1)) * 64] = gv;
-        } else {
-            if (!behind) ring[(t & (TRACE_ROWS - 1)) * 64] = gv;
+        ring[(t & (TRACE_ROWS - 1)) * 64] = gv;
+        if (wave_ballot(behind) != 0) {
             if (behind && done && trace) col[(int64_t)t * stride] = gv;
         }
         if constexpr (SUMS) {
