@@ -493,9 +493,11 @@ __device__ void unit_expchain(const DescDev& D, Meta* mp, const Pools& P, uint32
 // as soon as a draw is accepted.
 // ---------------------------------------------------------------------------
 // Without the mirrors a wave's LDS is 10 KiB, so four workgroups of four
-// waves fit a CU's 160 KiB (four waves per SIMD instead of three).
-using GammaRN = EpochReader<KIND_N, 1, true, false>;
-using GammaRE = EpochReader<KIND_E, 2, true, false>;
+// waves fit a CU's 160 KiB (four waves per SIMD instead of three).  The
+// readers generate every chunk, also inside the windows: the loop then holds
+// no load, and its epoch points never wait for the trace stores in flight.
+using GammaRN = EpochReader<KIND_N, 1, true, false, false>;
+using GammaRE = EpochReader<KIND_E, 2, true, false, false>;
 constexpr int GAMMA_OBUF_BYTES = TRACE_ROWS * 64 * 4;
 constexpr int GAMMA_LDS_BYTES = GammaRN::LDS_BYTES + GammaRE::LDS_BYTES + GAMMA_OBUF_BYTES;
 // An epoch's worst case fits the rings (a round takes at most one Gaussian

@@ -247,7 +247,12 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // MIRROR: the ring is followed by a copy of its first 64 entries, so that the
 // 64 entries from any position are contiguous; without it a read wraps its
 // index (one more instruction) and the ring takes 256 bytes less LDS.
-template <uint32_t KIND, int CHV, bool PAIRED = false, bool MIRROR = true>
+// WINDOW: chunks inside the pool's window are loaded from it.  Without it
+// every chunk is generated (the same entries the window holds), so the
+// staging registers never wait for a load: on gfx9 one counter tracks loads
+// and stores alike, and a wait for a load that may be in flight also waits
+// for every store the wave has issued (a chain's trace rows).
+template <uint32_t KIND, int CHV, bool PAIRED = false, bool MIRROR = true, bool WINDOW = true>
 struct EpochReader {
     static_assert(CHV == 1 || CHV == 2, "a chunk is one or two blocks per lane");
     using T = typename KindTraits<KIND>::T;
@@ -326,7 +331,7 @@ struct EpochReader {
             inflight = true;
             return;
         }
-        inflight = in_window(staged);
+        inflight = WINDOW && in_window(staged);
         if (inflight) load(staged);
     }
     __device__ __forceinline__ void stage() {
