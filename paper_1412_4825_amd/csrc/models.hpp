@@ -557,8 +557,10 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
 }
 
 constexpr int LDA_KMAX = 256;
-using LdaRN = EpochReader<KIND_N, 1>;
-using LdaRE = EpochReader<KIND_E, 1>;
+// The readers generate every chunk (no loads from the windows), so the
+// epoch points never wait for the theta and count rows in flight.
+using LdaRN = EpochReader<KIND_N, 1, false, true, false>;
+using LdaRE = EpochReader<KIND_E, 1, false, true, false>;
 constexpr int LDA_RINGS_BYTES = LdaRN::LDS_BYTES + LdaRE::LDS_BYTES;
 // Epoch points every two rounds keep the one-chunk rings covered.
 constexpr uint32_t LDA_EPOCH = 2;
