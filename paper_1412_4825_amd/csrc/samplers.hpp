@@ -137,6 +137,8 @@ __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t 
         // same lanes whenever every pending lane has 1 + c x > 0, which is
         // nearly always: both are read with the same ranks at once, and the
         // exponential call is redone with its own ranks when it is not so.
+        // The rare branches are marked so, which keeps them out of line and
+        // the common path free of taken branches.
         const uint32_t np = (uint32_t)__popcll(mp);
         if constexpr (!COVERED) {
             rn.reserve(np);
@@ -150,7 +152,7 @@ __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t 
         const float y = c * x;
         const float v0 = 1.0f + y;
         const uint64_t me = mp & wave_ballot(v0 > 0.0f);
-        if (me == mp) {
+        if (__builtin_expect(me == mp, 1)) {
             adv_e(np);
         } else {
             e = re.peek(mask_rank(me));
@@ -163,7 +165,7 @@ __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t 
         const MtStat st = mt_stat(d, y, v0, e);
         uint64_t macc = me & wave_ballot(st.stat > 0.0f);
         const uint64_t muns = me & wave_ballot(!(fabsf(st.stat) > st.bound));
-        if (muns != 0) {
+        if (__builtin_expect(muns != 0, 0)) {
             bool a64 = false;
             if (lane_in(muns)) a64 = mt_accept64(a, x, e);
             macc = (macc & ~muns) | (muns & wave_ballot(a64));
@@ -200,7 +202,7 @@ __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t 
             if (!live) return;
             if (i > 0) {
                 mh = wave_ballot(src.holding());
-                if (mh == 0) {
+                if (__builtin_expect(mh == 0, 0)) {
                     live = false;
                     return;
                 }
