@@ -14,6 +14,8 @@
 // to cancellation, so the wave decides in fp32 only when the statistic is
 // clear of its fp32 error bound and otherwise recomputes it in fp64.
 #pragma once
+#include <type_traits>
+
 #include "pool.hpp"
 
 namespace brng {
@@ -283,6 +285,30 @@ __device__ __forceinline__ int32_t wave_minmax(int32_t v) {
     return __builtin_amdgcn_readlane(v, 63);
 }
 
+// The minimum of a, the maximum of b and the minimum of c over the wave, the
+// three reductions interleaved step by step, so that no lane move reads a
+// register written by the instruction just before it (which would need wait
+// states of its own).
+__device__ __forceinline__ void wave_min_max_min(int32_t a, int32_t b, int32_t c, int32_t& amin,
+                                                 int32_t& bmax, int32_t& cmin) {
+    auto step = [&](auto ctl) {
+        constexpr int CTL = decltype(ctl)::value & 0xFFF;
+        constexpr int ROWS = decltype(ctl)::value >> 12;
+        a = min(a, __builtin_amdgcn_update_dpp(INT32_MAX, a, CTL, ROWS, 0xF, false));
+        b = max(b, __builtin_amdgcn_update_dpp(INT32_MIN, b, CTL, ROWS, 0xF, false));
+        c = min(c, __builtin_amdgcn_update_dpp(INT32_MAX, c, CTL, ROWS, 0xF, false));
+    };
+    step(std::integral_constant<int, 0xF111>{});  // row_shr:1
+    step(std::integral_constant<int, 0xF112>{});  // row_shr:2
+    step(std::integral_constant<int, 0xF114>{});  // row_shr:4
+    step(std::integral_constant<int, 0xF118>{});  // row_shr:8
+    step(std::integral_constant<int, 0xA142>{});  // row_bcast:15 into rows 1 and 3
+    step(std::integral_constant<int, 0xC143>{});  // row_bcast:31 into rows 2 and 3
+    amin = __builtin_amdgcn_readlane(a, 63);
+    bmax = __builtin_amdgcn_readlane(b, 63);
+    cmin = __builtin_amdgcn_readlane(c, 63);
+}
+
 // One chain per lane: g_t ~ Gamma(alpha_t, 1), alpha_{t+1} = 0.1 + g_t; the
 // lane starts its next step as soon as a draw is accepted.
 //
@@ -364,19 +390,19 @@ struct ChainSrc {
     // Epoch point (final: the end of the launch, when every written row goes
     // out).  Keeps room in the ring for the next EPOCH_ROUNDS steps.
     __device__ __forceinline__ void flush(bool final = false) {
-        const int32_t lo = wave_minmax<false>(t < L ? t : INT32_MAX);
-        const int32_t hi = wave_minmax<true>(t);
+        int32_t lo, hi, tmin;
+        wave_min_max_min(t < L ? t : INT32_MAX, t, t, lo, hi, tmin);
         if (trace) {
             const int32_t end = final ? hi : min(lo, hi);
             int32_t r = f;
-            if (vec && r + 4 <= end && r >= t0max) {
-                // every lane has written rows below the smallest t of the wave
-                const int32_t tmin = wave_minmax<false>(t);
+            // every lane has written rows below the smallest t of the wave
+            if (vec && r >= t0max)
                 for (; r + 4 <= min(end, tmin); r += 4) store_rows4(r);
-            }
-            for (; r < end; ++r) store_row(r);
-            f = max(f, end);
-            for (; f < hi + (int32_t)EPOCH_ROUNDS - TRACE_ROWS; ++f) store_row(f);
+            // rows below end are complete; rows below hi + EPOCH_ROUNDS -
+            // TRACE_ROWS go out partially, making room in the ring
+            const int32_t nf = max(end, hi + (int32_t)EPOCH_ROUNDS - TRACE_ROWS);
+            for (; r < nf; ++r) store_row(r);
+            f = max(f, nf);
         } else {
             f = max(f, max(min(lo, hi), hi + (int32_t)EPOCH_ROUNDS - TRACE_ROWS));
         }
