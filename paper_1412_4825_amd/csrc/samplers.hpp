@@ -343,7 +343,10 @@ struct ChainSrc {
     __device__ __forceinline__ float first() {
         t0 = t;
         t0max = wave_minmax<true>(t0);
-        f = wave_minmax<false>(t < L ? t : INT32_MAX);
+        // the smallest step a lane still holds; the largest step when no lane
+        // holds one (a finished unit launched again), so that f stays a row
+        // number and the flush's row arithmetic cannot overflow
+        f = min(wave_minmax<false>(t < L ? t : INT32_MAX), t0max);
         return alpha;
     }
     __device__ __forceinline__ bool holding() const { return t < L; }
@@ -394,10 +397,14 @@ struct ChainSrc {
         wave_min_max_min(t < L ? t : INT32_MAX, t, t, lo, hi, tmin);
         if (trace) {
             const int32_t end = final ? hi : min(lo, hi);
+            // f <= hi and every bound below is at least -TRACE_ROWS, so no
+            // sum or difference here overflows
             int32_t r = f;
             // every lane has written rows below the smallest t of the wave
-            if (vec && r >= t0max)
-                for (; r + 4 <= min(end, tmin); r += 4) store_rows4(r);
+            if (vec && r >= t0max) {
+                const int32_t lim = min(end, tmin) - 3;
+                for (; r < lim; r += 4) store_rows4(r);
+            }
             // rows below end are complete; rows below hi + EPOCH_ROUNDS -
             // TRACE_ROWS go out partially, making room in the ring
             const int32_t nf = max(end, hi + (int32_t)EPOCH_ROUNDS - TRACE_ROWS);

@@ -518,6 +518,43 @@ def test_gamma_trace_store_paths_bitwise_equal(dev):
         assert np.array_equal(x, y, equal_nan=True)
 
 
+def test_gamma_unit_without_steps_leaves_its_columns_alone(dev):
+    """A unit whose 64 chains all have zero steps (no lane holds a step when
+    the launch starts) stores nothing: its trace columns stay as they were,
+    its state and cursors do not move, and the other units' traces are the
+    same bits as in a run where that unit has steps of its own.  Trace rows
+    16-byte aligned (four-row stores) and not."""
+    import torch
+    b = _b()
+    n, seed, smax = 3 * 64 + 5, 77, 90
+    rng = np.random.default_rng(12)
+    steps_b = rng.integers(20, smax + 1, size=n).astype(np.int32)
+    steps_a = steps_b.copy()
+    steps_a[64:128] = 0  # unit 1
+    alpha0 = (0.1 * np.power(1000.0, rng.random(n))).astype(np.float32)
+    for stride in (n + 3, n):
+        outs = []
+        for steps in (steps_a, steps_b):
+            _say("gamma unit without steps", n, stride, int(steps[64:128].max()))
+            ctx = _ctx(seed, n, W_SMALL)
+            st = _t(alpha0, dev)
+            tg = torch.full((smax, stride), float("nan"), dtype=torch.float32, device=dev)
+            try:
+                _gibbs(ctx, b.BRNG_MODEL_GAMMA_CHAIN, n, st, smax, seed, dev, tg, None, stride,
+                       steps=_t(steps, dev))
+                outs.append((_np(tg)[:, :n], _np(st), b.brng_get_cursors(ctx)))
+            finally:
+                b.brng_destroy(ctx)
+        (ta, sa, ca), (tb, sb, cb) = outs
+        other = np.r_[0:64, 128:n]
+        assert np.array_equal(ta[:, other], tb[:, other], equal_nan=True)
+        assert np.array_equal(sa[other], sb[other])
+        assert np.isnan(ta[:, 64:128]).all()
+        assert np.array_equal(sa[64:128], alpha0[64:128])
+        assert np.array_equal(ca[[0, 2, 3]], cb[[0, 2, 3]])
+        assert np.array_equal(ca[1], oracle.new_cursors(4)[1])
+
+
 def test_lda(dev):
     import torch
     b = _b()
