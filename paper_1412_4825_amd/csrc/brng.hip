@@ -652,36 +652,47 @@ __global__ __launch_bounds__(256) void k_ldaf_phi_norm(int K, int V, uint32_t nb
 }
 
 // One uniform per token of document d (token order; theta_d drawn by the
-// Dirichlet launch before) and the token's topic: p_k = theta_k phi_w,k in fp32, q_k = rint(p_k 2^(24 - e)) with
-// max p = f 2^e, f in [1/2, 1) (an exact scaling; all 1 when max p = 0),
-// C_k = q_0 + ... + q_k, j = (u 2^24 - 1) / 2, t = (j C_{K-1}) >> 23,
-// z = the number of k with C_k <= t.  A word outside [0, V) gets z = -1 and
-// no count but still takes its uniform.  The uniforms are taken 64 at a time
-// (one per lane, in token order); then the wave works on one token at a
-// time with lane k on topic k (K <= 64): one coalesced read of the token's
-// phi row, the maximum and the prefix sums by DPP, the topic by a ballot.
-// New n_d. in place (LDS counts), n_kw added atomically (zero on entry), both
-// once per group of 64 tokens.
+// Dirichlet launch before) and the token's topic: p_k = theta_k phi_w,k in
+// fp32, q_k = rint(p_k 2^(24 - e)) with max p = f 2^e, f in [1/2, 1) (an
+// exact scaling; all 1 when max p is not positive), C_k = q_0 + ... + q_k,
+// j = (u 2^24 - 1) / 2, t = (j C_{K-1}) >> 23, z = the number of k with
+// C_k <= t.  A word outside [0, V) gets z = -1 and no count but still takes
+// its uniform.  The uniforms are taken 64 at a time (one per lane, in token
+// order), and lane l then works out the topic of token i0 + l by itself,
+// walking the K topics: its phi row (16-byte loads where rows are aligned),
+// theta from LDS (one broadcast read per four topics), the largest p as
+// int32 bits (the order a lane-parallel maximum over the topics, zeros of
+// absent topics included, would give the same), the q_k and their integer
+// sums.  A maximum and integer sums do not depend on their order, so the
+// topic is the same, bit for bit, as from any other arrangement of the rule.
+// KP: K padded to 16, 32 or 64 (the lane's registers are indexed
+// statically; padded topics weigh 0 and are never counted).  New n_d. in
+// place (LDS counts), n_kw added atomically (zero on entry), once per token.
+template <int KP>
 __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t D, int K, int V,
                                                    uint32_t nb, const int32_t* doff,
                                                    int32_t n_tokens,
                                                    const int32_t* words, const float* phi,
                                                    const float* theta, int32_t* z, int32_t* ndk,
                                                    int32_t* nkw) {
+    static_assert(KP == 16 || KP == 32 || KP == 64, "topics padded to 16, 32 or 64");
     extern __shared__ int32_t ldaf_cnt[];
     const uint32_t d = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
     if (d >= D) return;
     const uint32_t lane = lane_id();
     const uint32_t unit = (uint32_t)K * nb + d;
-    const bool topic = (int)lane < K;
-    int32_t* cnt = ldaf_cnt + 64 * wave_in_block();  // tokens per topic
+    int32_t* cnt = ldaf_cnt + 128 * wave_in_block();  // tokens per topic
+    float* thl = reinterpret_cast<float*>(cnt + 64);  // theta_d, zero past K
     const float* th_row = theta + (size_t)d * K;
     int32_t* ndk_row = ndk + (size_t)d * K;
-    const float th = topic ? th_row[lane] : 0.0f;
     cnt[lane] = 0;
+    thl[lane] = (int)lane < K ? th_row[lane] : 0.0f;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // rows start 16-byte aligned (and hold whole groups of four)
+    const bool v4 = (K & 3) == 0 && ((uintptr_t)phi & 15u) == 0;
+    const int32_t mb0 = K < 64 ? 0 : INT32_MIN;  // absent topics' zeros
     DirectReader<KIND_U> ru;
     ru.open(meta[unit], P.u + (size_t)unit * P.W[KIND_U], P.W[KIND_U]);
     const int32_t a = max(doff[d], 0), b = min(doff[d + 1], n_tokens);
@@ -690,24 +701,65 @@ __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t
         const bool act = i < b;
         const float u = ru.take(act);
         const int32_t wl = act ? words[i] : -1;
-        const uint32_t jl = (((uint32_t)(u * 16777216.0f)) - 1u) >> 1;
-        const int ntk = min(64, b - i0);
-        int32_t zl = -1;  // topic of token i0 + lane
-        for (int r = 0; r < ntk; ++r) {
-            const int32_t w = __builtin_amdgcn_readlane(wl, r);
-            if (w < 0 || w >= V) continue;  // wave-uniform
-            const float p = topic ? th * phi[(size_t)w * K + lane] : 0.0f;
-            const float m = __int_as_float(wave_minmax<true>(__float_as_int(p)));
-            uint32_t q = 1u;
-            if (m > 0.0f) q = (uint32_t)rintf(ldexpf(p, 24 - __builtin_amdgcn_frexp_expf(m)));
-            const int32_t C = wave_incl_scan(topic ? (int32_t)q : 0);
-            const uint32_t Q = (uint32_t)__builtin_amdgcn_readlane(C, K - 1);
-            const uint32_t j = (uint32_t)__builtin_amdgcn_readlane((int32_t)jl, r);
-            const uint32_t t = (uint32_t)(((uint64_t)j * Q) >> 23);
-            const int32_t zt = (int32_t)__popcll(wave_ballot(topic && (uint32_t)C <= t));
-            if ((int)lane == r) zl = zt;
+        const uint32_t j = (((uint32_t)(u * 16777216.0f)) - 1u) >> 1;
+        const bool ok = wl >= 0 && wl < V;
+        const float* row = phi + (size_t)(ok ? wl : 0) * K;  // row 0 stands in
+        // K through an empty asm: the group tests below are made where they
+        // are used instead of being kept, one per group, across the loop
+        int Kx = __builtin_amdgcn_readfirstlane(K);
+        asm volatile("" : "+s"(Kx));
+        float p[KP];
+        int32_t mb = mb0;
+#pragma unroll
+        for (int k = 0; k < KP; k += 4) {
+            const float4 t4 = *reinterpret_cast<const float4*>(thl + k);
+            float ph[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // absent topics: 0 (and theta 0)
+            if (k + 4 <= Kx) {
+                if (v4) {
+                    const float4 r4 = *reinterpret_cast<const float4*>(row + k);
+                    ph[0] = r4.x;
+                    ph[1] = r4.y;
+                    ph[2] = r4.z;
+                    ph[3] = r4.w;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ph[e] = row[k + e];
+                }
+            } else if (k < Kx) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (k + e < Kx) ph[e] = row[k + e];
+            }
+            const float tk[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                p[k + e] = tk[e] * ph[e];
+                mb = max(mb, __float_as_int(p[k + e]));
+            }
         }
-        // the group's counts: one atomic per token, issued together
+        // largest p positive: q_k = rint(p_k 2^(24 - e)) (absent topics 0,
+        // and Q >= 2^23 > t, so they are never counted); otherwise every
+        // topic weighs 1, C_k = k + 1, Q = K and z = t
+        const float m = __int_as_float(mb);
+        const bool pos = m > 0.0f;
+        const int sh = 24 - __builtin_amdgcn_frexp_expf(m);
+        uint32_t q[KP];
+        uint32_t Q = 0;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            q[k] = (uint32_t)rintf(ldexpf(p[k], sh));
+            Q += q[k];
+        }
+        const uint32_t t = (uint32_t)(((uint64_t)j * (pos ? Q : (uint32_t)K)) >> 23);
+        uint32_t C = 0;
+        int32_t zt = 0;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            C += q[k];
+            zt += C <= t ? 1 : 0;
+        }
+        if (!pos) zt = (int32_t)t;
+        const int32_t zl = ok ? zt : -1;
         if (act) z[i] = zl;
         if (zl >= 0) {
             atomicAdd(&cnt[zl], 1);
@@ -718,7 +770,7 @@ __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (topic) ndk_row[lane] = cnt[lane];
+    if ((int)lane < K) ndk_row[lane] = cnt[lane];
 }
 
 template <int MODEL>
@@ -1457,14 +1509,15 @@ brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
         }
         zero(d->d_nkw, (uint64_t)K * V);
         const dim3 grid((D + wpb - 1) / wpb);
-        const size_t lds = (size_t)wpb * 64 * sizeof(int32_t);
+        const size_t lds = (size_t)wpb * 128 * sizeof(int32_t);  // counts and theta
+        auto kern = K <= 16 ? k_ldaf_docs<16> : K <= 32 ? k_ldaf_docs<32> : k_ldaf_docs<64>;
         if (ts && s + 1 == d->sweeps)
-            hipExtLaunchKernelGGL(k_ldaf_docs, grid, blk, (uint32_t)lds, c->stream, ts, te, 0u,
+            hipExtLaunchKernelGGL(kern, grid, blk, (uint32_t)lds, c->stream, ts, te, 0u,
                                   c->meta, P, D, (int)K, (int)V, nb, d->d_doc_offsets, d->n_tokens,
                                   d->d_words, (const float*)d->d_phi, (const float*)d->d_theta,
                                   d->d_z, d->d_ndk, d->d_nkw);
         else
-            hipLaunchKernelGGL(k_ldaf_docs, grid, blk, lds, c->stream, c->meta, P, D, (int)K,
+            hipLaunchKernelGGL(kern, grid, blk, lds, c->stream, c->meta, P, D, (int)K,
                                (int)V, nb, d->d_doc_offsets, d->n_tokens, d->d_words,
                                (const float*)d->d_phi, (const float*)d->d_theta, d->d_z, d->d_ndk,
                                d->d_nkw);
