@@ -666,9 +666,11 @@ __global__ __launch_bounds__(256) void k_ldaf_phi_norm(int K, int V, uint32_t nb
 // sums.  A maximum and integer sums do not depend on their order, so the
 // topic is the same, bit for bit, as from any other arrangement of the rule.
 // KP: K padded to 16, 32 or 64 (the lane's registers are indexed
-// statically; padded topics weigh 0 and are never counted).  New n_d. in
-// place (LDS counts), n_kw added atomically (zero on entry), once per token.
-template <int KP>
+// statically; padded topics weigh 0 and are never counted); FULL: K = KP (no
+// padded topics, no selects).  A token's row is read with all its loads in
+// flight together.  New n_d. in place (LDS counts), n_kw added atomically
+// (zero on entry), once per token.
+template <int KP, bool FULL>
 __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t D, int K, int V,
                                                    uint32_t nb, const int32_t* doff,
                                                    int32_t n_tokens,
@@ -699,42 +701,44 @@ __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t
     for (int32_t i0 = a; i0 < b; i0 += 64) {
         const int32_t i = i0 + (int32_t)lane;
         const bool act = i < b;
+        const int32_t wl = act ? words[i] : -1;  // in flight during the take
         const float u = ru.take(act);
-        const int32_t wl = act ? words[i] : -1;
         const uint32_t j = (((uint32_t)(u * 16777216.0f)) - 1u) >> 1;
         const bool ok = wl >= 0 && wl < V;
         const float* row = phi + (size_t)(ok ? wl : 0) * K;  // row 0 stands in
-        // K through an empty asm: the group tests below are made where they
-        // are used instead of being kept, one per group, across the loop
+        // K through an empty asm: the padding tests below are made where they
+        // are used instead of being kept, one per topic, across the loop
         int Kx = __builtin_amdgcn_readfirstlane(K);
         asm volatile("" : "+s"(Kx));
+        // the row: every load issued before any is used (padded topics read
+        // a topic of the row and are zeroed below)
+        float ph[KP];
+        if (v4) {
+#pragma unroll
+            for (int k = 0; k < KP; k += 4) {
+                const int kc = FULL ? k : min(k, Kx - 4);
+                const float4 r4 = *reinterpret_cast<const float4*>(row + kc);
+                ph[k] = r4.x;
+                ph[k + 1] = r4.y;
+                ph[k + 2] = r4.z;
+                ph[k + 3] = r4.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < KP; ++k) ph[k] = row[FULL ? k : min(k, Kx - 1)];
+        }
         float p[KP];
         int32_t mb = mb0;
 #pragma unroll
         for (int k = 0; k < KP; k += 4) {
             const float4 t4 = *reinterpret_cast<const float4*>(thl + k);
-            float ph[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // absent topics: 0 (and theta 0)
-            if (k + 4 <= Kx) {
-                if (v4) {
-                    const float4 r4 = *reinterpret_cast<const float4*>(row + k);
-                    ph[0] = r4.x;
-                    ph[1] = r4.y;
-                    ph[2] = r4.z;
-                    ph[3] = r4.w;
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) ph[e] = row[k + e];
-                }
-            } else if (k < Kx) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (k + e < Kx) ph[e] = row[k + e];
-            }
             const float tk[4] = {t4.x, t4.y, t4.z, t4.w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                p[k + e] = tk[e] * ph[e];
-                mb = max(mb, __float_as_int(p[k + e]));
+                float v = tk[e] * ph[k + e];
+                if (!FULL) v = k + e < Kx ? v : 0.0f;
+                p[k + e] = v;
+                mb = max(mb, __float_as_int(v));
             }
         }
         // largest p positive: q_k = rint(p_k 2^(24 - e)) (absent topics 0,
@@ -1510,7 +1514,12 @@ brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
         zero(d->d_nkw, (uint64_t)K * V);
         const dim3 grid((D + wpb - 1) / wpb);
         const size_t lds = (size_t)wpb * 128 * sizeof(int32_t);  // counts and theta
-        auto kern = K <= 16 ? k_ldaf_docs<16> : K <= 32 ? k_ldaf_docs<32> : k_ldaf_docs<64>;
+        auto kern = K == 16   ? k_ldaf_docs<16, true>
+                    : K < 16  ? k_ldaf_docs<16, false>
+                    : K == 32 ? k_ldaf_docs<32, true>
+                    : K < 32  ? k_ldaf_docs<32, false>
+                    : K == 64 ? k_ldaf_docs<64, true>
+                              : k_ldaf_docs<64, false>;
         if (ts && s + 1 == d->sweeps)
             hipExtLaunchKernelGGL(kern, grid, blk, (uint32_t)lds, c->stream, ts, te, 0u,
                                   c->meta, P, D, (int)K, (int)V, nb, d->d_doc_offsets, d->n_tokens,
