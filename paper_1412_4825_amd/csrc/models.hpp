@@ -540,6 +540,20 @@ __device__ void unit_gamma(const DescDev& D, Meta* mp, const Pools& P, uint32_t 
         src.s2 = D.sums[(size_t)D.n_chains + chain];
     }
     const uint32_t smax = (uint32_t)min(D.max_steps, 1 << 24);
+    // Waves of longer chains issue first: they decide when the launch ends,
+    // and the waves of shorter chains on the same SIMD take the slots they
+    // leave.  Priority = the quarter of max_steps the wave's longest chain
+    // reaches (the wave's own issue priority; results do not depend on it).
+    {
+        const int32_t lmax = wave_minmax<true>(L - t0);
+        const int64_t pr = 4ll * lmax / ((int64_t)max(D.max_steps, 1) + 1);
+        if (pr >= 3)
+            __builtin_amdgcn_s_setprio(3);
+        else if (pr == 2)
+            __builtin_amdgcn_s_setprio(2);
+        else if (pr == 1)
+            __builtin_amdgcn_s_setprio(1);
+    }
     gamma_rounds<true>(rn, re, src, D.max_rounds > 0 ? (uint32_t)D.max_rounds : 4096u + 64u * smax);
     if (in) st[chain] = src.alpha;
     if (SUMS && in) {
