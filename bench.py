@@ -15,7 +15,9 @@ Documents continue from step to step.
 After it, under "workloads": the varying-shape gamma chains (262,144 chains
 of uneven length 50..1,000 with alpha_{t+1} = 0.1 + g_t) and the
 normal/exponential chains (65,536 chains x 1,000 steps, s' ~ N(0.9 s,
-0.5 + |s|) then e ~ Exp(1 + s'^2)), measured the same way.  --workload runs
+0.5 + |s|) then e ~ Exp(1 + s'^2)), measured the same way (a step refills
+only the windows its chain kernel reads: none for the gamma chains, whose
+kernel generates every entry it consumes).  --workload runs
 one workload alone: triangle (Eq. 1 / Fig. 1, 1,024 chains x 10,000
 iterations, fp64), normexp, gamma, lda, lda_full (full LDA on a synthetic
 corpus: 16,384 documents, 64 topics, 4,096 words, per sweep the topic-word
@@ -294,7 +296,11 @@ def setup_gamma(torch, b, args):
                 "note": "one brng_step_gamma launch per step over all %d chains, alpha update "
                         "on the stream between launches" % n}
 
+    # the chain kernel generates every entry it consumes (its readers never
+    # load a window), so no bulk refill precedes it; all pool bytes count
+    # as the kernel's
     return dict(ctx=ctx, fresh=fresh, resume=resume, kinds=[b.BRNG_N, b.BRNG_E],
+                fill_kinds=[],
                 keep=(st, tg, tsteps, tperm),
                 entry_bytes={b.BRNG_N: 4, b.BRNG_E: 4}, windows={b.BRNG_N: W, b.BRNG_E: W},
                 deviates=draws, out_bytes=draws * 4, dtype="f32", cpu=cpu, cpu1=cpu1, oaat=oaat,
