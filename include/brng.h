@@ -207,14 +207,18 @@ brng_status brng_step_dirichlet(brng_ctx *ctx, const int32_t *d_offsets,
  * [d_doc_offsets[d], d_doc_offsets[d+1]) clamped to [0, n_tokens); a word
  * id outside [0, n_vocab) gets z = -1, no count, and still takes its
  * uniform.  All arrays are caller-owned device memory.
- * Limits: 1 <= n_topics <= 64 (the token step holds one topic per lane),
- * 1 <= n_vocab <= BRNG_LDAF_VMAX, alpha, beta > 0.  Each topic block is
+ * Limits: 1 <= n_topics <= BRNG_LDAF_KMAX, 1 <= n_vocab <= BRNG_LDAF_VMAX,
+ * alpha, beta > 0.  The token step takes one token per lane; up to 64
+ * topics a lane keeps its weights in registers, above it forms them from
+ * its phi row once for the largest, once for the total and once for the
+ * count (the same topics either way).  Each topic block is
  * drawn by one wave (BRNG_LDAF_VBLOCK / 64 gamma rounds per sweep), beside
  * the documents' Dirichlets; with more than one block per topic a second
  * small kernel normalises phi.
  * Errors: BRNG_E_ARG (also for too few items), BRNG_E_KIND_DISABLED,
  * BRNG_E_UNSUPPORTED, BRNG_E_HIP. */
 #define BRNG_LDAF_VMAX (1 << 20)
+#define BRNG_LDAF_KMAX 1024
 #define BRNG_LDAF_VBLOCK 4096
 /* Items a full-LDA corpus uses: n_topics ceil(n_vocab / BRNG_LDAF_VBLOCK)
  * + n_docs (0 when n_vocab is 0). */

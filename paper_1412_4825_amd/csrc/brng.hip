@@ -636,15 +636,15 @@ __global__ __launch_bounds__(64) void k_ldaf_dirichlets(Meta* meta, Pools P, uin
 // grid-strided share of the [V][K] array.
 __global__ __launch_bounds__(256) void k_ldaf_phi_norm(int K, int V, uint32_t nb,
                                                        const float* psum, float* phi) {
-    __shared__ float tot[64];
+    __shared__ float tot[BRNG_LDAF_KMAX];
     const uint32_t t = threadIdx.x;
-    if (t < (uint32_t)K) {
+    for (uint32_t k = t; k < (uint32_t)K; k += blockDim.x) {
         float S = 0.0f;
-        for (uint32_t j = 0; j < nb; ++j) S += psum[t * nb + j];
-        tot[t] = S;
+        for (uint32_t j = 0; j < nb; ++j) S += psum[k * nb + j];
+        tot[k] = S;
     }
     __syncthreads();
-    const uint32_t n = (uint32_t)V * (uint32_t)K;  // at most 2^26
+    const uint32_t n = (uint32_t)V * (uint32_t)K;  // below 2^32 (checked by the caller)
     for (uint32_t i = blockIdx.x * blockDim.x + t; i < n; i += gridDim.x * blockDim.x) {
         const float S = tot[i % (uint32_t)K];
         phi[i] = S > 0.0f ? phi[i] / S : 0.0f;
@@ -775,6 +775,127 @@ __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if ((int)lane < K) ndk_row[lane] = cnt[lane];
+}
+
+// Documents of more than 64 topics (up to BRNG_LDAF_KMAX): the same rule and
+// the same order of uniforms as k_ldaf_docs, one token per lane, but a lane's
+// K weights do not fit its registers, so it forms them three times from its
+// phi row (for the largest, the total and the count); the count stops once
+// no lane's prefix sum is still <= its t (the sums only grow).  LDS per wave:
+// the counts and theta_d, K rounded up to 4 each.
+__global__ __launch_bounds__(512) void k_ldaf_docs_wide(Meta* meta, Pools P, uint32_t D, int K,
+                                                        int V, uint32_t nb, const int32_t* doff,
+                                                        int32_t n_tokens, const int32_t* words,
+                                                        const float* phi, const float* theta,
+                                                        int32_t* z, int32_t* ndk, int32_t* nkw) {
+    extern __shared__ int32_t ldaf_cnt[];
+    const uint32_t d = blockIdx.x * (blockDim.x >> 6) + wave_in_block();
+    if (d >= D) return;
+    const uint32_t lane = lane_id();
+    const uint32_t unit = (uint32_t)K * nb + d;
+    const int K4 = (K + 3) & ~3;
+    int32_t* cnt = ldaf_cnt + 2 * K4 * (int)wave_in_block();  // tokens per topic
+    float* thl = reinterpret_cast<float*>(cnt + K4);           // theta_d, zero past K
+    const float* th_row = theta + (size_t)d * K;
+    int32_t* ndk_row = ndk + (size_t)d * K;
+    for (int k = (int)lane; k < K4; k += 64) {
+        cnt[k] = 0;
+        thl[k] = k < K ? th_row[k] : 0.0f;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const bool v4 = (K & 3) == 0 && ((uintptr_t)phi & 15u) == 0;
+    const int Kf = K & ~3;  // topics in whole groups of four
+    DirectReader<KIND_U> ru;
+    ru.open(meta[unit], P.u + (size_t)unit * P.W[KIND_U], P.W[KIND_U]);
+    const int32_t a = max(doff[d], 0), b = min(doff[d + 1], n_tokens);
+    for (int32_t i0 = a; i0 < b; i0 += 64) {
+        const int32_t i = i0 + (int32_t)lane;
+        const bool act = i < b;
+        const int32_t wl = act ? words[i] : -1;  // in flight during the take
+        const float u = ru.take(act);
+        const uint32_t j = (((uint32_t)(u * 16777216.0f)) - 1u) >> 1;
+        const bool ok = wl >= 0 && wl < V;
+        const float* row = phi + (size_t)(ok ? wl : 0) * K;  // row 0 stands in
+        // weights of topics k .. k + 3 (k + 4 <= K)
+        auto group = [&](int k, float (&p)[4]) {
+            const float4 t4 = *reinterpret_cast<const float4*>(thl + k);
+            float ph[4];
+            if (v4) {
+                const float4 r4 = *reinterpret_cast<const float4*>(row + k);
+                ph[0] = r4.x;
+                ph[1] = r4.y;
+                ph[2] = r4.z;
+                ph[3] = r4.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) ph[e] = row[k + e];
+            }
+            p[0] = t4.x * ph[0];
+            p[1] = t4.y * ph[1];
+            p[2] = t4.z * ph[2];
+            p[3] = t4.w * ph[3];
+        };
+        // the weight of topic k (k < K), one at a time (the last partial group)
+        auto one = [&](int k) { return thl[k] * row[k]; };
+        int32_t mb = INT32_MIN;
+        for (int k = 0; k < Kf; k += 4) {
+            float p[4];
+            group(k, p);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) mb = max(mb, __float_as_int(p[e]));
+        }
+        for (int k = Kf; k < K; ++k) mb = max(mb, __float_as_int(one(k)));
+        const float m = __int_as_float(mb);
+        const bool pos = m > 0.0f;
+        const int sh = 24 - __builtin_amdgcn_frexp_expf(m);
+        auto qof = [&](float p) { return (uint32_t)rintf(ldexpf(p, sh)); };
+        uint32_t Q = 0;
+        for (int k = 0; k < Kf; k += 4) {
+            float p[4];
+            group(k, p);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Q += qof(p[e]);
+        }
+        for (int k = Kf; k < K; ++k) Q += qof(one(k));
+        // every topic weighs 1 when the largest weight is not positive:
+        // C_k = k + 1, Q = K, z = t
+        const uint32_t t = (uint32_t)(((uint64_t)j * (pos ? Q : (uint32_t)K)) >> 23);
+        int32_t zt = (int32_t)t;
+        if (wave_ballot(ok && pos) != 0) {
+            uint32_t C = 0;
+            int32_t cz = 0;
+            int k = 0;
+            for (; k < Kf; k += 4) {
+                float p[4];
+                group(k, p);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    C += qof(p[e]);
+                    cz += C <= t ? 1 : 0;
+                }
+                if (wave_ballot(ok && pos && C <= t) == 0) break;
+            }
+            if (k >= Kf)
+                for (k = Kf; k < K; ++k) {
+                    C += qof(one(k));
+                    cz += C <= t ? 1 : 0;
+                }
+            if (pos) zt = cz;
+        }
+        const int32_t zl = ok ? zt : -1;
+        if (act) z[i] = zl;
+        if (zl >= 0) {
+            atomicAdd(&cnt[zl], 1);
+            atomicAdd(&nkw[(size_t)zl * V + wl], 1);
+        }
+    }
+    ru.close(meta[unit]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int k = (int)lane; k < K; k += 64) ndk_row[k] = cnt[k];
 }
 
 template <int MODEL>
@@ -1468,7 +1589,7 @@ brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
     if (c->cfg.layout != BRNG_LAYOUT_ITEMS) return BRNG_E_ARG;
     if (c->cfg.prec != BRNG_F32) return BRNG_E_UNSUPPORTED;
     const uint32_t D = d->n_docs, K = d->n_topics, V = d->n_vocab;
-    if (D == 0 || K < 1 || K > 64 || V < 1 || V > BRNG_LDAF_VMAX || d->n_tokens < 0)
+    if (D == 0 || K < 1 || K > BRNG_LDAF_KMAX || V < 1 || V > BRNG_LDAF_VMAX || d->n_tokens < 0)
         return BRNG_E_ARG;
     const uint32_t nb = (V + LDAF_VBLOCK - 1) / LDAF_VBLOCK;
     if ((uint64_t)K * nb + D > c->n_units) return BRNG_E_ARG;
@@ -1512,6 +1633,27 @@ brng_status brng_run_lda_full(brng_ctx* c, const brng_lda_full_desc* d) {
                                nb, (const float*)psum, d->d_phi);
         }
         zero(d->d_nkw, (uint64_t)K * V);
+        if (K > 64) {
+            // counts and theta per wave, K rounded up to 4 each; workgroups
+            // kept within 64 KiB of LDS
+            const uint32_t K4 = (K + 3) & ~3u;
+            int wd = wpb;
+            while (wd > 1 && (size_t)wd * 2 * K4 * sizeof(int32_t) > 65536) wd /= 2;
+            const dim3 gridw((D + wd - 1) / wd), blkw(64 * wd);
+            const size_t ldsw = (size_t)wd * 2 * K4 * sizeof(int32_t);
+            if (ts && s + 1 == d->sweeps)
+                hipExtLaunchKernelGGL(k_ldaf_docs_wide, gridw, blkw, (uint32_t)ldsw, c->stream, ts, te,
+                                      0u, c->meta, P, D, (int)K, (int)V, nb, d->d_doc_offsets,
+                                      d->n_tokens, d->d_words, (const float*)d->d_phi,
+                                      (const float*)d->d_theta, d->d_z, d->d_ndk, d->d_nkw);
+            else
+                hipLaunchKernelGGL(k_ldaf_docs_wide, gridw, blkw, ldsw, c->stream, c->meta, P, D,
+                                   (int)K, (int)V, nb, d->d_doc_offsets, d->n_tokens, d->d_words,
+                                   (const float*)d->d_phi, (const float*)d->d_theta, d->d_z,
+                                   d->d_ndk, d->d_nkw);
+            HIPCHK(hipGetLastError());
+            continue;
+        }
         const dim3 grid((D + wpb - 1) / wpb);
         const size_t lds = (size_t)wpb * 128 * sizeof(int32_t);  // counts and theta
         auto kern = K == 16   ? k_ldaf_docs<16, true>

@@ -11,7 +11,10 @@ sweep replayed by the oracle from the device's own state:
 - cursors equal for every unit without such a decision.
 
 Cases: ragged documents (empty ones, up to a few hundred tokens) with a few
-word ids outside the vocabulary, topic counts 1, 13 and 64 (the limit),
+word ids outside the vocabulary, topic counts 1, 13 and 64 (the largest
+whose weights a lane keeps in registers) and 65, 100, 256 and 1,024 (the
+limit; weights formed from the row three times, with and without 16-byte
+row loads),
 vocabularies of 4,097, 8,192 and 30,000 words (two, two and eight blocks of
 4,096 words per topic, each block its own unit), a
 launch of all sweeps at once equal to the sweep-by-sweep calls, and window
@@ -66,7 +69,9 @@ def _bufs(dev, D, K, V, words, z0):
 
 @pytest.mark.parametrize("K,V,D,mean_len", [(13, 300, 40, 60.0), (64, 512, 24, 120.0),
                                             (1, 50, 10, 30.0), (64, 30000, 60, 150.0),
-                                            (5, 4097, 20, 40.0), (3, 8192, 12, 50.0)])
+                                            (5, 4097, 20, 40.0), (3, 8192, 12, 50.0),
+                                            (65, 300, 16, 60.0), (100, 200, 12, 80.0),
+                                            (256, 120, 8, 60.0), (1024, 64, 6, 40.0)])
 def test_lda_full_sweep_replay(dev, K, V, D, mean_len):
     import torch
     b = _b()
@@ -163,7 +168,7 @@ def test_lda_full_rejects_bad_arguments(dev):
                         stream=torch.cuda.current_stream())
     buf = _bufs(dev, D, K, V, words, z0)
     try:
-        for k, v, a in ((65, V, 0.1), (K, (1 << 20) + 1, 0.1), (K, V, 0.0), (K + 1, V, 0.1),
+        for k, v, a in ((1025, V, 0.1), (K, (1 << 20) + 1, 0.1), (K, V, 0.0), (K + 1, V, 0.1),
                         (K, 4097, 0.1)):
             # K + 1 topics with D documents, or two vocabulary blocks per
             # topic, need more units than the context has
@@ -174,7 +179,7 @@ def test_lda_full_rejects_bad_arguments(dev):
         b.brng_destroy(ctx)
 
 
-@pytest.mark.parametrize("K,V,D", [(24, 700, 50), (8, 9000, 40)])
+@pytest.mark.parametrize("K,V,D", [(24, 700, 50), (8, 9000, 40), (100, 300, 30)])
 def test_lda_full_window_and_launch_shape_invariance(dev, K, V, D):
     """Window length and waves per workgroup are speed knobs only: three
     configurations give the same topics, counts, draws and cursors bit for
