@@ -20,7 +20,8 @@ only the windows its chain kernel reads: none for the gamma chains, whose
 kernel generates every entry it consumes).  --workload runs
 one workload alone: triangle (Eq. 1 / Fig. 1, 1,024 chains x 10,000
 iterations, fp64), normexp, gamma, lda, lda_full (full LDA on a synthetic
-corpus: 16,384 documents, 64 topics, 4,096 words, per sweep the topic-word
+corpus: 16,384 documents, 64 topics (--lda-topics), 4,096 words
+(--lda-vocab), per sweep the topic-word
 and document-topic Dirichlets and one topic per token), served (the mixed
 request stream alone).
 
@@ -386,7 +387,7 @@ def setup_lda_full(torch, b, args):
     per token.  A step is one call of `sweeps_per_step` sweeps."""
     from paper_1412_4825_amd import workloads
     nd = args.chains or 16384
-    K, V = 64, args.lda_vocab
+    K, V = args.lda_topics, args.lda_vocab
     sweeps = args.chain_steps or 5
     alpha, beta = 0.1, 0.05
     c = workloads.lda_corpus(n_docs=nd, n_topics=K, n_vocab=V, seed=args.seed)
@@ -914,7 +915,9 @@ def main():
     ap.add_argument("--cpu-units", type=int, default=0)
     ap.add_argument("--oaat-steps", type=int, default=100)
     ap.add_argument("--lda-vocab", type=int, default=4096,
-                    help="lda_full: vocabulary size (64 topics)")
+                    help="lda_full: vocabulary size")
+    ap.add_argument("--lda-topics", type=int, default=64,
+                    help="lda_full: topics (1 .. 1,024)")
     ap.add_argument("--no-oaat", action="store_true",
                     help="skip the one-launch-per-step comparison (gamma)")
     ap.add_argument("--served-requests", type=int, default=1000)

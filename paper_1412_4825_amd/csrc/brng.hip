@@ -806,7 +806,8 @@ __global__ __launch_bounds__(512) void k_ldaf_docs_wide(Meta* meta, Pools P, uin
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const bool v4 = (K & 3) == 0 && ((uintptr_t)phi & 15u) == 0;
-    const int Kf = K & ~3;  // topics in whole groups of four
+    const int K16 = K & ~15;  // topics in whole groups of sixteen
+    const int Kf = K & ~3;    // and of four
     DirectReader<KIND_U> ru;
     ru.open(meta[unit], P.u + (size_t)unit * P.W[KIND_U], P.W[KIND_U]);
     const int32_t a = max(doff[d], 0), b = min(doff[d + 1], n_tokens);
@@ -818,47 +819,76 @@ __global__ __launch_bounds__(512) void k_ldaf_docs_wide(Meta* meta, Pools P, uin
         const uint32_t j = (((uint32_t)(u * 16777216.0f)) - 1u) >> 1;
         const bool ok = wl >= 0 && wl < V;
         const float* row = phi + (size_t)(ok ? wl : 0) * K;  // row 0 stands in
-        // weights of topics k .. k + 3 (k + 4 <= K)
-        auto group = [&](int k, float (&p)[4]) {
-            const float4 t4 = *reinterpret_cast<const float4*>(thl + k);
-            float ph[4];
+        // weights of topics k .. k + G - 1 (k + G <= K), the row's loads
+        // issued together
+        auto group = [&](int k, auto gc, float* p) {
+            constexpr int G = decltype(gc)::value;
+            float ph[G];
             if (v4) {
-                const float4 r4 = *reinterpret_cast<const float4*>(row + k);
-                ph[0] = r4.x;
-                ph[1] = r4.y;
-                ph[2] = r4.z;
-                ph[3] = r4.w;
+#pragma unroll
+                for (int g = 0; g < G; g += 4) {
+                    const float4 r4 = *reinterpret_cast<const float4*>(row + k + g);
+                    ph[g] = r4.x;
+                    ph[g + 1] = r4.y;
+                    ph[g + 2] = r4.z;
+                    ph[g + 3] = r4.w;
+                }
             } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) ph[e] = row[k + e];
+                for (int g = 0; g < G; ++g) ph[g] = row[k + g];
             }
-            p[0] = t4.x * ph[0];
-            p[1] = t4.y * ph[1];
-            p[2] = t4.z * ph[2];
-            p[3] = t4.w * ph[3];
+#pragma unroll
+            for (int g = 0; g < G; g += 4) {
+                const float4 t4 = *reinterpret_cast<const float4*>(thl + k + g);
+                p[g] = t4.x * ph[g];
+                p[g + 1] = t4.y * ph[g + 1];
+                p[g + 2] = t4.z * ph[g + 2];
+                p[g + 3] = t4.w * ph[g + 3];
+            }
         };
+        using G16 = std::integral_constant<int, 16>;
+        using G4 = std::integral_constant<int, 4>;
         // the weight of topic k (k < K), one at a time (the last partial group)
         auto one = [&](int k) { return thl[k] * row[k]; };
+        // topics [0, K16) in groups of 16, [K16, Kf) in groups of 4, then singly
         int32_t mb = INT32_MIN;
-        for (int k = 0; k < Kf; k += 4) {
-            float p[4];
-            group(k, p);
+        {
+            int k = 0;
+            for (; k < K16; k += 16) {
+                float p[16];
+                group(k, G16{}, p);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) mb = max(mb, __float_as_int(p[e]));
+                for (int e = 0; e < 16; ++e) mb = max(mb, __float_as_int(p[e]));
+            }
+            for (; k < Kf; k += 4) {
+                float p[4];
+                group(k, G4{}, p);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) mb = max(mb, __float_as_int(p[e]));
+            }
+            for (; k < K; ++k) mb = max(mb, __float_as_int(one(k)));
         }
-        for (int k = Kf; k < K; ++k) mb = max(mb, __float_as_int(one(k)));
         const float m = __int_as_float(mb);
         const bool pos = m > 0.0f;
         const int sh = 24 - __builtin_amdgcn_frexp_expf(m);
         auto qof = [&](float p) { return (uint32_t)rintf(ldexpf(p, sh)); };
         uint32_t Q = 0;
-        for (int k = 0; k < Kf; k += 4) {
-            float p[4];
-            group(k, p);
+        {
+            int k = 0;
+            for (; k < K16; k += 16) {
+                float p[16];
+                group(k, G16{}, p);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) Q += qof(p[e]);
+                for (int e = 0; e < 16; ++e) Q += qof(p[e]);
+            }
+            for (; k < Kf; k += 4) {
+                float p[4];
+                group(k, G4{}, p);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) Q += qof(p[e]);
+            }
+            for (; k < K; ++k) Q += qof(one(k));
         }
-        for (int k = Kf; k < K; ++k) Q += qof(one(k));
         // every topic weighs 1 when the largest weight is not positive:
         // C_k = k + 1, Q = K, z = t
         const uint32_t t = (uint32_t)(((uint64_t)j * (pos ? Q : (uint32_t)K)) >> 23);
@@ -866,22 +896,32 @@ __global__ __launch_bounds__(512) void k_ldaf_docs_wide(Meta* meta, Pools P, uin
         if (wave_ballot(ok && pos) != 0) {
             uint32_t C = 0;
             int32_t cz = 0;
+            bool more = true;  // some lane's prefix sum is still <= its t
             int k = 0;
-            for (; k < Kf; k += 4) {
+            for (; more && k < K16; k += 16) {
+                float p[16];
+                group(k, G16{}, p);
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    C += qof(p[e]);
+                    cz += C <= t ? 1 : 0;
+                }
+                more = wave_ballot(ok && pos && C <= t) != 0;
+            }
+            for (; more && k < Kf; k += 4) {
                 float p[4];
-                group(k, p);
+                group(k, G4{}, p);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     C += qof(p[e]);
                     cz += C <= t ? 1 : 0;
                 }
-                if (wave_ballot(ok && pos && C <= t) == 0) break;
+                more = wave_ballot(ok && pos && C <= t) != 0;
             }
-            if (k >= Kf)
-                for (k = Kf; k < K; ++k) {
-                    C += qof(one(k));
-                    cz += C <= t ? 1 : 0;
-                }
+            for (; more && k < K; ++k) {
+                C += qof(one(k));
+                cz += C <= t ? 1 : 0;
+            }
             if (pos) zt = cz;
         }
         const int32_t zl = ok ? zt : -1;
