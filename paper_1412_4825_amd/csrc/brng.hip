@@ -780,9 +780,10 @@ __global__ __launch_bounds__(512) void k_ldaf_docs(Meta* meta, Pools P, uint32_t
 // Documents of more than 64 topics (up to BRNG_LDAF_KMAX): the same rule and
 // the same order of uniforms as k_ldaf_docs, one token per lane, but a lane's
 // K weights do not fit its registers, so it forms them three times from its
-// phi row (for the largest, the total and the count); the count stops once
-// no lane's prefix sum is still <= its t (the sums only grow).  LDS per wave:
-// the counts and theta_d, K rounded up to 4 each.
+// phi row (for the largest, the total and the count), 32 topics at a time
+// with their row loads in flight together; the count stops once no lane's
+// prefix sum is still <= its t (the sums only grow).  LDS per wave: the
+// counts and theta_d, K rounded up to 4 each.
 __global__ __launch_bounds__(512) void k_ldaf_docs_wide(Meta* meta, Pools P, uint32_t D, int K,
                                                         int V, uint32_t nb, const int32_t* doff,
                                                         int32_t n_tokens, const int32_t* words,
@@ -806,7 +807,7 @@ __global__ __launch_bounds__(512) void k_ldaf_docs_wide(Meta* meta, Pools P, uin
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const bool v4 = (K & 3) == 0 && ((uintptr_t)phi & 15u) == 0;
-    const int K16 = K & ~15;  // topics in whole groups of sixteen
+    const int K32 = K & ~31;  // topics in whole groups of 32
     const int Kf = K & ~3;    // and of four
     DirectReader<KIND_U> ru;
     ru.open(meta[unit], P.u + (size_t)unit * P.W[KIND_U], P.W[KIND_U]);
@@ -846,19 +847,19 @@ __global__ __launch_bounds__(512) void k_ldaf_docs_wide(Meta* meta, Pools P, uin
                 p[g + 3] = t4.w * ph[g + 3];
             }
         };
-        using G16 = std::integral_constant<int, 16>;
+        using G32 = std::integral_constant<int, 32>;
         using G4 = std::integral_constant<int, 4>;
         // the weight of topic k (k < K), one at a time (the last partial group)
         auto one = [&](int k) { return thl[k] * row[k]; };
-        // topics [0, K16) in groups of 16, [K16, Kf) in groups of 4, then singly
+        // topics [0, K32) in groups of 32, [K32, Kf) in groups of 4, then singly
         int32_t mb = INT32_MIN;
         {
             int k = 0;
-            for (; k < K16; k += 16) {
-                float p[16];
-                group(k, G16{}, p);
+            for (; k < K32; k += 32) {
+                float p[32];
+                group(k, G32{}, p);
 #pragma unroll
-                for (int e = 0; e < 16; ++e) mb = max(mb, __float_as_int(p[e]));
+                for (int e = 0; e < 32; ++e) mb = max(mb, __float_as_int(p[e]));
             }
             for (; k < Kf; k += 4) {
                 float p[4];
@@ -875,11 +876,11 @@ __global__ __launch_bounds__(512) void k_ldaf_docs_wide(Meta* meta, Pools P, uin
         uint32_t Q = 0;
         {
             int k = 0;
-            for (; k < K16; k += 16) {
-                float p[16];
-                group(k, G16{}, p);
+            for (; k < K32; k += 32) {
+                float p[32];
+                group(k, G32{}, p);
 #pragma unroll
-                for (int e = 0; e < 16; ++e) Q += qof(p[e]);
+                for (int e = 0; e < 32; ++e) Q += qof(p[e]);
             }
             for (; k < Kf; k += 4) {
                 float p[4];
@@ -898,11 +899,11 @@ __global__ __launch_bounds__(512) void k_ldaf_docs_wide(Meta* meta, Pools P, uin
             int32_t cz = 0;
             bool more = true;  // some lane's prefix sum is still <= its t
             int k = 0;
-            for (; more && k < K16; k += 16) {
-                float p[16];
-                group(k, G16{}, p);
+            for (; more && k < K32; k += 32) {
+                float p[32];
+                group(k, G32{}, p);
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
+                for (int e = 0; e < 32; ++e) {
                     C += qof(p[e]);
                     cz += C <= t ? 1 : 0;
                 }
