@@ -565,15 +565,44 @@ __global__ __launch_bounds__(512) void k_ldaf_recount(uint32_t D, int K, int V,
 // first K nb workgroups draw the topics' gammas, workgroup k nb + j those of
 // topic k over words [j LDAF_VBLOCK, (j + 1) LDAF_VBLOCK) from unit k nb + j,
 // the others theta_d ~ Dir(alpha + n_d.) (document d = block - K nb), so that
-// the long topic draws run beside the many short document ones.  A topic
-// block's pools are staged through LDS by the epoch readers of the LDA kernel
-// (its thousands of components are many sequential rounds); phi is
+// the long topic draws run beside the many short document ones.  Every
+// unit's pools are staged through LDS by the epoch readers of the LDA kernel
+// (a topic block's thousands of components, or a document's up to 1,024,
+// are many sequential rounds); phi is
 // word-major ([V][K]), so that a token's K weights are one contiguous row.
 // With one block per topic the wave also normalises phi_k; with more, each
 // block leaves its gammas in phi and their fp32 sum in psum[k nb + j], and
 // k_ldaf_phi_norm divides by the topic's total.
 constexpr int LDAF_TOPIC_LDS = LdaRN::LDS_BYTES + LdaRE::LDS_BYTES;
 constexpr int LDAF_VBLOCK = BRNG_LDAF_VBLOCK;
+// The gammas of one unit's components (shapes base + cnt[c], c < n) into
+// y[c ys], through the LDS epoch readers.
+__device__ __forceinline__ void ldaf_gammas(Meta* meta, const Pools& P, uint32_t unit,
+                                            unsigned char* lds, int n, const int32_t* cnt,
+                                            float base, float* y, int ys) {
+    Meta m = meta[unit];
+    // the key words feed the scalar key schedule: make them provably uniform
+    m.key_unit = __builtin_amdgcn_readfirstlane(m.key_unit);
+    m.key_seed = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(m.key_seed >> 32)) << 32) |
+                 (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)m.key_seed);
+    LdaRN rn;
+    LdaRE re;
+    rn.open(m, P.n + (size_t)unit * P.W[KIND_N], P.W[KIND_N], reinterpret_cast<float*>(lds));
+    re.open(m, P.e + (size_t)unit * P.W[KIND_E], P.W[KIND_E],
+            reinterpret_cast<float*>(lds + LdaRN::LDS_BYTES));
+    CompSrc src;
+    src.K = n;
+    src.alpha = nullptr;
+    src.cnt = cnt;
+    src.base = base;
+    src.y = y;
+    src.ys = ys;
+    gamma_rounds<true, LDA_EPOCH>(rn, re, src, 4096u + 64u * (uint32_t)n);
+    rn.close(meta[unit]);
+    re.close(meta[unit]);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
 __global__ __launch_bounds__(64) void k_ldaf_dirichlets(Meta* meta, Pools P, uint32_t D, int K,
                                                         int V, uint32_t nb, float alpha,
                                                         float beta, const int32_t* ndk,
@@ -582,37 +611,30 @@ __global__ __launch_bounds__(64) void k_ldaf_dirichlets(Meta* meta, Pools P, uin
     __shared__ __align__(16) unsigned char lds[LDAF_TOPIC_LDS];
     const uint32_t blk = blockIdx.x;
     const uint32_t n_topic_units = (uint32_t)K * nb;
+    const uint32_t lane = lane_id();
     if (blk >= n_topic_units) {
+        // theta_d ~ Dir(alpha + n_d.), normalised by the sum of its gammas
         const uint32_t d = blk - n_topic_units;
         if (d >= D) return;
-        dirichlet_unit(meta, P, blk, K, nullptr, ndk + (size_t)d * K, alpha,
-                       theta + (size_t)d * K);
+        float* out = theta + (size_t)d * K;
+        ldaf_gammas(meta, P, blk, lds, K, ndk + (size_t)d * K, alpha, out, 1);
+        float part = 0.0f;
+        for (int b0 = 0; b0 < K; b0 += 64) {
+            const int k = b0 + (int)lane;
+            if (k < K) part += out[k];
+        }
+        const float S = wave_sum(part);
+        for (int b0 = 0; b0 < K; b0 += 64) {
+            const int k = b0 + (int)lane;
+            if (k < K) out[k] = S > 0.0f ? out[k] / S : 0.0f;
+        }
         return;
     }
     const uint32_t k = blk / nb, j = blk - k * nb;
     const int c0 = (int)j * LDAF_VBLOCK;
     const int Vb = min(LDAF_VBLOCK, V - c0);
-    const uint32_t lane = lane_id();
-    Meta m = meta[blk];
-    // the key words feed the scalar key schedule: make them provably uniform
-    m.key_unit = __builtin_amdgcn_readfirstlane(m.key_unit);
-    m.key_seed = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(m.key_seed >> 32)) << 32) |
-                 (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)m.key_seed);
-    LdaRN rn;
-    LdaRE re;
-    rn.open(m, P.n + (size_t)blk * P.W[KIND_N], P.W[KIND_N], reinterpret_cast<float*>(lds));
-    re.open(m, P.e + (size_t)blk * P.W[KIND_E], P.W[KIND_E],
-            reinterpret_cast<float*>(lds + LdaRN::LDS_BYTES));
     float* out = phi + (size_t)c0 * K + k;
-    CompSrc src;
-    src.K = Vb;
-    src.alpha = nullptr;
-    src.cnt = nkw + (size_t)k * V + c0;
-    src.base = beta;
-    src.y = out;
-    src.ys = K;
-    gamma_rounds<true, LDA_EPOCH>(rn, re, src, 4096u + 64u * (uint32_t)Vb);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    ldaf_gammas(meta, P, blk, lds, Vb, nkw + (size_t)k * V + c0, beta, out, K);
     float part = 0.0f;
     for (int b0 = 0; b0 < Vb; b0 += 64) {
         const int c = b0 + (int)lane;
@@ -627,8 +649,6 @@ __global__ __launch_bounds__(64) void k_ldaf_dirichlets(Meta* meta, Pools P, uin
     } else if (lane == 0) {
         psum[blk] = S;
     }
-    rn.close(meta[blk]);
-    re.close(meta[blk]);
 }
 
 // phi[w][k] /= sum over topic k's blocks of psum (in block order, fp32):
