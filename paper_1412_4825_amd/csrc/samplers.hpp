@@ -126,8 +126,12 @@ __device__ __forceinline__ void gamma_rounds(RN& rn, RE& re, Src& src, uint32_t 
     auto one_round = [&](const uint64_t mh) {
         // shapes outside (0, 2^64) have no draw (it completes at once with NaN
         // and consumes nothing); below 1 the boost applies
-        const uint64_t mv = wave_ballot(al > 0.0f) & wave_ballot(al < 0x1p64f);
-        const uint64_t mboost = mv & wave_ballot(al < 1.0f);
+        // from the bits: b - 1 below the bits of 2^64 less one is 0 < al <
+        // 2^64 (zero, negatives and NaN wrap or lie above), below those of
+        // 1 less one is 0 < al < 1
+        const uint32_t b1 = __float_as_uint(al) - 1u;
+        const uint64_t mv = wave_ballot(b1 < 0x5F7FFFFFu);
+        const uint64_t mboost = wave_ballot(b1 < 0x3F7FFFFFu);
         // selects, not a branch: al + 1 where the boost applies, al + 0 = al
         // elsewhere (al > 0 wherever the sum is used)
         const float ab = al + (lane_in(mboost) ? 1.0f : 0.0f);
@@ -361,9 +365,7 @@ struct ChainSrc {
         const bool done = lane_in(md);
         const bool behind = t < f;
         ring[(t & (TRACE_ROWS - 1)) * 64] = gv;
-        if (wave_ballot(behind) != 0) {
-            if (behind && done && trace) col[(int64_t)t * stride] = gv;
-        }
+        if (behind && done && trace) col[(int64_t)t * stride] = gv;
         if constexpr (SUMS) {
             if (done) {
                 const double d = (double)gv;
