@@ -179,11 +179,13 @@ def test_lda_full_rejects_bad_arguments(dev):
         b.brng_destroy(ctx)
 
 
-@pytest.mark.parametrize("K,V,D", [(24, 700, 50), (8, 9000, 40), (100, 300, 30)])
+@pytest.mark.parametrize("K,V,D", [(24, 700, 50), (8, 9000, 40), (100, 300, 30),
+                                   (1024, 64, 12)])
 def test_lda_full_window_and_launch_shape_invariance(dev, K, V, D):
     """Window length and waves per workgroup are speed knobs only: three
     configurations give the same topics, counts, draws and cursors bit for
-    bit over three sweeps (also with three vocabulary blocks per topic)."""
+    bit over three sweeps (also with three vocabulary blocks per topic, and
+    at 1,024 topics, where eight waves per workgroup take 64 KiB of LDS)."""
     import torch
     b = _b()
     seed = 99
