@@ -219,7 +219,7 @@ brng_status brng_step_dirichlet(brng_ctx *ctx, const int32_t *d_offsets,
  * BRNG_E_UNSUPPORTED, BRNG_E_HIP. */
 #define BRNG_LDAF_VMAX (1 << 20)
 #define BRNG_LDAF_KMAX 1024
-#define BRNG_LDAF_VBLOCK 4096
+#define BRNG_LDAF_VBLOCK 1024
 /* Items a full-LDA corpus uses: n_topics ceil(n_vocab / BRNG_LDAF_VBLOCK)
  * + n_docs (0 when n_vocab is 0). */
 uint64_t brng_lda_full_units(uint32_t n_topics, uint32_t n_vocab, uint32_t n_docs);

@@ -531,7 +531,7 @@ def lda_full_token_topic(theta_d, phi, w, u):
     return int(np.searchsorted(c, t, side="right"))
 
 
-LDA_FULL_VBLOCK = 4096  # words per topic block: one unit, one gamma stream
+LDA_FULL_VBLOCK = 1024  # words per topic block: one unit, one gamma stream
 
 
 def lda_full_units(K, V, D, vblock=LDA_FULL_VBLOCK):

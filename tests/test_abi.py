@@ -137,11 +137,11 @@ def test_static_run_refusals_without_device():
 
 
 def test_lda_full_units_matches_the_oracle_numbering():
-    """Items a full-LDA corpus needs: topic blocks of 4,096 words, then the
+    """Items a full-LDA corpus needs: topic blocks of 1,024 words, then the
     documents (the oracle's numbering of the same corpus)."""
     import oracle
     for K, V, D in ((64, 4096, 100), (64, 4097, 100), (1, 1 << 20, 0), (13, 300, 40),
                     (64, 50000, 16384), (3, 8192, 12)):
         assert b.brng_lda_full_units(K, V, D) == oracle.lda_full_units(K, V, D), (K, V, D)
-    assert b.brng_lda_full_units(64, 4097, 100) == 64 * 2 + 100
+    assert b.brng_lda_full_units(64, 4097, 100) == 64 * 5 + 100
     assert b.brng_lda_full_units(5, 0, 3) == 0

@@ -319,8 +319,9 @@ def test_lda_full_size(dev):
 @pytest.mark.parametrize("V", [4096, 50000])
 def test_lda_full_full_size(dev, V):
     """Full LDA at the bench's size (16,384 documents, 64 topics, window
-    512), over the bench's default vocabulary of 4,096 words and one of
-    50,000 (13 blocks of 4,096 words per topic): two calls of one sweep;
+    512), over the bench's default vocabulary of 4,096 words (four blocks
+    of 1,024 words per topic) and one of 50,000 (49 blocks): two calls of
+    one sweep;
     every topic's phi and eight sampled documents (theta, every token's
     topic, n_d.) against the oracle replayed from the device's state, n_kw
     against the counts of the new assignment."""

@@ -15,8 +15,8 @@ word ids outside the vocabulary, topic counts 1, 13 and 64 (the largest
 whose weights a lane keeps in registers) and 65, 100, 256 and 1,024 (the
 limit; weights formed from the row three times, with and without 16-byte
 row loads),
-vocabularies of 4,097, 8,192 and 30,000 words (two, two and eight blocks of
-4,096 words per topic, each block its own unit), a
+vocabularies of 4,097, 8,192 and 30,000 words (five, eight and thirty
+blocks of 1,024 words per topic, each block its own unit), a
 launch of all sweeps at once equal to the sweep-by-sweep calls, and window
 length and workgroup size changing nothing."""
 import numpy as np
